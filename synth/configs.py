@@ -1,0 +1,84 @@
+"""Named workloads and the solver settings each one is run with.
+
+The settings are plain numbers handed to both the oracle and the HIP
+library: tau = 5n (Sec. II.C), delta = 1.2 * m*n/|Phi| (the step-size choice
+"1.2/ratio" of the planted workload, applied to every workload), l = 5, s = 10,
+and the recycling settings the paper uses for images (strategy 2,
+i_reuse = 100, q_reuse = 10, Sec. V.B) and ratings (strategy 1, i_reuse = 50,
+q_reuse = 10, Sec. V.C).
+"""
+
+from .problems import planted, image_like, ratings
+
+
+def _base(m, n, nnz, **kw):
+    p = dict(tau=5.0 * n, delta=1.2 * m * n / nnz, eps=1e-4, i_max=200,
+             l=5, s=10, p_init=3, p_min=1, p_max=8, adaptive_p=1,
+             i_reuse=0, q_reuse=10, recycle=0, ritz_tol=1e-4, k_max=0,
+             seed=12345)
+    p.update(kw)
+    return p
+
+
+CONFIGS = {
+    # 500 x 500 planted rank 10, 20 % observed, plain fast SVT in FP64.
+    "planted500": dict(
+        make=lambda: planted(500, 500, 10, 0.2, seed_data=1, seed_phi=101,
+                             name="planted500"),
+        shape=(500, 500, 50000),
+        params=lambda m, n, nnz: _base(m, n, nnz, eps=1e-4, i_max=200)),
+    # 1024 x 1024 image-like, 50 % observed, p = 2 fixed ("3 Krylov blocks"),
+    # strategy-2 recycling.
+    "image1024": dict(
+        make=lambda: image_like(1024, 0.5, seed_data=2, seed_phi=102,
+                                name="image1024"),
+        shape=(1024, 1024, 524288),
+        params=lambda m, n, nnz: _base(m, n, nnz, eps=0.05, i_max=300,
+                                       p_init=2, adaptive_p=0, recycle=2,
+                                       i_reuse=100, q_reuse=10)),
+    # 70,000 x 10,700, 1e7 integer ratings, strategy-1 recycling.
+    "ratings70k": dict(
+        make=lambda: ratings(70000, 10700, 10_000_000, 20, seed_data=3,
+                             name="ratings70k"),
+        shape=(70000, 10700, 10_000_000),
+        params=lambda m, n, nnz: _base(m, n, nnz, eps=0.16, i_max=400,
+                                       recycle=1, i_reuse=50, q_reuse=10)),
+    # 1/10-scaled instance of the same generator (m, n / 10, nnz / 100).
+    "ratings70k_s10": dict(
+        make=lambda: ratings(7000, 1070, 100_000, 20, seed_data=3,
+                             name="ratings70k_s10"),
+        shape=(7000, 1070, 100_000),
+        params=lambda m, n, nnz: _base(m, n, nnz, eps=0.16, i_max=400,
+                                       recycle=1, i_reuse=50, q_reuse=10)),
+    # 140,000 x 27,000, 2e7 ratings, rank cap 100.
+    "ratings140k": dict(
+        make=lambda: ratings(140000, 27000, 20_000_000, 30, seed_data=5,
+                             name="ratings140k"),
+        shape=(140000, 27000, 20_000_000),
+        params=lambda m, n, nnz: _base(m, n, nnz, eps=0.16, i_max=400,
+                                       recycle=1, i_reuse=50, q_reuse=10,
+                                       k_max=100)),
+    "ratings140k_s10": dict(
+        make=lambda: ratings(14000, 2700, 200_000, 30, seed_data=5,
+                             name="ratings140k_s10"),
+        shape=(14000, 2700, 200_000),
+        params=lambda m, n, nnz: _base(m, n, nnz, eps=0.16, i_max=400,
+                                       recycle=1, i_reuse=50, q_reuse=10,
+                                       k_max=100)),
+}
+
+
+def get_config(name):
+    return CONFIGS[name]
+
+
+def make_problem(name):
+    """Return (problem, params) for a named workload."""
+    cfg = CONFIGS[name]
+    prob = cfg["make"]()
+    return prob, cfg["params"](prob.m, prob.n, prob.nnz)
+
+
+def serving_params(m, n, nnz):
+    """Per-request settings of the serving workload (no recycling)."""
+    return _base(m, n, nnz, eps=1e-4, i_max=200)
