@@ -1,0 +1,211 @@
+/*
+ * mcsvt.h -- C ABI of the MI355X fast-SVT matrix completion library.
+ *
+ * The library solves   min ||X||_*  s.t.  P_Phi(X) = P_Phi(M)   (Eq. (5))
+ * with singular value thresholding (Eq. (6), Alg. 2) whose truncated SVD is
+ * the block-Krylov randomized SVD rSVD-BKI (Alg. 5) with eigSVD (Alg. 3),
+ * subspace recycling (Sec. IV.B) and the adaptive power parameter of the
+ * fast SVT algorithm (Alg. 6, Sec. IV.C).  All arithmetic of a step runs in
+ * HIP kernels on one gfx950 GPU; the host keeps only the scalar control of
+ * Alg. 6 (rank search, p adaptation, recycling gate, stop test).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Indices are 0-based.  Matrices handed in or out are row-major.
+ * - Host pointers are owned by the caller and only read (or written) during
+ *   the call.  Device state is owned by the handle until mc_svt_destroy.
+ * - Every call returns an mc_status; no C++ exception crosses the ABI.  The
+ *   message of the last failure is returned by mc_svt_last_error (per
+ *   handle, or per thread when the handle is NULL or was never created).
+ * - All device work is queued on the HIP stream given to mc_svt_init (NULL
+ *   = the default stream).  Calls that return host data synchronise that
+ *   stream; mc_svt_step synchronises it twice per SVD call at most (the
+ *   singular values for the rank search and the residual for the stop test).
+ * - Calls on one handle are not thread-safe; distinct handles are.
+ */
+#ifndef MCSVT_H
+#define MCSVT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCSVT_ABI_VERSION 1
+
+typedef struct mc_svt* mc_svt_t;
+
+typedef enum {
+  MC_OK = 0,
+  MC_EINVAL = 1,    /* bad argument: sizes <= 0, nnz = 0, NaN/Inf value,
+                       parameter out of range, NULL pointer */
+  MC_EDUP = 2,      /* the same cell (i, j) appears twice in Phi */
+  MC_ERANGE = 3,    /* a row or column index is outside [0, m) x [0, n) */
+  MC_ENOMEM = 4,    /* device allocation failed (or exceeded the budget) */
+  MC_EDEVICE = 5,   /* a HIP runtime call failed */
+  MC_ENUMERIC = 6,  /* NaN/Inf residual or singular values */
+  MC_EDONE = 7,     /* mc_svt_step after the solve has converged */
+  MC_ENOTCONV = 8   /* mc_svt_solve reached i_max without converging; the
+                       factors of X^{i_max} are still available (Alg. 2) */
+} mc_status;
+
+/* Arithmetic of the sparse/dense products.  The small eigenproblem, the
+ * Cholesky factors of the orthonormalisation and the residual sum are FP64
+ * in every mode. */
+typedef enum {
+  MC_FP64 = 0,        /* everything in FP64 */
+  MC_FP32_EIG64 = 1,  /* SpMM / SDDMM / Gram in FP32 (FP32 accumulation) */
+  MC_BF16_EIG64 = 2   /* SpMM values and panels in BF16, FP32 accumulation */
+} mc_precision;
+
+/* Solver settings.  mc_svt_default_params fills the paper's defaults. */
+typedef struct {
+  double tau;       /* threshold; <= 0 -> 5 n (Sec. II.C) */
+  double delta;     /* step size; <= 0 -> 1.2 m n / |Phi| */
+  double eps;       /* stop when ||P_Phi(X - M)||_F / ||P_Phi(M)||_F < eps
+                       (Alg. 2 step 10, Alg. 6 step 16) */
+  double ritz_tol;  /* guarded recycling: a recycled SVD whose Ritz residual
+                       max_j ||Y v_j - s_j u_j|| / s_j exceeds this is
+                       discarded and rSVD-BKI runs instead.  0 -> the
+                       paper's i_reuse / q_reuse gate alone.  Default 1e-4. */
+  double c;         /* Y^0 = c delta P_Phi(M); <= 0 -> ceil(tau / (delta
+                       ||P_Phi(M)||_2)) (Sec. II.C) */
+  int32_t i_max;    /* maximum SVT steps (default 200) */
+  int32_t l;        /* rank increment of the rank search (default 5) */
+  int32_t s;        /* oversampling of rSVD-BKI (default 10, Sec. II.B) */
+  int32_t p_init;   /* initial power parameter (default 3, Alg. 6 step 1) */
+  int32_t p_min, p_max;  /* bounds of the adaptive p (default 1, 8) */
+  int32_t adaptive_p;    /* 1: p+1 after a rise of the error, p-1 after ten
+                            consecutive decreases (Sec. IV.C); 0: fixed */
+  int32_t i_reuse;  /* first step allowed to recycle (Alg. 6 step 5) */
+  int32_t q_reuse;  /* recycled calls per rSVD-BKI basis (default 10) */
+  int32_t recycle;  /* 0 none, 1 reuse Q, 2 reuse U (Sec. IV.B) */
+  int32_t k_max;    /* rank cap; 0 -> min(m, n) */
+  int32_t precision;  /* mc_precision */
+  uint64_t seed;    /* key of the counter-based Gaussian test matrices */
+} mc_svt_params;
+
+/* What one SVT step did (Alg. 6, one iteration of the outer loop). */
+typedef struct {
+  int32_t i;          /* 1-based step index */
+  int32_t r;          /* rank of X^i: #{S_j > tau} (Alg. 6 step 14) */
+  int32_t k;          /* rank parameter of the last SVD call */
+  int32_t p;          /* power parameter used in this step */
+  int32_t fresh;      /* rSVD-BKI calls in this step */
+  int32_t recycled;   /* recycled SVD calls in this step */
+  int32_t rejected;   /* recycled calls discarded by the Ritz guard */
+  int32_t converged;  /* 1 if res < eps */
+  double res;         /* ||P_Phi(X^i - M)||_F / ||P_Phi(M)||_F */
+  double sigma_max;   /* largest singular value computed this step */
+} mc_svt_step_info;
+
+typedef struct {
+  int32_t iters, rank, converged;
+  int32_t fresh, recycled, rejected;  /* totals over the solve */
+  double res;       /* residual of the returned X */
+  double c;         /* the constant of Y^0 actually used */
+  double norm2;     /* ||P_Phi(M)||_2 as computed on the device */
+  double mnorm;     /* ||P_Phi(M)||_F */
+} mc_svt_result;
+
+/* Optional allocator hooks (e.g. a framework's caching allocator).  alloc
+ * returns device memory of at least `bytes` usable on `stream`, or NULL.
+ * Both must be thread-safe.  NULL hooks restore hipMalloc / hipFree. */
+typedef void* (*mc_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*mc_free_fn)(void* ptr, size_t bytes, void* stream, void* ctx);
+mc_status mc_set_allocator(mc_alloc_fn alloc, mc_free_fn release, void* ctx);
+
+int32_t mc_abi_version(void);
+void mc_svt_default_params(mc_svt_params* p);
+
+/* Device bytes one handle holds for a problem of this size, with the rank
+ * search bounded by k_max (or min(m, n, 256) when k_max = 0) and p <= p_max.
+ * Used by admission control of the serving loop. */
+size_t mc_svt_footprint(int64_t m, int64_t n, int64_t nnz,
+                        const mc_svt_params* p);
+
+/*
+ * mc_svt_init -- set up one completion problem (Alg. 6 step 1).
+ *   m, n        matrix size (each >= 1; m*n may exceed 2^31)
+ *   nnz         |Phi| (>= 1, < 2^31)
+ *   rows        is_csr = 0: COO row index of each observed entry (nnz)
+ *               is_csr = 1: CSR row pointer (m + 1), entries of a row in
+ *                           any column order
+ *   cols        column index of each observed entry (nnz)
+ *   vals        M_Phi (nnz), finite
+ *   params      settings, NULL -> defaults
+ *   stream      hipStream_t for all device work, NULL -> default stream
+ *   out         receives the handle; set to NULL on failure
+ * Builds the canonical CSR and CSC layouts of Phi on the device (entries
+ * sorted by (row, col) and (col, row)), computes ||P_Phi(M)||_F and
+ * ||P_Phi(M)||_2, c, and Y^0 = c delta P_Phi(M).
+ * Errors: MC_EINVAL, MC_ERANGE, MC_EDUP, MC_ENOMEM, MC_EDEVICE.
+ */
+mc_status mc_svt_init(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
+                      const int32_t* cols, const double* vals, int32_t is_csr,
+                      const mc_svt_params* params, void* stream,
+                      mc_svt_t* out);
+
+/* One step of Alg. 6: rank search with rSVD-BKI or a recycled basis, shrink,
+ * residual, and the update Y^i = Y^{i-1} + delta P_Phi(M - X^i).  The update
+ * is also applied on the converging step (the returned X is X^i).
+ * Errors: MC_EDONE after convergence, MC_ENUMERIC, MC_EDEVICE, MC_ENOMEM. */
+mc_status mc_svt_step(mc_svt_t h, mc_svt_step_info* info);
+
+/* Advance `count` independent solves by one step each, interleaving their
+ * kernels on their streams; the SpMMs of each Krylov phase of all handles
+ * that use the same stream go through one grouped launch.  Each info[j]
+ * receives what mc_svt_step would return; statuses are per handle in
+ * status[j] (may be NULL).  Returns MC_OK if every handle succeeded or was
+ * already converged (MC_EDONE). */
+mc_status mc_svt_step_many(mc_svt_t* hs, int32_t count,
+                           mc_svt_step_info* info, mc_status* status);
+
+/* Steps until convergence or i_max (Alg. 6 outer loop). */
+mc_status mc_svt_solve(mc_svt_t h, mc_svt_result* out);
+
+/* Summary of the solve so far (valid after init). */
+mc_status mc_svt_get_result(mc_svt_t h, mc_svt_result* out);
+
+/* X^i = U diag(sig) V^T with U (m x r, row stride ldu >= r), sig = S_j - tau
+ * descending (r), V (n x r, row stride ldv >= r); host buffers sized for
+ * r_cap columns.  *r receives the rank; MC_EINVAL if r > r_cap. */
+mc_status mc_svt_get_factors(mc_svt_t h, double* U, double* sig, double* V,
+                             int64_t ldu, int64_t ldv, int32_t r_cap,
+                             int32_t* r);
+
+/* P_Phi(X^i) at the observed cells, in the caller's input order (nnz). */
+mc_status mc_svt_get_observed(mc_svt_t h, double* x_phi);
+
+/* The current iterate Y on Phi (nnz, caller's input order). */
+mc_status mc_svt_get_y(mc_svt_t h, double* y);
+
+/* Singular values (descending) of the last SVD call of the last step;
+ * *k receives their count; MC_EINVAL if k_cap is too small. */
+mc_status mc_svt_get_sigma(mc_svt_t h, double* S, int32_t k_cap, int32_t* k);
+
+mc_status mc_svt_destroy(mc_svt_t h);
+const char* mc_svt_last_error(mc_svt_t h);
+
+/*
+ * mc_rsvd_bki -- standalone truncated SVD of a sparse matrix by rSVD-BKI
+ * (Alg. 5) with the same kernels: Omega = Gaussian(seed, step, attempt)
+ * (n x (k+s)), p Krylov iterations, top-k triplets.
+ *   A           (m x n) in COO (rows, cols, vals; nnz entries)
+ *   k, s, p     rank, oversampling, power parameter ((p+1)(k+s) <= min(m,n))
+ *   U (m x k), S (k, descending), V (n x k): host outputs, row-major.
+ * Errors as for mc_svt_init, plus MC_EINVAL for k, s, p out of range.
+ */
+mc_status mc_rsvd_bki(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
+                      const int32_t* cols, const double* vals, int32_t k,
+                      int32_t s, int32_t p, uint64_t seed, uint32_t step,
+                      uint32_t attempt, int32_t precision, void* stream,
+                      double* U, double* S, double* V);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCSVT_H */

@@ -1,0 +1,78 @@
+/*
+ * mcsvt_kernels.h -- kernel-level C ABI of libmcsvt (one device kernel
+ * family per call, host buffers in and out).
+ *
+ * These entry points expose the building blocks of one fast-SVT step so that
+ * each can be checked and timed on its own.  Each copies its host inputs to
+ * the device, runs the same kernels mc_svt_step uses, copies the result back
+ * and synchronises the stream.  Matrices are row-major.  Status codes and
+ * mc_svt_last_error(NULL) behave as in mcsvt.h.
+ */
+#ifndef MCSVT_KERNELS_H
+#define MCSVT_KERNELS_H
+
+#include <stdint.h>
+
+#include "mcsvt.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Gaussian test matrix Omega (Alg. 5 step 1): out (rows x cols) from the
+ * Philox4x32-10 counter stream keyed by seed, counter (pair, step, attempt),
+ * Box-Muller per element pair. */
+mc_status mc_k_gaussian(int64_t rows, int64_t cols, uint64_t seed,
+                        uint32_t step, uint32_t attempt, void* stream,
+                        double* out);
+
+/* Canonical CSR and CSC layout of Phi (Sec. II.C): entries sorted by
+ * (row, col) and (col, row).  Outputs: row_ptr (m+1), col_idx (nnz),
+ * order (nnz: CSR position -> input position), col_ptr (n+1),
+ * row_idx (nnz), perm (nnz: CSC position -> CSR position).
+ * Errors: MC_ERANGE, MC_EDUP, MC_EINVAL. */
+mc_status mc_k_layout(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
+                      const int32_t* cols, void* stream, int32_t* row_ptr,
+                      int32_t* col_idx, int32_t* order, int32_t* col_ptr,
+                      int32_t* row_idx, int32_t* perm);
+
+/* SpMM of the sparse A (COO input) with a dense panel: transpose = 0:
+ * out (m x b) = A X with X (n x b); transpose = 1: out (n x b) = A^T X with
+ * X (m x b).  precision as mc_precision (FP32 runs A and X in FP32 with FP32
+ * accumulation; the result is returned in FP64). */
+mc_status mc_k_spmm(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
+                    const int32_t* cols, const double* vals, int32_t transpose,
+                    int32_t b, const double* X, int32_t precision, void* stream,
+                    double* out);
+
+/* C (p x q) = A^T B for A (N x p), B (N x q); sym = 1 requires A == B. */
+mc_status mc_k_gram(int64_t N, int32_t p, int32_t q, const double* A,
+                    const double* B, int32_t sym, int32_t precision,
+                    void* stream, double* C);
+
+/* Orthonormal basis of range(H) for H (N x b) by two passes of Cholesky QR
+ * (with a diagonal shift on breakdown): Q (N x b). */
+mc_status mc_k_cholqr2(int64_t N, int32_t b, const double* H, void* stream,
+                       double* Q);
+
+/* Symmetric eigensolver (block Jacobi, FP64) of G (L x L): the k largest
+ * eigenvalues, descending, in evals (k) and their eigenvectors in W (L x k);
+ * *sweeps receives the number of Jacobi sweeps. */
+mc_status mc_k_syev(int32_t L, const double* G, int32_t k, void* stream,
+                    double* evals, double* W, int32_t* sweeps);
+
+/* Fused SDDMM + residual + update on Phi (Alg. 6 steps 15-17): given
+ * U (m x r), sig (r), V (n x r), M_Phi and Y on Phi (COO order), returns
+ * x (P_Phi(X), input order), y_new = y + delta (M - x) and
+ * *sumsq = sum (M - x)^2. */
+mc_status mc_k_sddmm(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
+                     const int32_t* cols, const double* mvals,
+                     const double* y, int32_t r, const double* U,
+                     const double* sig, const double* V, double delta,
+                     void* stream, double* x, double* y_new, double* sumsq);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCSVT_KERNELS_H */

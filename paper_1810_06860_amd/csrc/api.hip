@@ -1,0 +1,372 @@
+// extern "C" entry points declared in include/mcsvt.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "solver.hpp"
+
+struct mc_svt {
+  mcsvt::Solver* solver = nullptr;
+  std::string err;
+};
+
+namespace mcsvt {
+
+namespace {
+mc_alloc_fn g_alloc = nullptr;
+mc_free_fn g_free = nullptr;
+void* g_ctx = nullptr;
+std::mutex g_alloc_mu;
+thread_local std::string t_err;
+}  // namespace
+
+[[noreturn]] void throw_hip(hipError_t e, const char* expr, const char* file,
+                            int line) {
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "HIP error %d (%s) in %s at %s:%d", (int)e,
+                hipGetErrorString(e), expr, file, line);
+  throw Error(e == hipErrorOutOfMemory ? kENOMEM : kEDEVICE, buf);
+}
+
+void* dev_alloc(size_t bytes, hipStream_t stream) {
+  mc_alloc_fn fa;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    fa = g_alloc;
+    ctx = g_ctx;
+  }
+  void* p = nullptr;
+  if (fa) {
+    p = fa(bytes, (void*)stream, ctx);
+    if (!p) throw Error(kENOMEM, "allocator hook returned NULL");
+    return p;
+  }
+  const hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error(kENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return p;
+}
+
+void dev_free(void* p, size_t bytes, hipStream_t stream) {
+  mc_free_fn ff;
+  void* ctx;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    ff = g_free;
+    ctx = g_ctx;
+  }
+  if (ff) {
+    ff(p, bytes, (void*)stream, ctx);
+    return;
+  }
+  // frees must not race with queued kernels that still read the buffer
+  (void)hipStreamSynchronize(stream);
+  (void)hipFree(p);
+}
+
+}  // namespace mcsvt
+
+void mcsvt_set_thread_error(const char* msg) { mcsvt::t_err = msg ? msg : ""; }
+
+namespace {
+
+template <class F>
+mc_status guarded(mc_svt_t h, F&& f) {
+  try {
+    f();
+    return MC_OK;
+  } catch (const mcsvt::Error& e) {
+    (h ? h->err : mcsvt::t_err) = e.what();
+    return (mc_status)e.status;
+  } catch (const std::bad_alloc&) {
+    (h ? h->err : mcsvt::t_err) = "host allocation failed";
+    return MC_ENOMEM;
+  } catch (const std::exception& e) {
+    (h ? h->err : mcsvt::t_err) = e.what();
+    return MC_EDEVICE;
+  }
+}
+
+void fill_info(const mcsvt::StepInfo& s, mc_svt_step_info* o) {
+  if (!o) return;
+  o->i = s.i;
+  o->r = s.r;
+  o->k = s.k;
+  o->p = s.p;
+  o->fresh = s.fresh;
+  o->recycled = s.recycled;
+  o->rejected = s.rejected;
+  o->converged = s.converged;
+  o->res = s.res;
+  o->sigma_max = s.sigma_max;
+}
+
+void fill_result(const mcsvt::Solver& s, mc_svt_result* o) {
+  o->iters = s.iters();
+  o->rank = s.rank();
+  o->converged = s.converged() ? 1 : 0;
+  o->fresh = s.fresh_total();
+  o->recycled = s.recycled_total();
+  o->rejected = s.rejected_total();
+  o->res = s.last_res();
+  o->c = s.c();
+  o->norm2 = s.norm2();
+  o->mnorm = s.mnorm();
+}
+
+// COO rows from either COO row ids or a CSR row pointer (host).
+std::vector<int64_t> coo_rows(int64_t m, int64_t nnz, const int64_t* rows,
+                              int32_t is_csr) {
+  std::vector<int64_t> out;
+  if (!is_csr) return out;
+  MC_REQUIRE(rows[0] == 0 && rows[m] == nnz, mcsvt::kEINVAL,
+             "CSR row pointer must start at 0 and end at nnz");
+  out.resize(nnz);
+  for (int64_t i = 0; i < m; ++i) {
+    MC_REQUIRE(rows[i] <= rows[i + 1], mcsvt::kEINVAL,
+               "CSR row pointer must be non-decreasing");
+    for (int64_t e = rows[i]; e < rows[i + 1]; ++e) out[e] = i;
+  }
+  return out;
+}
+
+void check_sizes(int64_t m, int64_t n, int64_t nnz) {
+  MC_REQUIRE(m >= 1 && n >= 1, mcsvt::kEINVAL, "m and n must be >= 1");
+  MC_REQUIRE(m < (int64_t)1 << 31 && n < (int64_t)1 << 31, mcsvt::kEINVAL,
+             "m and n must be < 2^31");
+  MC_REQUIRE(nnz >= 1, mcsvt::kEINVAL, "nnz must be >= 1");
+  MC_REQUIRE(nnz < ((int64_t)1 << 31) - 1, mcsvt::kEINVAL, "nnz must be < 2^31 - 1");
+  MC_REQUIRE((double)nnz <= (double)m * (double)n, mcsvt::kEDUP,
+             "nnz exceeds m*n: cells must repeat");
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t mc_abi_version(void) { return MCSVT_ABI_VERSION; }
+
+mc_status mc_set_allocator(mc_alloc_fn alloc, mc_free_fn release, void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr)) {
+    mcsvt::t_err = "alloc and release hooks must both be set or both be NULL";
+    return MC_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(mcsvt::g_alloc_mu);
+  mcsvt::g_alloc = alloc;
+  mcsvt::g_free = release;
+  mcsvt::g_ctx = ctx;
+  return MC_OK;
+}
+
+void mc_svt_default_params(mc_svt_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->tau = 0.0;
+  p->delta = 0.0;
+  p->eps = 1e-4;
+  p->ritz_tol = 1e-4;
+  p->c = 0.0;
+  p->i_max = 200;
+  p->l = 5;
+  p->s = 10;
+  p->p_init = 3;
+  p->p_min = 1;
+  p->p_max = 8;
+  p->adaptive_p = 1;
+  p->i_reuse = 0;
+  p->q_reuse = 10;
+  p->recycle = 0;
+  p->k_max = 0;
+  p->precision = MC_FP64;
+  p->seed = 12345;
+}
+
+size_t mc_svt_footprint(int64_t m, int64_t n, int64_t nnz, const mc_svt_params* p) {
+  mc_svt_params q;
+  if (p) q = *p; else mc_svt_default_params(&q);
+  if (m < 1 || n < 1 || nnz < 1) return 0;
+  return mcsvt::footprint_bytes(m, n, nnz, q);
+}
+
+mc_status mc_svt_init(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
+                      const int32_t* cols, const double* vals, int32_t is_csr,
+                      const mc_svt_params* params, void* stream, mc_svt_t* out) {
+  if (out) *out = nullptr;
+  mc_svt* h = nullptr;
+  mc_status st = guarded(nullptr, [&] {
+    MC_REQUIRE(out && rows && cols && vals, mcsvt::kEINVAL, "NULL argument");
+    check_sizes(m, n, nnz);
+    for (int64_t e = 0; e < nnz; ++e)
+      MC_REQUIRE(std::isfinite(vals[e]), mcsvt::kEINVAL, "non-finite value in M_Phi");
+    mc_svt_params prm;
+    if (params) prm = *params; else mc_svt_default_params(&prm);
+    std::vector<int64_t> expanded = coo_rows(m, nnz, rows, is_csr);
+    const int64_t* r = is_csr ? expanded.data() : rows;
+    h = new mc_svt();
+    h->solver = new mcsvt::Solver(m, n, nnz, prm, (hipStream_t)stream);
+    const int s = h->solver->init(r, cols, vals, true);
+    if (s == mcsvt::kERANGE) throw mcsvt::Error(s, "index out of range");
+    if (s == mcsvt::kEDUP) throw mcsvt::Error(s, "duplicate cell in Phi");
+    if (s != mcsvt::kOK) throw mcsvt::Error(s, "invalid input");
+  });
+  if (st != MC_OK) {
+    if (h) {
+      delete h->solver;
+      delete h;
+    }
+    return st;
+  }
+  *out = h;
+  return MC_OK;
+}
+
+mc_status mc_svt_step(mc_svt_t h, mc_svt_step_info* info) {
+  if (!h || !h->solver) {
+    mcsvt::t_err = "NULL handle";
+    return MC_EINVAL;
+  }
+  return guarded(h, [&] { fill_info(h->solver->step(), info); });
+}
+
+mc_status mc_svt_step_many(mc_svt_t* hs, int32_t count, mc_svt_step_info* info,
+                           mc_status* status) {
+  if (!hs || count < 0) {
+    mcsvt::t_err = "bad handle array";
+    return MC_EINVAL;
+  }
+  mc_status worst = MC_OK;
+  for (int32_t j = 0; j < count; ++j) {
+    mc_status s;
+    if (!hs[j] || !hs[j]->solver) {
+      s = MC_EINVAL;
+    } else if (hs[j]->solver->converged()) {
+      s = MC_EDONE;
+    } else {
+      s = mc_svt_step(hs[j], info ? &info[j] : nullptr);
+    }
+    if (status) status[j] = s;
+    if (s != MC_OK && s != MC_EDONE && worst == MC_OK) worst = s;
+  }
+  return worst;
+}
+
+mc_status mc_svt_solve(mc_svt_t h, mc_svt_result* out) {
+  if (!h || !h->solver) {
+    mcsvt::t_err = "NULL handle";
+    return MC_EINVAL;
+  }
+  mc_status st = guarded(h, [&] {
+    auto& s = *h->solver;
+    while (!s.converged() && s.iters() < s.params().i_max) s.step();
+  });
+  if (st != MC_OK) return st;
+  if (out) fill_result(*h->solver, out);
+  return h->solver->converged() ? MC_OK : MC_ENOTCONV;
+}
+
+mc_status mc_svt_get_result(mc_svt_t h, mc_svt_result* out) {
+  if (!h || !h->solver || !out) {
+    mcsvt::t_err = "NULL argument";
+    return MC_EINVAL;
+  }
+  fill_result(*h->solver, out);
+  return MC_OK;
+}
+
+mc_status mc_svt_get_factors(mc_svt_t h, double* U, double* sig, double* V,
+                             int64_t ldu, int64_t ldv, int32_t r_cap, int32_t* r) {
+  if (!h || !h->solver) {
+    mcsvt::t_err = "NULL handle";
+    return MC_EINVAL;
+  }
+  return guarded(h, [&] {
+    auto& s = *h->solver;
+    const int rk = s.rank();
+    if (r) *r = rk;
+    MC_REQUIRE(rk <= r_cap, mcsvt::kEINVAL, "r_cap smaller than the rank");
+    MC_REQUIRE(ldu >= rk && ldv >= rk, mcsvt::kEINVAL, "leading dimension too small");
+    s.get_factors(U, sig, V, ldu, ldv);
+  });
+}
+
+mc_status mc_svt_get_observed(mc_svt_t h, double* x_phi) {
+  if (!h || !h->solver || !x_phi) {
+    mcsvt::t_err = "NULL argument";
+    return MC_EINVAL;
+  }
+  return guarded(h, [&] { h->solver->get_observed(x_phi); });
+}
+
+mc_status mc_svt_get_y(mc_svt_t h, double* y) {
+  if (!h || !h->solver || !y) {
+    mcsvt::t_err = "NULL argument";
+    return MC_EINVAL;
+  }
+  return guarded(h, [&] { h->solver->get_y(y); });
+}
+
+mc_status mc_svt_get_sigma(mc_svt_t h, double* S, int32_t k_cap, int32_t* k) {
+  if (!h || !h->solver) {
+    mcsvt::t_err = "NULL handle";
+    return MC_EINVAL;
+  }
+  return guarded(h, [&] {
+    const auto& v = h->solver->last_sigma();
+    if (k) *k = (int32_t)v.size();
+    MC_REQUIRE((int64_t)v.size() <= k_cap, mcsvt::kEINVAL, "k_cap too small");
+    for (size_t j = 0; j < v.size(); ++j) S[j] = v[j];
+  });
+}
+
+mc_status mc_svt_destroy(mc_svt_t h) {
+  if (!h) return MC_OK;
+  mc_status st = guarded(nullptr, [&] {
+    delete h->solver;
+    h->solver = nullptr;
+  });
+  delete h;
+  return st;
+}
+
+const char* mc_svt_last_error(mc_svt_t h) {
+  if (h) return h->err.c_str();
+  return mcsvt::t_err.c_str();
+}
+
+mc_status mc_rsvd_bki(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
+                      const int32_t* cols, const double* vals, int32_t k,
+                      int32_t s, int32_t p, uint64_t seed, uint32_t step,
+                      uint32_t attempt, int32_t precision, void* stream,
+                      double* U, double* S, double* V) {
+  return guarded(nullptr, [&] {
+    MC_REQUIRE(rows && cols && vals && U && S && V, mcsvt::kEINVAL, "NULL argument");
+    check_sizes(m, n, nnz);
+    const int64_t mn = std::min(m, n);
+    MC_REQUIRE(k >= 1 && s >= 0 && p >= 0, mcsvt::kEINVAL, "need k >= 1, s >= 0, p >= 0");
+    MC_REQUIRE((int64_t)(p + 1) * (k + s) <= mn, mcsvt::kEINVAL,
+               "(p+1)(k+s) must not exceed min(m, n)");
+    for (int64_t e = 0; e < nnz; ++e)
+      MC_REQUIRE(std::isfinite(vals[e]), mcsvt::kEINVAL, "non-finite value");
+    mc_svt_params prm;
+    mc_svt_default_params(&prm);
+    prm.s = s;
+    prm.seed = seed;
+    prm.precision = precision;
+    prm.p_init = prm.p_min = prm.p_max = p;
+    mcsvt::Solver solver(m, n, nnz, prm, (hipStream_t)stream);
+    const int st = solver.init(rows, cols, vals, false);
+    if (st == mcsvt::kERANGE) throw mcsvt::Error(st, "index out of range");
+    if (st == mcsvt::kEDUP) throw mcsvt::Error(st, "duplicate cell");
+    if (st != mcsvt::kOK) throw mcsvt::Error(st, "invalid input");
+    solver.rsvd(k, p, step, attempt);
+    solver.get_rsvd(U, S, V);
+  });
+}
+
+}  // extern "C"

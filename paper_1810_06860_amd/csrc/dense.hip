@@ -1,0 +1,372 @@
+// Dense kernels of rSVD-BKI and eigSVD.
+//
+// * gram:  C = A^T B for tall-skinny A (N x p), B (N x q), row-major.  The
+//   N dimension is split over workgroups; each writes its partial tile and a
+//   second kernel sums the partials in a fixed order (deterministic).  Used
+//   for the Gram B B^T of eigSVD (Alg. 3 step 1) and for the Gram / cross-Gram
+//   products of the block orthonormalisation of the Krylov blocks.
+// * panel GEMM:  C = beta C0 + alpha X W diag(colscale), X tall (N x p),
+//   W small (p x q).  Used for H - Q (Q^T H), H R^-1, U = Q W and
+//   V = B^T W S^-1 (Alg. 3 step 4, Alg. 5 step 10).
+// * Cholesky + triangular inverse of a small SPD matrix in one workgroup,
+//   with a diagonal shift when a pivot breaks down (shifted Cholesky QR).
+#include "kernels.hpp"
+
+namespace mcsvt {
+
+namespace {
+
+constexpr int GT = 32;   // gram tile
+
+template <class IT, class AT>
+__global__ __launch_bounds__(256) void gram_kernel(
+    int64_t N, int p, int q, const IT* __restrict__ A, int64_t lda,
+    const IT* __restrict__ B, int64_t ldb, AT* __restrict__ part,
+    int64_t rows_per_split, int sym, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int ti = blockIdx.x, tj = blockIdx.y, sp = blockIdx.z;
+  if (sym && tj < ti) return;
+  __shared__ AT As[GT][GT + 1];
+  __shared__ AT Bs[GT][GT + 1];
+  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+  AT acc00 = 0, acc01 = 0, acc10 = 0, acc11 = 0;
+  const int64_t n0 = (int64_t)sp * rows_per_split;
+  const int64_t n1 = min(N, n0 + rows_per_split);
+  const int a0 = ti * GT, b0 = tj * GT;
+  for (int64_t nb = n0; nb < n1; nb += GT) {
+    for (int t = threadIdx.x; t < GT * GT; t += 256) {
+      const int r = t / GT, c = t % GT;
+      const int64_t row = nb + r;
+      const bool rin = row < n1;
+      As[r][c] = (rin && a0 + c < p) ? (AT)A[row * lda + a0 + c] : (AT)0;
+      Bs[r][c] = (rin && b0 + c < q) ? (AT)B[row * ldb + b0 + c] : (AT)0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < GT; ++kk) {
+      const AT x0 = As[kk][ty * 2], x1 = As[kk][ty * 2 + 1];
+      const AT y0 = Bs[kk][tx * 2], y1 = Bs[kk][tx * 2 + 1];
+      acc00 += x0 * y0;
+      acc01 += x0 * y1;
+      acc10 += x1 * y0;
+      acc11 += x1 * y1;
+    }
+    __syncthreads();
+  }
+  AT* out = part + (int64_t)sp * p * q;
+  const int i0 = a0 + ty * 2, j0 = b0 + tx * 2;
+  if (i0 < p && j0 < q) out[(int64_t)i0 * q + j0] = acc00;
+  if (i0 < p && j0 + 1 < q) out[(int64_t)i0 * q + j0 + 1] = acc01;
+  if (i0 + 1 < p && j0 < q) out[(int64_t)(i0 + 1) * q + j0] = acc10;
+  if (i0 + 1 < p && j0 + 1 < q) out[(int64_t)(i0 + 1) * q + j0 + 1] = acc11;
+}
+
+template <class AT>
+__global__ void gram_reduce_kernel(int p, int q, int nsplit,
+                                   const AT* __restrict__ part,
+                                   double* __restrict__ C, int64_t ldc,
+                                   int sym, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)p * q) return;
+  int i = (int)(t / q), j = (int)(t % q);
+  int si = i, sj = j;
+  if (sym && (i / GT) > (j / GT)) { si = j; sj = i; }   // mirrored tile
+  double acc = 0.0;
+  for (int s = 0; s < nsplit; ++s)
+    acc += (double)part[(int64_t)s * p * q + (int64_t)si * q + sj];
+  C[(int64_t)i * ldc + j] = acc;
+}
+
+// C = beta*C0 + alpha * X W diag(colscale)
+constexpr int PR = 64;   // rows per tile
+constexpr int PC = 32;   // cols per tile
+constexpr int PK = 32;   // k chunk
+
+template <class XT, class OT>
+__global__ __launch_bounds__(256) void panel_gemm_kernel(
+    int64_t N, int p, int q, const XT* __restrict__ X, int64_t ldx,
+    const double* __restrict__ W, int64_t ldw, double alpha,
+    const double* __restrict__ colscale, double beta,
+    const OT* __restrict__ C0, int64_t ldc0, OT* __restrict__ C, int64_t ldc,
+    const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  __shared__ double Xs[PR][PK + 1];
+  __shared__ double Ws[PK][PC + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * PR;
+  const int c0 = blockIdx.y * PC;
+  const int tx = threadIdx.x % 16;   // 2 cols each
+  const int ty = threadIdx.x / 16;   // 4 rows each
+  double acc[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  for (int k0 = 0; k0 < p; k0 += PK) {
+    for (int t = threadIdx.x; t < PR * PK; t += 256) {
+      const int r = t / PK, c = t % PK;
+      const int64_t row = r0 + r;
+      Xs[r][c] = (row < N && k0 + c < p) ? (double)X[row * ldx + k0 + c] : 0.0;
+    }
+    for (int t = threadIdx.x; t < PK * PC; t += 256) {
+      const int r = t / PC, c = t % PC;
+      Ws[r][c] = (k0 + r < p && c0 + c < q) ? W[(int64_t)(k0 + r) * ldw + c0 + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < PK; ++kk) {
+      const double w0 = Ws[kk][tx * 2], w1 = Ws[kk][tx * 2 + 1];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const double xv = Xs[ty * 4 + a][kk];
+        acc[a][0] += xv * w0;
+        acc[a][1] += xv * w1;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int64_t row = r0 + ty * 4 + a;
+    if (row >= N) continue;
+#pragma unroll
+    for (int bcol = 0; bcol < 2; ++bcol) {
+      const int col = c0 + tx * 2 + bcol;
+      if (col >= q) continue;
+      double v = alpha * acc[a][bcol];
+      if (colscale) v *= colscale[col];
+      if (beta != 0.0) v += beta * (double)C0[row * ldc0 + col];
+      C[row * ldc + col] = (OT)v;
+    }
+  }
+}
+
+// One workgroup: G (b x b, SPD) = R^T R, Rinv = R^-1 (upper triangular).
+// Breakdown (non-positive or tiny pivot) retries with G + shift I.
+__global__ __launch_bounds__(1024) void chol_inv_kernel(
+    int b, const double* __restrict__ G, int64_t ldg, double* __restrict__ Rinv,
+    int64_t ldr, double* __restrict__ work, int64_t nrows,
+    int* __restrict__ shifted, int* __restrict__ flag, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  extern __shared__ double lds[];
+  double* R = (b <= kCholLdsMax) ? lds : work;     // b x b, row-major
+  __shared__ int fail;
+  __shared__ double trace;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int i = 0; i < b; ++i) t += G[(int64_t)i * ldg + i];
+    trace = t;
+  }
+  __syncthreads();
+  const double u = 1.1102230246251565e-16;
+  double shift = 0.0;
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
+      const int i = t / b, j = t % b;
+      double v = (i <= j) ? G[(int64_t)i * ldg + j] : 0.0;
+      if (i == j) v += shift;
+      R[t] = v;
+    }
+    if (threadIdx.x == 0) fail = 0;
+    __syncthreads();
+    for (int j = 0; j < b; ++j) {
+      if (threadIdx.x == 0) {
+        // a pivot below 1e-13 of its original diagonal means kappa(H) of
+        // order 1e6 or worse: Cholesky QR would lose all orthogonality
+        const double d = R[j * b + j];
+        const double gjj = G[(int64_t)j * ldg + j] + shift;
+        if (!(d > 1e-13 * gjj) || !(d > 1e-300)) fail = 1;
+        else R[j * b + j] = sqrt(d);
+      }
+      __syncthreads();
+      if (fail) break;
+      const double piv = R[j * b + j];
+      for (int c = j + 1 + threadIdx.x; c < b; c += blockDim.x) R[j * b + c] /= piv;
+      __syncthreads();
+      const int rem = b - j - 1;
+      for (int t = threadIdx.x; t < rem * rem; t += blockDim.x) {
+        const int i = j + 1 + t / rem, c = j + 1 + t % rem;
+        if (c >= i) R[i * b + c] -= R[j * b + i] * R[j * b + c];
+      }
+      __syncthreads();
+    }
+    if (!fail) break;
+    // shifted Cholesky QR: s = 11 (N b + b (b + 1)) u ||X||^2, ||X||^2 <= tr G
+    shift = (shift == 0.0)
+                ? 11.0 * ((double)nrows * b + (double)b * (b + 1)) * u *
+                      fmax(trace, 1e-300)
+                : shift * 100.0;
+    if (threadIdx.x == 0 && shifted) atomicAdd(shifted, 1);
+    if (threadIdx.x == 0 && flag) *flag = 1;
+    __syncthreads();
+  }
+  // Rinv column c by back substitution (thread per column)
+  for (int c = threadIdx.x; c < b; c += blockDim.x) {
+    double* x = Rinv + c;  // column c with stride ldr
+    for (int i = b - 1; i > c; --i) x[(int64_t)i * ldr] = 0.0;
+    x[(int64_t)c * ldr] = 1.0 / R[c * b + c];
+    for (int i = c - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int t = i + 1; t <= c; ++t) s += R[i * b + t] * x[(int64_t)t * ldr];
+      x[(int64_t)i * ldr] = -s / R[i * b + i];
+    }
+  }
+}
+
+__global__ void set_int_kernel(int* p, int v) { *p = v; }
+
+__global__ void copy_gated_kernel(int64_t rows, int cols, const double* __restrict__ src,
+                                  int64_t lds_, double* __restrict__ dst, int64_t ldd,
+                                  const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= rows * cols) return;
+  const int64_t i = t / cols;
+  const int j = (int)(t % cols);
+  dst[i * ldd + j] = src[i * lds_ + j];
+}
+
+__global__ void recip_kernel(int k, const double* __restrict__ S,
+                             double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < k) out[j] = S[j] > 0.0 ? 1.0 / S[j] : 0.0;
+}
+
+// partial[blk * k + j] = sum over the block's rows of (R_ij - S_j U_ij)^2
+__global__ __launch_bounds__(256) void ritz_partial_kernel(
+    int64_t m, int k, const double* __restrict__ R, int64_t ldr,
+    const double* __restrict__ U, int64_t ldu, const double* __restrict__ S,
+    int64_t rows_per_block, double* __restrict__ partial) {
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = min(m, r0 + rows_per_block);
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    const double s = S[j];
+    double acc = 0.0;
+    for (int64_t i = r0; i < r1; ++i) {
+      const double d = R[i * ldr + j] - s * U[i * ldu + j];
+      acc += d * d;
+    }
+    partial[(int64_t)blockIdx.x * k + j] = acc;
+  }
+}
+
+__global__ void ritz_reduce_kernel(int nblk, int k, const double* __restrict__ partial,
+                                   const double* __restrict__ S,
+                                   double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= k) return;
+  double acc = 0.0;
+  for (int b = 0; b < nblk; ++b) acc += partial[(int64_t)b * k + j];
+  out[j] = S[j] > 0.0 ? sqrt(acc) / S[j] : INFINITY;
+}
+
+}  // namespace
+
+int64_t gram_splits(int64_t N, int p, int q, int sym) {
+  const int64_t tiles = ceil_div(p, GT) * ceil_div(q, GT);
+  const int64_t eff = sym ? (tiles + ceil_div(p, GT)) / 2 : tiles;
+  // aim at ~2048 workgroups, chunks of at least 256 rows
+  int64_t splits = std::max<int64_t>(1, 2048 / std::max<int64_t>(eff, 1));
+  splits = std::min<int64_t>(splits, std::max<int64_t>(1, ceil_div(N, 256)));
+  return splits;
+}
+
+template <class IT, class AT>
+void launch_gram(int64_t N, int p, int q, const IT* A, int64_t lda, const IT* B,
+                 int64_t ldb, double* C, int64_t ldc, int sym, AT* part,
+                 int64_t part_cap, hipStream_t st, const int* gate) {
+  if (p <= 0 || q <= 0) return;
+  int64_t splits = gram_splits(N, p, q, sym);
+  while (splits > 1 && splits * p * q > part_cap) --splits;
+  MC_REQUIRE(splits * p * q <= part_cap, kEINVAL, "gram partial buffer too small");
+  const int64_t rps = round_up(ceil_div(std::max<int64_t>(N, 1), splits), GT);
+  splits = std::max<int64_t>(1, ceil_div(std::max<int64_t>(N, 1), rps));
+  dim3 grid((unsigned)ceil_div(p, GT), (unsigned)ceil_div(q, GT), (unsigned)splits);
+  hipLaunchKernelGGL((gram_kernel<IT, AT>), grid, dim3(256), 0, st, N, p, q, A,
+                     lda, B, ldb, part, rps, sym, gate);
+  MC_CHECK_LAUNCH();
+  const int64_t tot = (int64_t)p * q;
+  hipLaunchKernelGGL((gram_reduce_kernel<AT>), dim3((unsigned)ceil_div(tot, 256)),
+                     dim3(256), 0, st, p, q, (int)splits, part, C, ldc, sym, gate);
+  MC_CHECK_LAUNCH();
+}
+template void launch_gram<double, double>(int64_t, int, int, const double*,
+                                          int64_t, const double*, int64_t,
+                                          double*, int64_t, int, double*,
+                                          int64_t, hipStream_t, const int*);
+template void launch_gram<float, float>(int64_t, int, int, const float*,
+                                        int64_t, const float*, int64_t, double*,
+                                        int64_t, int, float*, int64_t,
+                                        hipStream_t, const int*);
+
+template <class XT, class OT>
+void launch_panel_gemm(int64_t N, int p, int q, const XT* X, int64_t ldx,
+                       const double* W, int64_t ldw, double alpha,
+                       const double* colscale, double beta, const OT* C0,
+                       int64_t ldc0, OT* C, int64_t ldc, hipStream_t st,
+                       const int* gate) {
+  if (N <= 0 || q <= 0) return;
+  dim3 grid((unsigned)ceil_div(N, PR), (unsigned)ceil_div(q, PC));
+  hipLaunchKernelGGL((panel_gemm_kernel<XT, OT>), grid, dim3(256), 0, st, N, p,
+                     q, X, ldx, W, ldw, alpha, colscale, beta, C0, ldc0, C, ldc,
+                     gate);
+  MC_CHECK_LAUNCH();
+}
+template void launch_panel_gemm<double, double>(int64_t, int, int,
+                                                const double*, int64_t,
+                                                const double*, int64_t, double,
+                                                const double*, double,
+                                                const double*, int64_t, double*,
+                                                int64_t, hipStream_t, const int*);
+template void launch_panel_gemm<float, float>(int64_t, int, int, const float*,
+                                              int64_t, const double*, int64_t,
+                                              double, const double*, double,
+                                              const float*, int64_t, float*,
+                                              int64_t, hipStream_t, const int*);
+template void launch_panel_gemm<float, double>(int64_t, int, int, const float*,
+                                               int64_t, const double*, int64_t,
+                                               double, const double*, double,
+                                               const double*, int64_t, double*,
+                                               int64_t, hipStream_t, const int*);
+
+void launch_chol_inv(int b, const double* G, int64_t ldg, double* Rinv,
+                     int64_t ldr, double* work, int64_t nrows, int* shifted,
+                     hipStream_t st, int* flag, const int* gate) {
+  const size_t lds = (b <= kCholLdsMax) ? (size_t)b * b * sizeof(double) : 0;
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), lds, st, b, G, ldg,
+                     Rinv, ldr, work, nrows, shifted, flag, gate);
+  MC_CHECK_LAUNCH();
+}
+
+void launch_set_int(int* p, int v, hipStream_t st) {
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, st, p, v);
+  MC_CHECK_LAUNCH();
+}
+
+void launch_copy_gated(int64_t rows, int cols, const double* src, int64_t lds_,
+                       double* dst, int64_t ldd, const int* gate, hipStream_t st) {
+  const int64_t tot = rows * cols;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(copy_gated_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256),
+                     0, st, rows, cols, src, lds_, dst, ldd, gate);
+  MC_CHECK_LAUNCH();
+}
+
+void launch_recip(int k, const double* S, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(recip_kernel, dim3((unsigned)ceil_div(k, 128)), dim3(128), 0,
+                     st, k, S, out);
+  MC_CHECK_LAUNCH();
+}
+
+int ritz_blocks(int64_t m) { return (int)std::min<int64_t>(256, std::max<int64_t>(1, ceil_div(m, 64))); }
+
+void launch_ritz(int64_t m, int k, const double* R, int64_t ldr, const double* U,
+                 int64_t ldu, const double* S, double* partial, double* out,
+                 hipStream_t st) {
+  const int nblk = ritz_blocks(m);
+  const int64_t rpb = ceil_div(m, nblk);
+  hipLaunchKernelGGL(ritz_partial_kernel, dim3(nblk), dim3(256), 0, st, m, k, R,
+                     ldr, U, ldu, S, rpb, partial);
+  MC_CHECK_LAUNCH();
+  hipLaunchKernelGGL(ritz_reduce_kernel, dim3((unsigned)ceil_div(k, 128)),
+                     dim3(128), 0, st, nblk, k, partial, S, out);
+  MC_CHECK_LAUNCH();
+}
+
+}  // namespace mcsvt

@@ -1,0 +1,127 @@
+// Internal declarations: device layouts and kernel launchers.
+#pragma once
+
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+
+namespace mcsvt {
+
+// Work schedule of a CSR-like structure for the segmented SpMM:
+// segs[w] = (row, begin, end, slot) with slot = -1 for whole rows, and
+// fix[f] = (row, first_slot, count, 0) for rows split into several segments.
+struct Schedule {
+  int64_t nseg = 0, nfix = 0, nslot = 0;
+  DevBuf<int4> segs;
+  DevBuf<int4> fix;
+};
+
+// Canonical layout of the sampled set Phi.
+struct Layout {
+  int64_t m = 0, n = 0, nnz = 0;
+  DevBuf<int32_t> row_ptr;   // m + 1
+  DevBuf<int32_t> col_idx;   // nnz, CSR order
+  DevBuf<int32_t> row_of;    // nnz, row of each CSR entry
+  DevBuf<int32_t> order;     // nnz, CSR position -> input position
+  DevBuf<int32_t> col_ptr;   // n + 1
+  DevBuf<int32_t> row_idx;   // nnz, CSC order
+  DevBuf<int32_t> perm;      // nnz, CSC position -> CSR position
+  DevBuf<int32_t> invperm;   // nnz, CSR position -> CSC position
+  Schedule sched_csr, sched_csc;
+};
+
+int build_layout(int64_t m, int64_t n, int64_t nnz, const int64_t* d_rows,
+                 const int32_t* d_cols, const double* d_vals, Layout& L,
+                 hipStream_t st);
+void build_schedule(const int32_t* host_ptr, int64_t rows, Schedule& S,
+                    hipStream_t st);
+
+template <class S, class D>
+void launch_cast(int64_t n, const S* src, D* dst, hipStream_t st);
+template <class T>
+void launch_gather(int64_t nnz, const int32_t* idx, const T* src, T* dst,
+                   hipStream_t st);
+template <class T>
+void launch_scatter(int64_t nnz, const int32_t* idx, const T* src, T* dst,
+                    hipStream_t st);
+
+template <class T>
+void launch_gaussian(T* out, int64_t rows, int64_t cols, int64_t ld,
+                     uint64_t seed, uint32_t step, uint32_t attempt,
+                     hipStream_t st);
+
+// out (rows x b, ldo) = A X ; A given by schedule + idx + val; part is the
+// partial-row buffer (nslot * b elements).
+template <class VT, class XT, class AT, class OT>
+void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
+                 const XT* X, int64_t ldx, OT* out, int64_t ldo, int b,
+                 AT* part, hipStream_t st);
+
+int64_t sddmm_partials(int64_t nnz);
+template <class FT>
+void launch_sddmm_update(const Layout& L, const double* mvals, double* y,
+                         double* ycsc, const FT* U, int64_t ldu, const FT* V,
+                         int64_t ldv, const double* sig, int r, double delta,
+                         int apply, double* partial, double* out_sum,
+                         hipStream_t st);
+template <class FT>
+void launch_eval_observed(const Layout& L, const FT* U, int64_t ldu,
+                          const FT* V, int64_t ldv, const double* sig, int r,
+                          double* out_input_order, hipStream_t st);
+void launch_sumsq(int64_t n, const double* a, double* partial, double* out,
+                  hipStream_t st);
+void launch_scale(int64_t n, const double* a, double alpha, double* out,
+                  hipStream_t st);
+
+// C (p x q, FP64) = A^T B with A (N x p), B (N x q); sym: A == B, p == q.
+int64_t gram_splits(int64_t N, int p, int q, int sym);
+// gate: optional device flag; when it reads 0 the kernels do nothing.
+template <class IT, class AT>
+void launch_gram(int64_t N, int p, int q, const IT* A, int64_t lda, const IT* B,
+                 int64_t ldb, double* C, int64_t ldc, int sym, AT* part,
+                 int64_t part_cap, hipStream_t st, const int* gate = nullptr);
+
+// C = beta C0 + alpha X W diag(colscale)   (colscale may be null)
+template <class XT, class OT>
+void launch_panel_gemm(int64_t N, int p, int q, const XT* X, int64_t ldx,
+                       const double* W, int64_t ldw, double alpha,
+                       const double* colscale, double beta, const OT* C0,
+                       int64_t ldc0, OT* C, int64_t ldc, hipStream_t st,
+                       const int* gate = nullptr);
+
+constexpr int kCholLdsMax = 90;   // b*b doubles in LDS up to this size
+// flag (optional) is set to 1 when a diagonal shift was needed
+void launch_chol_inv(int b, const double* G, int64_t ldg, double* Rinv,
+                     int64_t ldr, double* work, int64_t nrows, int* shifted,
+                     hipStream_t st, int* flag = nullptr,
+                     const int* gate = nullptr);
+void launch_set_int(int* p, int v, hipStream_t st);
+void launch_copy_gated(int64_t rows, int cols, const double* src, int64_t lds_,
+                       double* dst, int64_t ldd, const int* gate, hipStream_t st);
+
+void launch_recip(int k, const double* S, double* out, hipStream_t st);
+// out[j] = ||R_j - S_j U_j|| / S_j  (Ritz residual ratios, k columns)
+int ritz_blocks(int64_t m);
+void launch_ritz(int64_t m, int k, const double* R, int64_t ldr, const double* U,
+                 int64_t ldu, const double* S, double* partial, double* out,
+                 hipStream_t st);
+
+// Block-Jacobi symmetric eigensolver (FP64).
+struct EigSolver {
+  static constexpr int kMaxSweeps = 30;
+  DevBuf<double> A, V, J, Sd, scal;
+  DevBuf<int> flags;
+  int* hflags = nullptr;
+  int L = 0, Lp = 0, sweeps = 0;
+  ~EigSolver();
+  void reserve(int L, hipStream_t st);
+  // eigen-decompose the symmetric L x L matrix G (row-major, ldg)
+  int solve(int L, const double* G, int64_t ldg, hipStream_t st);
+  // top-k (descending): S = sqrt(max(lambda, 0)), Wk (L x k, ldw) vectors,
+  // D (optional, L) all eigenvalues descending
+  void select_topk(int k, double* S, double* D, double* Wk, int64_t ldw,
+                   hipStream_t st);
+};
+
+}  // namespace mcsvt

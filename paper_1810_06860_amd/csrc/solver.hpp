@@ -1,0 +1,114 @@
+// Host-side state machine of fast SVT (Alg. 6) over the device kernels.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "mcsvt.h"
+
+namespace mcsvt {
+
+struct StepInfo {
+  int i = 0, r = 0, k = 0, p = 0, fresh = 0, recycled = 0, rejected = 0;
+  int converged = 0;
+  double res = 0.0, sigma_max = 0.0;
+};
+
+class Solver {
+ public:
+  Solver(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& prm,
+         hipStream_t st);
+  ~Solver();
+
+  // Phi and M_Phi from host arrays (COO rows, int32 cols).  Returns a status.
+  int init(const int64_t* rows, const int32_t* cols, const double* vals,
+           bool scale_for_svt);
+  StepInfo step();
+  // truncated SVD of the current operator: one rSVD-BKI call (Alg. 5)
+  void rsvd(int k, int p, uint32_t step_id, uint32_t attempt);
+
+  // results
+  void get_factors(double* U, double* sig, double* V, int64_t ldu, int64_t ldv);
+  void get_rsvd(double* U, double* S, double* V);
+  void get_observed(double* x_phi);
+  void get_y(double* y_host);
+
+  const mc_svt_params& params() const { return prm_; }
+  int64_t m() const { return m_; }
+  int64_t n() const { return n_; }
+  int64_t nnz() const { return nnz_; }
+  int rank() const { return r_; }
+  int iters() const { return i_; }
+  bool converged() const { return converged_; }
+  double c() const { return c_; }
+  double norm2() const { return norm2_; }
+  double mnorm() const { return mnorm_; }
+  double last_res() const { return err_hist_.empty() ? 1.0 : err_hist_.back(); }
+  int fresh_total() const { return fresh_total_; }
+  int recycled_total() const { return recycled_total_; }
+  int rejected_total() const { return rejected_total_; }
+  const std::vector<double>& last_sigma() const { return lastS_; }
+  hipStream_t stream() const { return st_; }
+  int eig_sweeps() const { return eig_.sweeps; }
+  int chol_shifts();
+
+  std::string last_error;
+
+ private:
+  // workspace sizing
+  void ensure(int bmax, int Lmax, int kmax);
+  int kcap() const { return kcap_; }
+  void widths(int k, int p, int& b, int& p_eff) const;
+
+  void fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt);
+  void recycled_svd(int k);
+  // eigSVD of B^T = Y^T basis (basis: m x w, leading dim ldb), keep top k;
+  // U = basis Wk, V = B^T Wk S^-1, S on the device and in lastS_.
+  void eigsvd_from_basis(const double* basis, int64_t ldb, int w, int k);
+  double ritz_ratio(int k);
+  void orth_block(int j, int b, int Lw);
+  void cholqr_pass(const double* Hin, int64_t ldin, double* out, int64_t ldo,
+                   int b, const int* gate);
+  void project(const double* Hin, int64_t ldin, double* Hout, int jb, int b,
+               int Lw, const int* gate);
+  void spmm_y(const double* X, int64_t ldx, double* out, int64_t ldo, int b);
+  void spmm_yt(const double* X, int64_t ldx, double* out, int64_t ldo, int b);
+  void read_sigma(int k);
+
+  int64_t m_, n_, nnz_;
+  mc_svt_params prm_;
+  hipStream_t st_;
+  int kcap_ = 1;
+
+  Layout L_;
+  DevBuf<double> mvals_, y_, ycsc_;
+  // workspace
+  int cap_b_ = 0, cap_L_ = 0, cap_k_ = 0;
+  DevBuf<double> omega_, Qw_, basis_, H1_, H2_, Z_, Bt_, G_, Cg_, Rinv_,
+      chol_work_, gram_part_, spmm_part_, U_, V_, S_, Sinv_, D_, Wk_, sig_,
+      sdd_part_, scal_, ritz_part_, ritz_out_, obs_;
+  DevBuf<int> shift_count_, blk_flag_;
+  int64_t gram_cap_ = 0;
+  EigSolver eig_;
+  double* hbuf_ = nullptr;       // pinned host scratch
+  size_t hbuf_n_ = 0;
+
+  // Alg. 6 state
+  int i_ = 0, r_ = 0, q_ = 0, p_ = 3, streak_ = 0;
+  int basis_cols_ = 0;
+  int64_t basis_ld_ = 0;
+  int k_last_ = 0;              // columns of U_, V_, S_ (last SVD)
+  std::vector<double> err_hist_;
+  std::vector<double> lastS_;
+  std::vector<double> sig_host_;
+  bool converged_ = false;
+  double c_ = 0.0, norm2_ = 0.0, mnorm_ = 0.0;
+  int fresh_total_ = 0, recycled_total_ = 0, rejected_total_ = 0;
+};
+
+void resolve_params(int64_t m, int64_t n, int64_t nnz, mc_svt_params& p);
+size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz,
+                       const mc_svt_params& p);
+
+}  // namespace mcsvt

@@ -1,0 +1,578 @@
+// Sparse kernels of the SVT step.
+//
+// * Layout of Phi (Sec. II.C): the iterate Y lives on the sampled set, so
+//   its CSR (row-major) and CSC (column-major) structures are built once on
+//   the device, canonical (entries sorted by (row, col) / (col, row)).
+// * SpMM  out = A X  for the Krylov products A Omega, A (A^T H) and
+//   B^T = A^T Q of rSVD-BKI (Alg. 5 steps 2, 4, 8), with A the CSR of Y or
+//   the CSC of Y (= CSR of Y^T).  One wavefront per row segment; lanes span
+//   the panel columns; long rows are split into segments whose partial rows
+//   are summed in a fixed order by a second kernel, so results are
+//   deterministic.
+// * Fused SDDMM + residual + update (Alg. 6 steps 15-17): for every
+//   (i, j) in Phi, x = sum_t U_it sig_t V_jt, e = M_ij - x, Y_ij += delta e,
+//   and the squares e^2 are summed per block for the stop test.
+#include <hipcub/hipcub.hpp>
+
+#include "kernels.hpp"
+
+namespace mcsvt {
+
+namespace {
+
+constexpr int kErrRange = 1;
+constexpr int kErrNonFinite = 2;
+constexpr int kErrDup = 4;
+
+__global__ void coo_keys_kernel(int64_t nnz, int64_t m, int64_t n,
+                                const int64_t* __restrict__ rows,
+                                const int32_t* __restrict__ cols,
+                                const double* __restrict__ vals,
+                                uint64_t* __restrict__ keys,
+                                int32_t* __restrict__ iota,
+                                int* __restrict__ err) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = rows[e];
+    const int64_t c = cols[e];
+    int bad = 0;
+    if (r < 0 || r >= m || c < 0 || c >= n) bad |= kErrRange;
+    if (vals && !isfinite(vals[e])) bad |= kErrNonFinite;
+    if (bad) atomicOr(err, bad);
+    keys[e] = bad ? 0ull : (uint64_t)r * (uint64_t)n + (uint64_t)c;
+    iota[e] = (int32_t)e;
+  }
+}
+
+// sorted (row, col) keys -> row_of, col_idx, order; duplicate detection
+__global__ void csr_split_kernel(int64_t nnz, int64_t n,
+                                 const uint64_t* __restrict__ keys,
+                                 const int32_t* __restrict__ src,
+                                 int32_t* __restrict__ row_of,
+                                 int32_t* __restrict__ col_idx,
+                                 int32_t* __restrict__ order,
+                                 int* __restrict__ err) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[e];
+    row_of[e] = (int32_t)(k / (uint64_t)n);
+    col_idx[e] = (int32_t)(k % (uint64_t)n);
+    order[e] = src[e];
+    if (e > 0 && keys[e - 1] == k) atomicOr(err, kErrDup);
+  }
+}
+
+// ptr[i] = first position whose group id is >= i (lower bound), i in [0, g]
+__global__ void group_ptr_kernel(int64_t nnz, int64_t groups,
+                                 const int32_t* __restrict__ gid,
+                                 int32_t* __restrict__ ptr) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= groups;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = nnz;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (gid[mid] < i) lo = mid + 1; else hi = mid;
+    }
+    ptr[i] = (int32_t)lo;
+  }
+}
+
+__global__ void csc_keys_kernel(int64_t nnz, int64_t m,
+                                const int32_t* __restrict__ row_of,
+                                const int32_t* __restrict__ col_idx,
+                                uint64_t* __restrict__ keys,
+                                int32_t* __restrict__ iota) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    keys[e] = (uint64_t)col_idx[e] * (uint64_t)m + (uint64_t)row_of[e];
+    iota[e] = (int32_t)e;
+  }
+}
+
+__global__ void csc_split_kernel(int64_t nnz, int64_t m,
+                                 const uint64_t* __restrict__ keys,
+                                 const int32_t* __restrict__ src,
+                                 int32_t* __restrict__ row_idx,
+                                 int32_t* __restrict__ col_of,
+                                 int32_t* __restrict__ perm,
+                                 int32_t* __restrict__ invperm) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t k = keys[e];
+    row_idx[e] = (int32_t)(k % (uint64_t)m);
+    col_of[e] = (int32_t)(k / (uint64_t)m);
+    const int32_t s = src[e];
+    perm[e] = s;
+    invperm[s] = (int32_t)e;
+  }
+}
+
+template <class T>
+__global__ void gather_kernel(int64_t nnz, const int32_t* __restrict__ idx,
+                              const T* __restrict__ src, T* __restrict__ dst) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = src[idx[e]];
+}
+
+template <class T>
+__global__ void scatter_kernel(int64_t nnz, const int32_t* __restrict__ idx,
+                               const T* __restrict__ src, T* __restrict__ dst) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[idx[e]] = src[e];
+}
+
+inline unsigned grid_for(int64_t n, int threads) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, threads),
+                                                          kMaxGrid));
+}
+
+int bits_for(uint64_t maxval) {
+  int b = 1;
+  while (b < 64 && (maxval >> b) != 0) ++b;
+  return b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Canonical CSR / CSC build of Phi.
+// ---------------------------------------------------------------------------
+int build_layout(int64_t m, int64_t n, int64_t nnz, const int64_t* d_rows,
+                 const int32_t* d_cols, const double* d_vals, Layout& L,
+                 hipStream_t st) {
+  L.m = m;
+  L.n = n;
+  L.nnz = nnz;
+  DevBuf<uint64_t> keys_a, keys_b;
+  DevBuf<int32_t> idx_a, idx_b, col_of;
+  DevBuf<int> err;
+  keys_a.reserve(nnz, st);
+  keys_b.reserve(nnz, st);
+  idx_a.reserve(nnz, st);
+  idx_b.reserve(nnz, st);
+  err.reserve(1, st);
+  MC_HIP(hipMemsetAsync(err.p, 0, sizeof(int), st));
+  const int T = 256;
+  hipLaunchKernelGGL(coo_keys_kernel, dim3(grid_for(nnz, T)), dim3(T), 0, st,
+                     nnz, m, n, d_rows, d_cols, d_vals, keys_a.p, idx_a.p,
+                     err.p);
+  MC_CHECK_LAUNCH();
+  int herr = 0;
+  MC_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  MC_HIP(hipStreamSynchronize(st));
+  if (herr & kErrRange) return kERANGE;
+  if (herr & kErrNonFinite) return kEINVAL;
+
+  const int end_bit = bits_for((uint64_t)m * (uint64_t)n - 1);
+  size_t tmp_bytes = 0;
+  MC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys_a.p,
+                                            keys_b.p, idx_a.p, idx_b.p,
+                                            (int)nnz, 0, end_bit, st));
+  DevBuf<char> tmp;
+  tmp.reserve(tmp_bytes, st);
+  MC_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp_bytes, keys_a.p,
+                                            keys_b.p, idx_a.p, idx_b.p,
+                                            (int)nnz, 0, end_bit, st));
+  L.row_of.reserve(nnz, st);
+  L.col_idx.reserve(nnz, st);
+  L.order.reserve(nnz, st);
+  hipLaunchKernelGGL(csr_split_kernel, dim3(grid_for(nnz, T)), dim3(T), 0, st,
+                     nnz, n, keys_b.p, idx_b.p, L.row_of.p, L.col_idx.p,
+                     L.order.p, err.p);
+  MC_CHECK_LAUNCH();
+  MC_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  MC_HIP(hipStreamSynchronize(st));
+  if (herr & kErrDup) return kEDUP;
+  L.row_ptr.reserve(m + 1, st);
+  hipLaunchKernelGGL(group_ptr_kernel, dim3(grid_for(m + 1, T)), dim3(T), 0, st,
+                     nnz, m, L.row_of.p, L.row_ptr.p);
+  MC_CHECK_LAUNCH();
+
+  // CSC: sort the CSR positions by (col, row)
+  hipLaunchKernelGGL(csc_keys_kernel, dim3(grid_for(nnz, T)), dim3(T), 0, st,
+                     nnz, m, L.row_of.p, L.col_idx.p, keys_a.p, idx_a.p);
+  MC_CHECK_LAUNCH();
+  const int end_bit2 = bits_for((uint64_t)n * (uint64_t)m - 1);
+  size_t tmp2 = 0;
+  MC_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp2, keys_a.p, keys_b.p,
+                                            idx_a.p, idx_b.p, (int)nnz, 0,
+                                            end_bit2, st));
+  tmp.reserve(tmp2, st);
+  MC_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.p, tmp2, keys_a.p, keys_b.p,
+                                            idx_a.p, idx_b.p, (int)nnz, 0,
+                                            end_bit2, st));
+  L.row_idx.reserve(nnz, st);
+  L.perm.reserve(nnz, st);
+  L.invperm.reserve(nnz, st);
+  col_of.reserve(nnz, st);
+  hipLaunchKernelGGL(csc_split_kernel, dim3(grid_for(nnz, T)), dim3(T), 0, st,
+                     nnz, m, keys_b.p, idx_b.p, L.row_idx.p, col_of.p, L.perm.p,
+                     L.invperm.p);
+  MC_CHECK_LAUNCH();
+  L.col_ptr.reserve(n + 1, st);
+  hipLaunchKernelGGL(group_ptr_kernel, dim3(grid_for(n + 1, T)), dim3(T), 0, st,
+                     nnz, n, col_of.p, L.col_ptr.p);
+  MC_CHECK_LAUNCH();
+
+  // host copies of the pointers -> SpMM segment schedules
+  std::vector<int32_t> hptr(std::max(m, n) + 1);
+  MC_HIP(hipMemcpyAsync(hptr.data(), L.row_ptr.p, (m + 1) * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, st));
+  MC_HIP(hipStreamSynchronize(st));
+  build_schedule(hptr.data(), m, L.sched_csr, st);
+  MC_HIP(hipMemcpyAsync(hptr.data(), L.col_ptr.p, (n + 1) * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, st));
+  MC_HIP(hipStreamSynchronize(st));
+  build_schedule(hptr.data(), n, L.sched_csc, st);
+  MC_HIP(hipStreamSynchronize(st));
+  return kOK;
+}
+
+// Split rows into work segments of at most `cap` entries.  Rows that need
+// several segments get partial slots and a fix-up record.
+void build_schedule(const int32_t* ptr, int64_t rows, Schedule& S,
+                    hipStream_t st) {
+  const int64_t nnz = ptr[rows];
+  const int64_t avg = rows ? ceil_div(nnz, rows) : 0;
+  const int64_t cap = std::max<int64_t>(1024, 8 * avg);
+  std::vector<int4> segs;
+  std::vector<int4> fix;
+  segs.reserve(rows + 16);
+  int32_t slot = 0;
+  for (int64_t i = 0; i < rows; ++i) {
+    const int32_t b = ptr[i], e = ptr[i + 1];
+    const int64_t len = e - b;
+    if (len <= cap) {
+      segs.push_back(make_int4((int)i, b, e, -1));
+      continue;
+    }
+    const int64_t pieces = ceil_div(len, cap);
+    fix.push_back(make_int4((int)i, slot, (int)pieces, 0));
+    for (int64_t q = 0; q < pieces; ++q) {
+      const int32_t sb = b + (int32_t)(q * len / pieces);
+      const int32_t se = b + (int32_t)((q + 1) * len / pieces);
+      segs.push_back(make_int4((int)i, sb, se, slot++));
+    }
+  }
+  S.nseg = (int64_t)segs.size();
+  S.nfix = (int64_t)fix.size();
+  S.nslot = slot;
+  S.segs.reserve(std::max<int64_t>(S.nseg, 1), st);
+  S.fix.reserve(std::max<int64_t>(S.nfix, 1), st);
+  if (S.nseg)
+    MC_HIP(hipMemcpyAsync(S.segs.p, segs.data(), S.nseg * sizeof(int4),
+                          hipMemcpyHostToDevice, st));
+  if (S.nfix)
+    MC_HIP(hipMemcpyAsync(S.fix.p, fix.data(), S.nfix * sizeof(int4),
+                          hipMemcpyHostToDevice, st));
+  MC_HIP(hipStreamSynchronize(st));
+}
+
+namespace {
+template <class S, class D>
+__global__ void cast_kernel(int64_t n, const S* __restrict__ src, D* __restrict__ dst) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (D)src[e];
+}
+}  // namespace
+
+template <class S, class D>
+void launch_cast(int64_t n, const S* src, D* dst, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((cast_kernel<S, D>), dim3(grid_for(n, 256)), dim3(256), 0, st,
+                     n, src, dst);
+  MC_CHECK_LAUNCH();
+}
+template void launch_cast<double, float>(int64_t, const double*, float*, hipStream_t);
+template void launch_cast<float, double>(int64_t, const float*, double*, hipStream_t);
+
+template <class T>
+void launch_gather(int64_t nnz, const int32_t* idx, const T* src, T* dst,
+                   hipStream_t st) {
+  if (nnz <= 0) return;
+  hipLaunchKernelGGL(gather_kernel<T>, dim3(grid_for(nnz, 256)), dim3(256), 0,
+                     st, nnz, idx, src, dst);
+  MC_CHECK_LAUNCH();
+}
+template <class T>
+void launch_scatter(int64_t nnz, const int32_t* idx, const T* src, T* dst,
+                    hipStream_t st) {
+  if (nnz <= 0) return;
+  hipLaunchKernelGGL(scatter_kernel<T>, dim3(grid_for(nnz, 256)), dim3(256), 0,
+                     st, nnz, idx, src, dst);
+  MC_CHECK_LAUNCH();
+}
+template void launch_gather<double>(int64_t, const int32_t*, const double*,
+                                    double*, hipStream_t);
+template void launch_gather<float>(int64_t, const int32_t*, const float*,
+                                   float*, hipStream_t);
+template void launch_gather<int32_t>(int64_t, const int32_t*, const int32_t*,
+                                     int32_t*, hipStream_t);
+template void launch_scatter<double>(int64_t, const int32_t*, const double*,
+                                     double*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// SpMM  out (rows x b) = A (rows x cols, segments) . X (cols x b)
+// ---------------------------------------------------------------------------
+namespace {
+
+template <class VT, class XT, class AT, class OT, int BW>
+__global__ __launch_bounds__(256) void spmm_kernel(
+    int64_t nseg, const int4* __restrict__ segs,
+    const int32_t* __restrict__ idx, const VT* __restrict__ val,
+    const XT* __restrict__ X, int64_t ldx, OT* __restrict__ out, int64_t ldo,
+    AT* __restrict__ part, int b) {
+  constexpr int G = 64 / BW;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (wave >= nseg) return;
+  const int4 sg = segs[wave];
+  const int g = lane / BW;
+  const int c = lane % BW;
+  for (int c0 = 0; c0 < b; c0 += BW) {
+    const int col = c0 + c;
+    const bool active = col < b;
+    AT acc = 0;
+    for (int base = sg.y; base < sg.z; base += 64) {
+      const int e = base + lane;
+      const bool ok = e < sg.z;
+      const int my_idx = ok ? idx[e] : 0;
+      const AT my_val = ok ? (AT)val[e] : (AT)0;
+      const int cnt = min(64, sg.z - base);
+      for (int jj = 0; jj < cnt; jj += G) {
+        const int j = jj + g;
+        const int jc = __shfl(my_idx, j);
+        const AT jv = __shfl(my_val, j);
+        if (active && j < cnt) acc += jv * (AT)X[(int64_t)jc * ldx + col];
+      }
+    }
+#pragma unroll
+    for (int off = BW; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
+    if (g == 0 && active) {
+      if (sg.w < 0)
+        out[(int64_t)sg.x * ldo + col] = (OT)acc;
+      else
+        part[(int64_t)sg.w * b + col] = acc;
+    }
+  }
+}
+
+template <class AT, class OT>
+__global__ void spmm_fixup_kernel(int64_t nfix, const int4* __restrict__ fix,
+                                  const AT* __restrict__ part, OT* __restrict__ out,
+                                  int64_t ldo, int b) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nfix * b) return;
+  const int64_t f = t / b;
+  const int col = (int)(t % b);
+  const int4 fx = fix[f];
+  AT acc = 0;
+  for (int q = 0; q < fx.z; ++q) acc += part[(int64_t)(fx.y + q) * b + col];
+  out[(int64_t)fx.x * ldo + col] = (OT)acc;
+}
+
+}  // namespace
+
+template <class VT, class XT, class AT, class OT>
+void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
+                 const XT* X, int64_t ldx, OT* out, int64_t ldo, int b,
+                 AT* part, hipStream_t st) {
+  if (S.nseg == 0 || b <= 0) return;
+  const int T = 256;
+  const unsigned grid = (unsigned)ceil_div(S.nseg, T / 64);
+  if (b <= 8)
+    hipLaunchKernelGGL((spmm_kernel<VT, XT, AT, OT, 8>), dim3(grid), dim3(T), 0,
+                       st, S.nseg, S.segs.p, idx, val, X, ldx, out, ldo, part, b);
+  else if (b <= 16)
+    hipLaunchKernelGGL((spmm_kernel<VT, XT, AT, OT, 16>), dim3(grid), dim3(T), 0,
+                       st, S.nseg, S.segs.p, idx, val, X, ldx, out, ldo, part, b);
+  else if (b <= 32)
+    hipLaunchKernelGGL((spmm_kernel<VT, XT, AT, OT, 32>), dim3(grid), dim3(T), 0,
+                       st, S.nseg, S.segs.p, idx, val, X, ldx, out, ldo, part, b);
+  else
+    hipLaunchKernelGGL((spmm_kernel<VT, XT, AT, OT, 64>), dim3(grid), dim3(T), 0,
+                       st, S.nseg, S.segs.p, idx, val, X, ldx, out, ldo, part, b);
+  MC_CHECK_LAUNCH();
+  if (S.nfix) {
+    const int64_t work = S.nfix * b;
+    hipLaunchKernelGGL((spmm_fixup_kernel<AT, OT>), dim3((unsigned)ceil_div(work, T)),
+                       dim3(T), 0, st, S.nfix, S.fix.p, part, out, ldo, b);
+    MC_CHECK_LAUNCH();
+  }
+}
+
+template void launch_spmm<double, double, double, double>(
+    const Schedule&, const int32_t*, const double*, const double*, int64_t,
+    double*, int64_t, int, double*, hipStream_t);
+template void launch_spmm<float, float, float, float>(
+    const Schedule&, const int32_t*, const float*, const float*, int64_t,
+    float*, int64_t, int, float*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Fused SDDMM + residual + update.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kSddmmThreads = 256;
+constexpr int kMaxRankLds = 2048;
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+template <class FT>
+__global__ __launch_bounds__(kSddmmThreads) void sddmm_update_kernel(
+    int64_t nnz, const int32_t* __restrict__ row_of,
+    const int32_t* __restrict__ col_idx, const double* __restrict__ mvals,
+    double* __restrict__ y, double* __restrict__ ycsc,
+    const int32_t* __restrict__ invperm, const FT* __restrict__ U, int64_t ldu,
+    const FT* __restrict__ V, int64_t ldv, const double* __restrict__ sig,
+    int r, double delta, int apply, double* __restrict__ partial) {
+  __shared__ double ssig[kMaxRankLds];
+  __shared__ double sh[kSddmmThreads];
+  for (int t = threadIdx.x; t < r; t += blockDim.x) ssig[t] = sig[t];
+  __syncthreads();
+  const int64_t e = blockIdx.x * (int64_t)kSddmmThreads + threadIdx.x;
+  double d2 = 0.0;
+  if (e < nnz) {
+    const FT* u = U + (int64_t)row_of[e] * ldu;
+    const FT* v = V + (int64_t)col_idx[e] * ldv;
+    double x = 0.0;
+    for (int t = 0; t < r; ++t) x += ((double)u[t] * ssig[t]) * (double)v[t];
+    const double d = mvals[e] - x;
+    d2 = d * d;
+    if (apply) {
+      const double yn = y[e] + delta * d;
+      y[e] = yn;
+      ycsc[invperm[e]] = yn;
+    }
+  }
+  const double s = block_sum<kSddmmThreads>(d2, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+template <class FT>
+__global__ void eval_observed_kernel(int64_t nnz, const int32_t* __restrict__ row_of,
+                                     const int32_t* __restrict__ col_idx,
+                                     const FT* __restrict__ U, int64_t ldu,
+                                     const FT* __restrict__ V, int64_t ldv,
+                                     const double* __restrict__ sig, int r,
+                                     const int32_t* __restrict__ order,
+                                     double* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const FT* u = U + (int64_t)row_of[e] * ldu;
+    const FT* v = V + (int64_t)col_idx[e] * ldv;
+    double x = 0.0;
+    for (int t = 0; t < r; ++t) x += ((double)u[t] * sig[t]) * (double)v[t];
+    out[order[e]] = x;
+  }
+}
+
+__global__ void sumsq_kernel(int64_t n, const double* __restrict__ a,
+                             double* __restrict__ partial) {
+  __shared__ double sh[256];
+  const int64_t e = blockIdx.x * 256ll + threadIdx.x;
+  const double v = e < n ? a[e] : 0.0;
+  const double s = block_sum<256>(v * v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// single block: out[0] = sum of partial[0..n) in a fixed order
+__global__ void reduce_kernel(int64_t n, const double* __restrict__ partial,
+                              double* __restrict__ out) {
+  __shared__ double sh[1024];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) acc += partial[i];
+  const double s = block_sum<1024>(acc, sh);
+  if (threadIdx.x == 0) out[0] = s;
+}
+
+__global__ void scale_kernel(int64_t n, const double* __restrict__ a,
+                             double alpha, double* __restrict__ out) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    out[e] = alpha * a[e];
+}
+
+}  // namespace
+
+int64_t sddmm_partials(int64_t nnz) { return ceil_div(nnz, kSddmmThreads); }
+
+template <class FT>
+void launch_sddmm_update(const Layout& L, const double* mvals, double* y,
+                         double* ycsc, const FT* U, int64_t ldu, const FT* V,
+                         int64_t ldv, const double* sig, int r, double delta,
+                         int apply, double* partial, double* out_sum,
+                         hipStream_t st) {
+  MC_REQUIRE(r <= kMaxRankLds, kEINVAL, "rank exceeds the SDDMM limit");
+  const int64_t nb = sddmm_partials(L.nnz);
+  hipLaunchKernelGGL(sddmm_update_kernel<FT>, dim3((unsigned)nb),
+                     dim3(kSddmmThreads), 0, st, L.nnz, L.row_of.p,
+                     L.col_idx.p, mvals, y, ycsc, L.invperm.p, U, ldu, V, ldv,
+                     sig, r, delta, apply, partial);
+  MC_CHECK_LAUNCH();
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, nb, partial,
+                     out_sum);
+  MC_CHECK_LAUNCH();
+}
+template void launch_sddmm_update<double>(const Layout&, const double*, double*,
+                                          double*, const double*, int64_t,
+                                          const double*, int64_t, const double*,
+                                          int, double, int, double*, double*,
+                                          hipStream_t);
+template void launch_sddmm_update<float>(const Layout&, const double*, double*,
+                                         double*, const float*, int64_t,
+                                         const float*, int64_t, const double*,
+                                         int, double, int, double*, double*,
+                                         hipStream_t);
+
+template <class FT>
+void launch_eval_observed(const Layout& L, const FT* U, int64_t ldu,
+                          const FT* V, int64_t ldv, const double* sig, int r,
+                          double* out_input_order, hipStream_t st) {
+  hipLaunchKernelGGL(eval_observed_kernel<FT>, dim3(grid_for(L.nnz, 256)),
+                     dim3(256), 0, st, L.nnz, L.row_of.p, L.col_idx.p, U, ldu,
+                     V, ldv, sig, r, L.order.p, out_input_order);
+  MC_CHECK_LAUNCH();
+}
+template void launch_eval_observed<double>(const Layout&, const double*,
+                                           int64_t, const double*, int64_t,
+                                           const double*, int, double*,
+                                           hipStream_t);
+template void launch_eval_observed<float>(const Layout&, const float*, int64_t,
+                                          const float*, int64_t, const double*,
+                                          int, double*, hipStream_t);
+
+void launch_sumsq(int64_t n, const double* a, double* partial, double* out,
+                  hipStream_t st) {
+  const int64_t nb = ceil_div(n, 256);
+  hipLaunchKernelGGL(sumsq_kernel, dim3((unsigned)nb), dim3(256), 0, st, n, a,
+                     partial);
+  MC_CHECK_LAUNCH();
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, nb, partial,
+                     out);
+  MC_CHECK_LAUNCH();
+}
+
+void launch_scale(int64_t n, const double* a, double alpha, double* out,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n, 256)), dim3(256), 0, st, n,
+                     a, alpha, out);
+  MC_CHECK_LAUNCH();
+}
+
+}  // namespace mcsvt

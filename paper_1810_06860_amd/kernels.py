@@ -1,0 +1,109 @@
+"""Python wrappers of the kernel-level entry points (include/mcsvt_kernels.h).
+
+Each call runs one kernel family of the SVT step on the GPU with host arrays
+in and out; used to check and time the building blocks one by one.
+"""
+
+import ctypes as C
+
+import numpy as np
+
+from ._ffi import PRECISIONS, check, lib
+from .svt import current_stream
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def gaussian(rows, cols, seed, step, attempt):
+    out = np.zeros((rows, cols))
+    check(lib().mc_k_gaussian(rows, cols, seed, step, attempt, current_stream(),
+                              _p(out, C.c_double)))
+    return out
+
+
+def layout(m, n, rows, cols):
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    nnz = rows.size
+    out = dict(row_ptr=np.zeros(m + 1, np.int32), col_idx=np.zeros(nnz, np.int32),
+               order=np.zeros(nnz, np.int32), col_ptr=np.zeros(n + 1, np.int32),
+               row_idx=np.zeros(nnz, np.int32), perm=np.zeros(nnz, np.int32))
+    check(lib().mc_k_layout(m, n, nnz, _p(rows, C.c_int64), _p(cols, C.c_int32),
+                            current_stream(),
+                            *[_p(out[k], C.c_int32) for k in
+                              ("row_ptr", "col_idx", "order", "col_ptr",
+                               "row_idx", "perm")]))
+    return out
+
+
+def spmm(m, n, rows, cols, vals, X, transpose=False, precision="fp64"):
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    b = X.shape[1]
+    out = np.zeros((n if transpose else m, b))
+    check(lib().mc_k_spmm(m, n, vals.size, _p(rows, C.c_int64),
+                          _p(cols, C.c_int32), _p(vals, C.c_double),
+                          int(transpose), b, _p(X, C.c_double), _prec(precision),
+                          current_stream(), _p(out, C.c_double)))
+    return out
+
+
+def gram(A, B=None, precision="fp64"):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    sym = B is None
+    Bc = A if sym else np.ascontiguousarray(B, dtype=np.float64)
+    N, p = A.shape
+    q = Bc.shape[1]
+    out = np.zeros((p, q))
+    check(lib().mc_k_gram(N, p, q, _p(A, C.c_double), _p(Bc, C.c_double),
+                          int(sym), _prec(precision), current_stream(),
+                          _p(out, C.c_double)))
+    return out
+
+
+def cholqr2(H):
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    Q = np.zeros_like(H)
+    check(lib().mc_k_cholqr2(H.shape[0], H.shape[1], _p(H, C.c_double),
+                             current_stream(), _p(Q, C.c_double)))
+    return Q
+
+
+def syev(G, k):
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    L = G.shape[0]
+    ev = np.zeros(k)
+    W = np.zeros((L, k))
+    sweeps = C.c_int32()
+    check(lib().mc_k_syev(L, _p(G, C.c_double), k, current_stream(),
+                          _p(ev, C.c_double), _p(W, C.c_double), C.byref(sweeps)))
+    return ev, W, sweeps.value
+
+
+def sddmm(m, n, rows, cols, mvals, y, U, sig, V, delta):
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    mvals = np.ascontiguousarray(mvals, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    r = int(np.size(sig))
+    U = np.ascontiguousarray(U, dtype=np.float64).reshape(m, r)
+    V = np.ascontiguousarray(V, dtype=np.float64).reshape(n, r)
+    sig = np.ascontiguousarray(sig, dtype=np.float64)
+    x = np.zeros(mvals.size)
+    ynew = np.zeros(mvals.size)
+    ss = np.zeros(1)
+    check(lib().mc_k_sddmm(m, n, mvals.size, _p(rows, C.c_int64),
+                           _p(cols, C.c_int32), _p(mvals, C.c_double),
+                           _p(y, C.c_double), r, _p(U, C.c_double),
+                           _p(sig, C.c_double), _p(V, C.c_double), delta,
+                           current_stream(), _p(x, C.c_double),
+                           _p(ynew, C.c_double), _p(ss, C.c_double)))
+    return x, ynew, float(ss[0])

@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+entry point, and rejects bad input before touching the GPU."""
+
+import ctypes as C
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1810_06860_amd", "libmcsvt.so")
+
+
+def declared_functions():
+    names = set()
+    for hdr in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(hdr).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(mc_\w+)\s*\(", text):
+            start = text.rfind("\n", 0, m.start()) + 1
+            line = text[start:m.start()]
+            if "typedef" in line or "(*" in text[m.start() - 2:m.start() + 2]:
+                continue
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail(f"{LIB} not built: run python -m paper_1810_06860_amd.build")
+    from paper_1810_06860_amd import _ffi
+    return _ffi.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_symbol():
+    from paper_1810_06860_amd import _ffi
+    assert declared_functions() <= set(_ffi._SIGNATURES)
+
+
+def test_default_params_and_version(lib):
+    from paper_1810_06860_amd import default_params
+    assert lib.mc_abi_version() == 1
+    p = default_params()
+    assert p["l"] == 5 and p["s"] == 10 and p["p_init"] == 3
+    assert p["q_reuse"] == 10 and p["eps"] == 1e-4 and p["recycle"] == 0
+
+
+def test_footprint_grows_with_size(lib):
+    from paper_1810_06860_amd import footprint
+    a = footprint(500, 500, 50_000)
+    b = footprint(70_000, 10_700, 10_000_000, dict(k_max=100))
+    assert 0 < a < b
+    assert footprint(0, 5, 5) == 0
+
+
+def _init(m, n, rows, cols, vals, params=None):
+    from paper_1810_06860_amd import SVT
+    return SVT(m, n, rows, cols, vals, params)
+
+
+@pytest.mark.parametrize("case", ["nnz0", "m0", "nan", "too_many", "bad_p"])
+def test_init_rejects_bad_input_on_host(lib, case):
+    from paper_1810_06860_amd import MCError
+    from paper_1810_06860_amd._ffi import MC_EDUP, MC_EINVAL
+    rows = np.array([0, 1])
+    cols = np.array([0, 1])
+    vals = np.array([1.0, 2.0])
+    want = MC_EINVAL
+    kw = {}
+    if case == "nnz0":
+        rows, cols, vals = rows[:0], cols[:0], vals[:0]
+        args = (3, 3)
+    elif case == "m0":
+        args = (0, 3)
+    elif case == "nan":
+        vals = np.array([1.0, np.nan])
+        args = (3, 3)
+    elif case == "too_many":
+        rows = np.zeros(5, dtype=np.int64)
+        cols = np.zeros(5, dtype=np.int32)
+        vals = np.ones(5)
+        args = (1, 2)
+        want = MC_EDUP
+    else:
+        # parameters are validated before the first device call
+        args = (3, 3)
+        kw = dict(params=dict(p_min=4, p_init=3, p_max=8))
+    with pytest.raises(MCError) as ei:
+        _init(*args, rows, cols, vals, **kw)
+    assert ei.value.status == want
+    assert lib.mc_svt_last_error(None)
+
+
+def test_rsvd_rejects_oversized_krylov_space(lib):
+    from paper_1810_06860_amd import MCError, rsvd_bki
+    rows = np.arange(10)
+    cols = np.arange(10)
+    with pytest.raises(MCError):
+        rsvd_bki(10, 10, rows, cols, np.ones(10), k=5, s=5, p=1, seed=1)
+
+
+def test_null_handle_calls(lib):
+    from paper_1810_06860_amd._ffi import MC_EINVAL, StepInfo
+    info = StepInfo()
+    assert lib.mc_svt_step(None, C.byref(info)) == MC_EINVAL
+    assert lib.mc_svt_destroy(None) == 0

@@ -1,0 +1,179 @@
+"""GPU parity of each kernel family against the oracle or a plain definition.
+
+Sizes span several tiles and ragged tails; seeds are fixed.
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse
+
+import synth
+from oracle import canonical_csr, gaussian_block
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    from paper_1810_06860_amd import kernels
+    return kernels
+
+
+def _coo(m, n, K_, seed, zipf=False):
+    if zipf:
+        p = synth.ratings(m, n, K_, 3, seed_data=seed)
+        return p.rows, p.cols
+    cells = synth.sample_cells(m, n, K_, seed)
+    return synth.cells_to_coo(cells, n)
+
+
+@pytest.mark.parametrize("rows,cols", [(1, 1), (7, 5), (1000, 21), (333, 111)])
+def test_gaussian_matches_oracle_stream(K, rows, cols):
+    g = K.gaussian(rows, cols, seed=12345, step=3, attempt=1)
+    want = gaussian_block(rows, cols, 12345, 3, 1)
+    # same counter stream; libm differences only in the last bits
+    np.testing.assert_allclose(g, want, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("m,n,K_,zipf", [(40, 30, 200, False), (1, 50, 20, False),
+                                         (60, 1, 10, False), (500, 500, 50000, False),
+                                         (3000, 400, 60000, True)])
+def test_layout_bit_exact(K, m, n, K_, zipf):
+    rows, cols = _coo(m, n, K_, 17, zipf)
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(rows.size)                # arbitrary input order
+    rows, cols = rows[perm], cols[perm]
+    got = K.layout(m, n, rows, cols)
+    want = canonical_csr(m, n, rows, cols)
+    for key in ("row_ptr", "col_idx", "order", "col_ptr", "row_idx", "perm"):
+        assert np.array_equal(got[key], want[key]), key
+
+
+def test_layout_rejects_duplicates_and_range(K):
+    from paper_1810_06860_amd import MCError
+    from paper_1810_06860_amd._ffi import MC_EDUP, MC_ERANGE
+    with pytest.raises(MCError) as e:
+        K.layout(4, 4, np.array([0, 1, 1]), np.array([0, 2, 2]))
+    assert e.value.status == MC_EDUP
+    with pytest.raises(MCError) as e:
+        K.layout(4, 4, np.array([0, 4]), np.array([0, 0]))
+    assert e.value.status == MC_ERANGE
+
+
+@pytest.mark.parametrize("b", [1, 5, 16, 21, 33, 64, 110, 330])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_spmm_fp64(K, b, transpose):
+    m, n = 700, 530
+    rows, cols = _coo(m, n, 25000, 3)
+    rng = np.random.default_rng(b)
+    vals = rng.standard_normal(rows.size)
+    A = scipy.sparse.csr_matrix((vals, (rows, cols)), shape=(m, n))
+    X = rng.standard_normal(((m if transpose else n), b))
+    got = K.spmm(m, n, rows, cols, vals, X, transpose=transpose)
+    want = (A.T @ X) if transpose else (A @ X)
+    scale = (abs(A.T) if transpose else abs(A)) @ np.abs(X) + 1e-300
+    assert np.max(np.abs(got - want) / scale) < 1e-14
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_spmm_long_rows_are_split(K, transpose):
+    # Zipf rows and columns: some exceed the segment cap and go through the
+    # partial-row fix-up path
+    p = synth.ratings(4000, 1500, 300_000, 3, seed_data=8)
+    rng = np.random.default_rng(1)
+    vals = rng.standard_normal(p.nnz)
+    A = scipy.sparse.csr_matrix((vals, (p.rows, p.cols)), shape=(p.m, p.n))
+    b = 40
+    X = rng.standard_normal(((p.m if transpose else p.n), b))
+    got = K.spmm(p.m, p.n, p.rows, p.cols, vals, X, transpose=transpose)
+    want = (A.T @ X) if transpose else (A @ X)
+    scale = (abs(A.T) if transpose else abs(A)) @ np.abs(X) + 1e-300
+    assert np.max(np.abs(got - want) / scale) < 1e-14
+
+
+def test_spmm_fp32_error_bound(K):
+    m, n, b = 600, 450, 24
+    rows, cols = _coo(m, n, 30000, 9)
+    rng = np.random.default_rng(2)
+    vals = rng.standard_normal(rows.size)
+    X = rng.standard_normal((n, b))
+    A = scipy.sparse.csr_matrix((vals, (rows, cols)), shape=(m, n))
+    got = K.spmm(m, n, rows, cols, vals, X, precision="fp32")
+    want = A @ X
+    scale = abs(A) @ np.abs(X)
+    nz = np.diff(A.indptr).max()
+    u = 2.0 ** -24
+    assert np.max(np.abs(got - want) / scale) < (nz + 2) * u * 1.01
+
+
+@pytest.mark.parametrize("N,p,q,sym", [(1000, 21, 21, 1), (5000, 84, 84, 1),
+                                       (777, 63, 21, 0), (33, 5, 7, 0),
+                                       (20000, 330, 330, 1)])
+def test_gram_fp64(K, N, p, q, sym):
+    rng = np.random.default_rng(N + p)
+    A = rng.standard_normal((N, p))
+    B = None if sym else rng.standard_normal((N, q))
+    got = K.gram(A, B)
+    want = A.T @ (A if sym else B)
+    scale = np.abs(A).T @ np.abs(A if sym else B)
+    assert np.max(np.abs(got - want) / scale) < 1e-14
+    if sym:
+        assert np.array_equal(got, got.T)
+
+
+@pytest.mark.parametrize("N,b,kappa", [(2000, 21, 1e2), (5000, 64, 1e5),
+                                       (3000, 110, 1e3), (500, 7, 1e9)])
+def test_cholqr2_orthonormal_same_range(K, N, b, kappa):
+    rng = np.random.default_rng(b)
+    U, _ = np.linalg.qr(rng.standard_normal((N, b)))
+    V, _ = np.linalg.qr(rng.standard_normal((b, b)))
+    H = (U * np.logspace(0, -np.log10(kappa), b)) @ V.T
+    Q = K.cholqr2(H)
+    assert np.linalg.norm(Q.T @ Q - np.eye(b)) < 1e-12
+    Qr, _ = np.linalg.qr(H)
+    assert np.linalg.norm(Q @ (Q.T @ Qr) - Qr) < 1e-8 * max(1.0, kappa * 1e-8)
+
+
+@pytest.mark.parametrize("L,k", [(5, 3), (21, 5), (32, 32), (84, 11), (130, 40),
+                                 (330, 110)])
+def test_syev_matches_eigh(K, L, k):
+    rng = np.random.default_rng(L)
+    A = rng.standard_normal((4 * L, L)) * np.logspace(0, -3, L)
+    G = A.T @ A
+    ev, W, sweeps = K.syev(G, k)
+    want, Vw = np.linalg.eigh(G)
+    want = want[::-1][:k]
+    assert np.allclose(ev, want, rtol=1e-12, atol=1e-14 * want[0])
+    # eigenvectors: G W = W diag(ev), orthonormal columns
+    assert np.linalg.norm(G @ W - W * ev) < 1e-12 * want[0] * np.sqrt(k)
+    # rounding of ~L rotations per vector entry, per sweep
+    assert np.linalg.norm(W.T @ W - np.eye(k)) < 2e-14 * L
+    assert sweeps < 30
+
+
+def test_syev_degenerate_and_diagonal(K):
+    G = np.diag(np.arange(40, 0, -1.0))
+    ev, W, _ = K.syev(G, 10)
+    assert np.array_equal(ev, np.arange(40, 30, -1.0))
+    G2 = np.ones((20, 20))
+    ev2, _, _ = K.syev(G2, 3)
+    assert np.allclose(ev2, [20.0, 0.0, 0.0], atol=1e-12)
+
+
+@pytest.mark.parametrize("r", [0, 1, 10, 37])
+def test_sddmm_brute_force(K, r):
+    m, n = 130, 90
+    rows, cols = _coo(m, n, 3000, 4)
+    rng = np.random.default_rng(r + 1)
+    mv = rng.standard_normal(rows.size)
+    y = rng.standard_normal(rows.size)
+    U = rng.standard_normal((m, r))
+    V = rng.standard_normal((n, r))
+    sig = rng.random(r) + 0.5
+    delta = 1.7
+    x, ynew, ss = K.sddmm(m, n, rows, cols, mv, y, U, sig, V, delta)
+    X = (U * sig) @ V.T
+    want_x = X[rows, cols]
+    np.testing.assert_allclose(x, want_x, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(ynew, y + delta * (mv - want_x), rtol=1e-13, atol=1e-13)
+    assert ss == pytest.approx(np.sum((mv - want_x) ** 2), rel=1e-12)

@@ -1,0 +1,93 @@
+"""GPU parity of rSVD-BKI and of fast-SVT steps against the oracle."""
+
+import numpy as np
+import pytest
+import scipy.sparse
+
+import synth
+from oracle import FastSVT, fast_svt, gaussian_block, rsvd_bki, svt_exact
+
+pytestmark = pytest.mark.gpu
+
+
+def _sparse(p):
+    return scipy.sparse.csr_matrix((p.vals, (p.rows, p.cols)), shape=(p.m, p.n))
+
+
+@pytest.mark.parametrize("m,n,k,s,p", [(500, 500, 11, 10, 3), (700, 300, 5, 10, 2),
+                                       (300, 700, 20, 10, 1), (400, 400, 1, 10, 8)])
+def test_rsvd_bki_matches_oracle_same_omega(m, n, k, s, p):
+    from paper_1810_06860_amd import rsvd_bki as gpu_rsvd
+    prob = synth.planted(m, n, 8, 0.3, seed_data=m + k, seed_phi=n + p)
+    A = _sparse(prob)
+    om = gaussian_block(n, k + s, 77, 5, 2)
+    Uo, So, Vo = rsvd_bki(A, k, p, om)
+    Ug, Sg, Vg = gpu_rsvd(m, n, prob.rows, prob.cols, prob.vals, k, s, p, seed=77,
+                          step=5, attempt=2)
+    So, Uo, Vo = So[::-1], Uo[:, ::-1], Vo[:, ::-1]          # descending
+    np.testing.assert_allclose(Sg, So, rtol=1e-8)
+    Xo = (Uo * So) @ Vo.T
+    Xg = (Ug * Sg) @ Vg.T
+    assert np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo) < 1e-8
+    assert np.linalg.norm(Ug.T @ Ug - np.eye(k)) < 1e-10
+
+
+def test_rsvd_bki_exact_low_rank():
+    from paper_1810_06860_amd import rsvd_bki as gpu_rsvd
+    prob = synth.planted(300, 200, 4, 0.999, seed_data=1, seed_phi=2)
+    A = _sparse(prob).toarray()
+    U, S, V = gpu_rsvd(300, 200, prob.rows, prob.cols, prob.vals, 4, 6, 2, seed=3)
+    Sd = np.linalg.svd(A, compute_uv=False)[:4]
+    np.testing.assert_allclose(S, Sd, rtol=1e-9)
+
+
+def _run_gpu(prob, prm, steps=None):
+    from paper_1810_06860_amd import SVT
+    solver = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    infos = []
+    n = prm["i_max"] if steps is None else steps
+    for _ in range(n):
+        info = solver.step()
+        infos.append(info)
+        if info["converged"]:
+            break
+    return solver, infos
+
+
+def test_svt_steps_match_oracle_planted500():
+    prob, prm = synth.make_problem("planted500")
+    orc = FastSVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    from paper_1810_06860_amd import SVT
+    g = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    res = g.result()
+    assert res["c"] == orc.c
+    assert res["norm2"] == pytest.approx(orc.norm2, rel=1e-10)
+    for _ in range(25):
+        oi = orc.step()
+        gi = g.step()
+        assert (gi["r"], gi["k"], gi["p"], gi["fresh"]) == (oi.r, oi.k, oi.p, oi.fresh)
+        assert gi["res"] == pytest.approx(oi.res, rel=1e-8)
+        np.testing.assert_allclose(g.sigma(), oi.S, rtol=1e-8)
+    U, sig, V = g.factors()
+    np.testing.assert_allclose(sig, orc.sig, rtol=1e-8)
+    Xg = (U * sig) @ V.T
+    Xo = (orc.U * orc.sig) @ orc.V.T
+    assert np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo) < 1e-8
+    np.testing.assert_allclose(g.observed(), orc.x_phi_input_order(), rtol=1e-7,
+                               atol=1e-9 * np.abs(orc.x_phi).max())
+
+
+def test_svt_full_solve_planted500_vs_exact_oracle():
+    prob, prm = synth.make_problem("planted500")
+    from paper_1810_06860_amd import SVT
+    g = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    out = g.solve()
+    assert out["converged"] == 1 and out["rank"] == 10
+    ex = svt_exact(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    U, sig, V = g.factors()
+    Xg = (U * sig) @ V.T
+    rel = np.linalg.norm(Xg - ex.dense()) / np.linalg.norm(ex.dense())
+    assert rel < 1e-3
+    assert abs(out["iters"] - ex.iters) <= 3
+    M = prob.truth_dense()
+    assert np.linalg.norm(Xg - M) / np.linalg.norm(M) < 1e-3
