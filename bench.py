@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Fast-SVT benchmark on one MI355X: SVT steps/s plus the roofline of the
+dominant kernel and the CPU oracle timed beside it.
+
+    python bench.py [--steps K] [--warmup W] [--workload image1024]
+                    [--precision fp64] [--cpu-seconds 30]
+
+A "step" is one iteration of the fast SVT algorithm: the rank search with
+rSVD-BKI (or a recycled basis), shrinkage, the residual on Phi and the update
+of Y.  The solve starts untimed (problem set-up and W warm-up steps), then K
+consecutive steps are timed with the stream synchronised on both sides.  All
+inputs and solver state are resident in HBM for the whole timed region.
+
+Prints one JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("SVT steps/sec + SpMM HBM GB/s at rel.err≤1e-3; "
+          "p50/p99 solve latency")
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 (vector and matrix)
+FP32_PEAK_TFLOPS = 157.3
+
+HBM_FAMILIES = ("spmm_fwd", "spmm_bwd", "sddmm")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=290)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="image1024")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
+    ap.add_argument("--prof-steps", type=int, default=60,
+                    help="steps of the event-profiled pass (per-kernel times)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for "
+                         "calibrating HBM counters under a profiler)")
+    return ap.parse_args()
+
+
+def roofline(prof, prec):
+    fams = {k: v for k, v in prof.items() if v["launches"] > 0 and v["ms"] > 0}
+    if not fams:
+        return None, None
+    dom = max(fams, key=lambda k: fams[k]["ms"])
+    v = fams[dom]
+    per_launch_ms = v["ms"] / v["launches"]
+    if dom in HBM_FAMILIES:
+        achieved = v["bytes"] / v["launches"] / (per_launch_ms * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS,
+                    unit="GB/s")
+    else:
+        peak = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
+        achieved = v["flops"] / v["launches"] / (per_launch_ms * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=round(achieved, 4), peak=peak,
+                    unit="TFLOP/s")
+    roof["frac"] = round(roof["achieved"] / roof["peak"], 5)
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["launches"] = v["launches"]
+    roof["avg_launch_us"] = round(per_launch_ms * 1e3, 3)
+    return dom, roof
+
+
+def family_table(prof, total_s):
+    out = {}
+    for k, v in prof.items():
+        if v["launches"] == 0:
+            continue
+        ms = v["ms"]
+        ent = dict(launches=v["launches"], ms=round(ms, 3),
+                   share=round(ms * 1e-3 / total_s, 4) if total_s > 0 else None)
+        if v["bytes"] and ms > 0:
+            ent["GBps"] = round(v["bytes"] / (ms * 1e-3) / 1e9, 1)
+        if v["flops"] and ms > 0:
+            ent["TFLOPs"] = round(v["flops"] / (ms * 1e-3) / 1e12, 4)
+        out[k] = ent
+    return out
+
+
+def cpu_baseline(prob, prm, budget_s, max_steps):
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    orc = oracle.FastSVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    steps = 0
+    t0 = time.perf_counter()
+    while steps < max_steps and time.perf_counter() - t0 < budget_s:
+        info = orc.step()
+        steps += 1
+        if info.converged:
+            break
+    dt = time.perf_counter() - t0
+    return orc, dict(value=round(steps / dt, 4), unit="steps/s", cores=int(threads),
+                     kind="oracle",
+                     sample=(f"first {steps} fast-SVT steps of the same workload "
+                             f"(NumPy/SciPy FP64, {dt:.1f} s wall)"))
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
+              "by this build (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1810_06860_amd import SVT
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    prob, prm = synth.make_problem(a.workload)
+    prm = dict(prm)
+    prm["precision"] = a.precision
+    prm["i_max"] = max(prm["i_max"], a.warmup + a.steps)
+    solver = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    for _ in range(a.warmup):
+        info = solver.step()
+        if info["converged"]:
+            raise SystemExit("workload converged during warm-up; lower --warmup")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(a.steps):
+        info = solver.step()
+        infos.append(info)
+        if info["converged"]:
+            break
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # Per-kernel durations: the same workload re-run with kernel-by-kernel
+    # launches and HIP events around each launch on the solve's stream.
+    prof_solver = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals,
+                      dict(prm, use_graphs=0))
+    for _ in range(a.warmup):
+        prof_solver.step()
+    prof_solver.profile(True)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    pdone = 0
+    for _ in range(min(a.prof_steps, a.steps)):
+        pinfo = prof_solver.step()
+        pdone += 1
+        if pinfo["converged"]:
+            break
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
+    prof = prof_solver.get_profile()
+    prof_solver.profile(False)
+    prof_solver.close()
+    done = len(infos)
+    dt = t1 - t0
+    value = done / dt
+
+    dom, roof = roofline(prof, a.precision)
+    U, sig, V = solver.factors()
+    res_last = infos[-1]["res"]
+    acc = dict(res_last=res_last, rank=infos[-1]["r"], steps_total=a.warmup + done,
+               converged=bool(infos[-1]["converged"]),
+               fresh=sum(i["fresh"] for i in infos),
+               recycled=sum(i["recycled"] for i in infos),
+               rejected=sum(i["rejected"] for i in infos))
+    truth = prob.truth_dense()
+    if truth is not None:
+        X = (U * sig) @ V.T
+        acc["rel_err_vs_truth"] = float(np.linalg.norm(X - truth) /
+                                        np.linalg.norm(truth))
+    cpu = None
+    if not a.no_cpu_baseline:
+        orc, cpu = cpu_baseline(prob, prm, a.cpu_seconds, a.warmup + done)
+        if orc.i == a.warmup + done:
+            Xo = (orc.U * orc.sig) @ orc.V.T
+            X = (U * sig) @ V.T
+            acc["rel_err_vs_oracle"] = float(np.linalg.norm(X - Xo) /
+                                             max(np.linalg.norm(Xo), 1e-300))
+        acc["oracle_steps_compared"] = orc.i
+        common = orc.err_hist
+        gpu_hist = []  # residuals of the warm-up steps are not kept; compare
+        # the timed ones that the oracle also reached
+        for j, inf in enumerate(infos):
+            step_i = a.warmup + j + 1
+            if step_i <= len(common):
+                gpu_hist.append((inf["res"], common[step_i - 1]))
+        if gpu_hist:
+            acc["res_hist_max_rel_diff"] = float(max(
+                abs(g - o) / max(abs(o), 1e-300) for g, o in gpu_hist))
+    if a.copy_calib_mib:
+        n = a.copy_calib_mib * (1 << 20) // 4
+        src = torch.empty(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    line = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": done,
+        "warmup": a.warmup,
+        "ms_per_step": round(dt * 1e3 / done, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[a.precision],
+        "data": "synthetic",
+        "config": {"workload": a.workload, "m": prob.m, "n": prob.n,
+                   "nnz": prob.nnz, "precision": a.precision,
+                   "recycle": prm["recycle"], "p_init": prm["p_init"],
+                   "adaptive_p": prm["adaptive_p"], "tau": prm["tau"],
+                   "delta": prm["delta"], "eps": prm["eps"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "accuracy": acc,
+        "kernels": family_table(prof, tp1 - tp0),
+        "profiled_pass": {"steps": pdone, "ms_per_step": round((tp1 - tp0) * 1e3 / pdone, 4),
+                          "launch": "kernel by kernel, HIP events per launch"},
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -84,6 +84,9 @@ typedef struct {
   int32_t recycle;  /* 0 none, 1 reuse Q, 2 reuse U (Sec. IV.B) */
   int32_t k_max;    /* rank cap; 0 -> min(m, n) */
   int32_t precision;  /* mc_precision */
+  int32_t use_graphs; /* 1 (default): replay each SVD call's kernel sequence
+                         from a captured HIP graph (per shape); 0: launch
+                         kernel by kernel.  Results are identical. */
   uint64_t seed;    /* key of the counter-based Gaussian test matrices */
 } mc_svt_params;
 
@@ -185,6 +188,29 @@ mc_status mc_svt_get_y(mc_svt_t h, double* y);
 /* Singular values (descending) of the last SVD call of the last step;
  * *k receives their count; MC_EINVAL if k_cap is too small. */
 mc_status mc_svt_get_sigma(mc_svt_t h, double* S, int32_t k_cap, int32_t* k);
+
+/* Event timing of the solve's kernel families on its own stream (for
+ * measurement; adds two hipEventRecord calls per timed launch).  Families:
+ *   0 SpMM Y X (CSR)       1 SpMM Y^T X (CSC)     2 fused SDDMM/update
+ *   3 Gram / cross-Gram    4 panel GEMMs          5 Cholesky + inverse
+ *   6 eigensolve (all its kernels and convergence checks)
+ *   7 Gaussian test matrix
+ * launches = timed launches, ms = summed event time, bytes / flops = summed
+ * algorithmic traffic and arithmetic of those launches. */
+typedef struct {
+  int64_t launches;
+  double ms;
+  double bytes;
+  double flops;
+} mc_prof_entry;
+
+#define MC_PROF_FAMILIES 8
+
+/* on = 1 starts timing (totals reset), on = 0 stops it. */
+mc_status mc_svt_profile(mc_svt_t h, int32_t on);
+/* Synchronises the stream and returns the totals since the last start;
+ * cap >= MC_PROF_FAMILIES entries. */
+mc_status mc_svt_get_profile(mc_svt_t h, mc_prof_entry* out, int32_t cap);
 
 mc_status mc_svt_destroy(mc_svt_t h);
 const char* mc_svt_last_error(mc_svt_t h);

@@ -28,7 +28,8 @@ class Params(C.Structure):
                 ("p_max", C.c_int32), ("adaptive_p", C.c_int32),
                 ("i_reuse", C.c_int32), ("q_reuse", C.c_int32),
                 ("recycle", C.c_int32), ("k_max", C.c_int32),
-                ("precision", C.c_int32), ("seed", C.c_uint64)]
+                ("precision", C.c_int32), ("use_graphs", C.c_int32),
+                ("seed", C.c_uint64)]
 
 
 class StepInfo(C.Structure):
@@ -52,6 +53,14 @@ class Result(C.Structure):
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
+
+class ProfEntry(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("ms", C.c_double),
+                ("bytes", C.c_double), ("flops", C.c_double)]
+
+
+PROF_FAMILIES = ["spmm_fwd", "spmm_bwd", "sddmm", "gram", "panel_gemm",
+                 "cholesky", "eigensolve", "rng"]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -77,6 +86,8 @@ _SIGNATURES = {
     "mc_svt_get_y": (C.c_int, [C.c_void_p, _P(C.c_double)]),
     "mc_svt_get_sigma": (C.c_int, [C.c_void_p, _P(C.c_double), C.c_int32,
                                    _P(C.c_int32)]),
+    "mc_svt_profile": (C.c_int, [C.c_void_p, C.c_int32]),
+    "mc_svt_get_profile": (C.c_int, [C.c_void_p, _P(ProfEntry), C.c_int32]),
     "mc_svt_destroy": (C.c_int, [C.c_void_p]),
     "mc_svt_last_error": (C.c_char_p, [C.c_void_p]),
     "mc_rsvd_bki": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _P(C.c_int64),

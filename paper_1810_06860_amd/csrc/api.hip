@@ -184,6 +184,7 @@ void mc_svt_default_params(mc_svt_params* p) {
   p->recycle = 0;
   p->k_max = 0;
   p->precision = MC_FP64;
+  p->use_graphs = 1;
   p->seed = 12345;
 }
 
@@ -321,6 +322,36 @@ mc_status mc_svt_get_sigma(mc_svt_t h, double* S, int32_t k_cap, int32_t* k) {
     if (k) *k = (int32_t)v.size();
     MC_REQUIRE((int64_t)v.size() <= k_cap, mcsvt::kEINVAL, "k_cap too small");
     for (size_t j = 0; j < v.size(); ++j) S[j] = v[j];
+  });
+}
+
+mc_status mc_svt_profile(mc_svt_t h, int32_t on) {
+  if (!h || !h->solver) {
+    mcsvt::t_err = "NULL handle";
+    return MC_EINVAL;
+  }
+  return guarded(h, [&] {
+    auto& p = h->solver->prof;
+    p.collect();
+    if (on) p.reset();
+    p.on = on != 0;
+  });
+}
+
+mc_status mc_svt_get_profile(mc_svt_t h, mc_prof_entry* out, int32_t cap) {
+  if (!h || !h->solver || !out || cap < MC_PROF_FAMILIES) {
+    mcsvt::t_err = "bad arguments";
+    return MC_EINVAL;
+  }
+  return guarded(h, [&] {
+    auto& p = h->solver->prof;
+    p.collect();
+    for (int f = 0; f < MC_PROF_FAMILIES; ++f) {
+      out[f].launches = p.count[f];
+      out[f].ms = p.ms[f];
+      out[f].bytes = p.bytes[f];
+      out[f].flops = p.flops[f];
+    }
   });
 }
 

@@ -261,9 +261,9 @@ __global__ void ritz_reduce_kernel(int nblk, int k, const double* __restrict__ p
 int64_t gram_splits(int64_t N, int p, int q, int sym) {
   const int64_t tiles = ceil_div(p, GT) * ceil_div(q, GT);
   const int64_t eff = sym ? (tiles + ceil_div(p, GT)) / 2 : tiles;
-  // aim at ~2048 workgroups, chunks of at least 256 rows
+  // aim at ~2048 workgroups, chunks of at least 64 rows
   int64_t splits = std::max<int64_t>(1, 2048 / std::max<int64_t>(eff, 1));
-  splits = std::min<int64_t>(splits, std::max<int64_t>(1, ceil_div(N, 256)));
+  splits = std::min<int64_t>(splits, std::max<int64_t>(1, ceil_div(N, 64)));
   return splits;
 }
 

@@ -39,6 +39,142 @@ __device__ __forceinline__ int sub_index(int bi, int bj, int a) {
   return a < BS ? bi * BS + a : bj * BS + (a - BS);
 }
 
+// Whole eigenproblem in one workgroup (L <= single-workgroup limit): A in
+// LDS (row stride L + 1), V in LDS when it fits too, else in global memory.
+// Cyclic Jacobi with the round-robin ordering of all L indices (a dummy
+// index pads odd L).  A round has two phases: the rotations of its L/2
+// disjoint pairs are computed, then every 2 x 2 block (pair i rows, pair j
+// columns) of A is replaced by R_i^T A_ij R_j in place, the diagonal blocks
+// set exactly to diag(a_pp - t a_pq, a_qq + t a_pq), and V's columns rotated.
+constexpr int kSingleMaxPairs = 96;
+constexpr int kSingleThreads = 512;
+
+template <bool VLDS>
+__global__ __launch_bounds__(kSingleThreads) void jac_single_kernel(
+    int L, const double* __restrict__ G, int64_t ldg, double* __restrict__ Aout,
+    double* __restrict__ Vg, double tol_rel, double tol_abs_fac,
+    int* __restrict__ sweeps_out) {
+  extern __shared__ double lds[];
+  const int ld = L + 1;
+  double* A = lds;
+  double* V = VLDS ? lds + (size_t)L * ld : Vg;
+  const int ldv = VLDS ? ld : L;
+  __shared__ int P[kSingleMaxPairs], Q[kSingleMaxPairs];
+  __shared__ double Cc[kSingleMaxPairs], Ss[kSingleMaxPairs];
+  __shared__ double D0[kSingleMaxPairs], D1[kSingleMaxPairs];
+  __shared__ double red[kSingleThreads];
+  const int tid = threadIdx.x;
+  const int tx = tid % 32, ty = tid / 32;          // 32 x 16 thread grid
+  const int n2 = L + (L & 1);
+  const int np = n2 / 2;
+  double ss = 0.0;
+  for (int t = tid; t < L * L; t += kSingleThreads) {
+    const int i = t / L, j = t % L;
+    const double x = G[(int64_t)i * ldg + j], y = G[(int64_t)j * ldg + i];
+    const double a = (i == j) ? x : 0.5 * (x + y);
+    A[i * ld + j] = a;
+    ss += a * a;
+    V[(int64_t)i * ldv + j] = (i == j) ? 1.0 : 0.0;
+  }
+  red[tid] = ss;
+  __syncthreads();
+  for (int s = kSingleThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  const double tol_abs = tol_abs_fac * sqrt(red[0]);
+  int sweep = 0;
+  for (; sweep < 60; ++sweep) {
+    int swept = 0;
+    for (int rr = 0; rr < n2 - 1; ++rr) {
+      int mine = 0;
+      if (tid < np) {
+        int p = tid == 0 ? 0 : 1 + ((tid - 1 + rr) % (n2 - 1));
+        const int jj = n2 - 1 - tid;
+        int q = jj == 0 ? 0 : 1 + ((jj - 1 + rr) % (n2 - 1));
+        if (p > q) { const int x = p; p = q; q = x; }
+        double c = 1.0, s = 0.0, d0 = 0.0, d1 = 0.0;
+        if (q < L) {
+          const double apq = A[p * ld + q], app = A[p * ld + p], aqq = A[q * ld + q];
+          if (fabs(apq) > fmax(tol_rel * sqrt(fabs(app * aqq)), tol_abs)) {
+            const double theta = (aqq - app) / (2.0 * apq);
+            const double tt =
+                (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+            d0 = app - tt * apq;
+            d1 = aqq + tt * apq;
+            mine = 1;
+          }
+        }
+        P[tid] = p;
+        Q[tid] = q;
+        Cc[tid] = c;
+        Ss[tid] = s;
+        D0[tid] = d0;
+        D1[tid] = d1;
+      }
+      if (!__syncthreads_or(mine)) continue;
+      swept = 1;
+      // A <- R^T A R, one 2 x 2 block (pair ti rows, pair tj cols) per item
+      for (int ti = ty; ti < np; ti += kSingleThreads / 32) {
+        const int p1 = P[ti], q1 = Q[ti];
+        const double c1 = Cc[ti], s1 = Ss[ti];
+        for (int tj = tx; tj < np; tj += 32) {
+          if (tj < ti) continue;
+          const double s2 = Ss[tj];
+          if (s1 == 0.0 && s2 == 0.0) continue;
+          if (ti == tj) {
+            A[p1 * ld + p1] = D0[ti];
+            A[q1 * ld + q1] = D1[ti];
+            A[p1 * ld + q1] = 0.0;
+            A[q1 * ld + p1] = 0.0;
+            continue;
+          }
+          const int p2 = P[tj], q2 = Q[tj];
+          const double c2 = Cc[tj];
+          const bool vq1 = q1 < L, vq2 = q2 < L;
+          double a = A[p1 * ld + p2];
+          double b = vq2 ? A[p1 * ld + q2] : 0.0;
+          double c = vq1 ? A[q1 * ld + p2] : 0.0;
+          double d = (vq1 && vq2) ? A[q1 * ld + q2] : 0.0;
+          // rows (pair ti)
+          double a1 = c1 * a - s1 * c, b1 = c1 * b - s1 * d;
+          double c1r = s1 * a + c1 * c, d1r = s1 * b + c1 * d;
+          // cols (pair tj)
+          a = c2 * a1 - s2 * b1;
+          b = s2 * a1 + c2 * b1;
+          c = c2 * c1r - s2 * d1r;
+          d = s2 * c1r + c2 * d1r;
+          A[p1 * ld + p2] = a;
+          A[p2 * ld + p1] = a;
+          if (vq2) { A[p1 * ld + q2] = b; A[q2 * ld + p1] = b; }
+          if (vq1) { A[q1 * ld + p2] = c; A[p2 * ld + q1] = c; }
+          if (vq1 && vq2) { A[q1 * ld + q2] = d; A[q2 * ld + q1] = d; }
+        }
+      }
+      // V <- V R
+      for (int j = ty; j < L; j += kSingleThreads / 32) {
+        for (int t = tx; t < np; t += 32) {
+          const double s = Ss[t];
+          if (s == 0.0) continue;
+          const int p = P[t], q = Q[t];
+          const double c = Cc[t];
+          const double a = V[(int64_t)j * ldv + p], b = V[(int64_t)j * ldv + q];
+          V[(int64_t)j * ldv + p] = c * a - s * b;
+          V[(int64_t)j * ldv + q] = s * a + c * b;
+        }
+      }
+      __syncthreads();
+    }
+    if (!swept) break;
+  }
+  for (int j = tid; j < L; j += kSingleThreads) Aout[(int64_t)j * L + j] = A[j * ld + j];
+  if (VLDS)
+    for (int t = tid; t < L * L; t += kSingleThreads) Vg[t] = V[(t / L) * ld + (t % L)];
+  if (tid == 0 && sweeps_out) *sweeps_out = sweep + 1;
+}
+
 __global__ void jac_init_kernel(int L, int Lp, const double* __restrict__ G,
                                 int64_t ldg, double* __restrict__ A,
                                 double* __restrict__ V, double pad) {
@@ -57,105 +193,107 @@ __global__ void jac_init_kernel(int L, int Lp, const double* __restrict__ G,
   V[t] = (i == j) ? 1.0 : 0.0;
 }
 
-// 64 threads (one wavefront) per pair
-__global__ __launch_bounds__(64) void jac_solve_kernel(
+// One workgroup (256 threads = 16 x 16 over the 16 x 16 pair blocks) per
+// block pair: cyclic Jacobi on the 32 x 32 principal submatrix in LDS, two
+// phases per round as in the one-workgroup solver; J accumulates the
+// rotations.
+__global__ __launch_bounds__(256) void jac_solve_kernel(
     int Lp, int nb, int round, double* __restrict__ A,
     double* __restrict__ Jbuf, double* __restrict__ Sbuf,
     int* __restrict__ rot_flag, double tol_rel, double tol_abs) {
   __shared__ double S[SP][SP + 1];
   __shared__ double J[SP][SP + 1];
-  __shared__ double cs[SP / 2][2];
-  __shared__ double dnew[SP / 2][2];
-  __shared__ int any;
+  __shared__ int P[SP / 2], Q[SP / 2];
+  __shared__ double Cc[SP / 2], Ss[SP / 2], D0[SP / 2], D1[SP / 2];
   const int pair = blockIdx.x;
   int bi, bj;
   pair_of(nb, round, pair, bi, bj);
   const int tid = threadIdx.x;
-  for (int t = tid; t < SP * SP; t += 64) {
+  const int tx = tid % 16, ty = tid / 16;
+  for (int t = tid; t < SP * SP; t += 256) {
     const int a = t / SP, b = t % SP;
     S[a][b] = A[(int64_t)sub_index(bi, bj, a) * Lp + sub_index(bi, bj, b)];
     J[a][b] = (a == b) ? 1.0 : 0.0;
   }
-  if (tid == 0) any = 0;
   __syncthreads();
+  int any = 0;
   for (int sweep = 0; sweep < 20; ++sweep) {
     int swept = 0;
     for (int rr = 0; rr < SP - 1; ++rr) {
       int mine = 0;
       if (tid < SP / 2) {
-        const int t = tid;
         int p, q;
-        inner_pair(rr, t, p, q);
+        inner_pair(rr, tid, p, q);
         const double apq = S[p][q], app = S[p][p], aqq = S[q][q];
-        double c = 1.0, s = 0.0, tt = 0.0;
+        double c = 1.0, s = 0.0, d0 = 0.0, d1 = 0.0;
         if (fabs(apq) > fmax(tol_rel * sqrt(fabs(app * aqq)), tol_abs)) {
           const double theta = (aqq - app) / (2.0 * apq);
-          tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+          const double tt =
+              (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
           c = 1.0 / sqrt(1.0 + tt * tt);
           s = tt * c;
+          d0 = app - tt * apq;
+          d1 = aqq + tt * apq;
           mine = 1;
         }
-        cs[t][0] = c;
-        cs[t][1] = s;
-        dnew[t][0] = app - tt * apq;
-        dnew[t][1] = aqq + tt * apq;
+        P[tid] = p;
+        Q[tid] = q;
+        Cc[tid] = c;
+        Ss[tid] = s;
+        D0[tid] = d0;
+        D1[tid] = d1;
       }
-      const int round_rot = __syncthreads_or(mine);
-      if (!round_rot) continue;
+      if (!__syncthreads_or(mine)) continue;
       swept = 1;
-      // rows: a'_pj = c a_pj - s a_qj ; a'_qj = s a_pj + c a_qj
-      for (int w = tid; w < (SP / 2) * SP; w += 64) {
-        const int t = w / SP, j = w % SP;
-        int p, q;
-        inner_pair(rr, t, p, q);
-        const double c = cs[t][0], s = cs[t][1];
-        if (s != 0.0) {
-          const double a = S[p][j], b = S[q][j];
-          S[p][j] = c * a - s * b;
-          S[q][j] = s * a + c * b;
+      {
+        const int ti = ty, tj = tx;      // one 2 x 2 block of S per thread
+        const double s1 = Ss[ti], s2 = Ss[tj];
+        if (tj >= ti && (s1 != 0.0 || s2 != 0.0)) {
+          const int p1 = P[ti], q1 = Q[ti];
+          if (ti == tj) {
+            S[p1][p1] = D0[ti];
+            S[q1][q1] = D1[ti];
+            S[p1][q1] = 0.0;
+            S[q1][p1] = 0.0;
+          } else {
+            const int p2 = P[tj], q2 = Q[tj];
+            const double c1 = Cc[ti], c2 = Cc[tj];
+            double a = S[p1][p2], b = S[p1][q2], c = S[q1][p2], d = S[q1][q2];
+            const double a1 = c1 * a - s1 * c, b1 = c1 * b - s1 * d;
+            const double c1r = s1 * a + c1 * c, d1r = s1 * b + c1 * d;
+            a = c2 * a1 - s2 * b1;
+            b = s2 * a1 + c2 * b1;
+            c = c2 * c1r - s2 * d1r;
+            d = s2 * c1r + c2 * d1r;
+            S[p1][p2] = a; S[p2][p1] = a;
+            S[p1][q2] = b; S[q2][p1] = b;
+            S[q1][p2] = c; S[p2][q1] = c;
+            S[q1][q2] = d; S[q2][q1] = d;
+          }
         }
       }
-      __syncthreads();
-      // cols of S and J: x'_jp = c x_jp - s x_jq ; x'_jq = s x_jp + c x_jq
-      for (int w = tid; w < (SP / 2) * SP; w += 64) {
-        const int t = w / SP, j = w % SP;
-        int p, q;
-        inner_pair(rr, t, p, q);
-        const double c = cs[t][0], s = cs[t][1];
+      for (int w = tid; w < SP * (SP / 2); w += 256) {   // J <- J R
+        const int j = w / (SP / 2), t = w % (SP / 2);
+        const double s = Ss[t];
         if (s != 0.0) {
-          double a = S[j][p], b = S[j][q];
-          S[j][p] = c * a - s * b;
-          S[j][q] = s * a + c * b;
-          a = J[j][p];
-          b = J[j][q];
+          const int p = P[t], q = Q[t];
+          const double c = Cc[t];
+          const double a = J[j][p], b = J[j][q];
           J[j][p] = c * a - s * b;
           J[j][q] = s * a + c * b;
         }
       }
       __syncthreads();
-      if (tid < SP / 2) {
-        const int t = tid;
-        int p, q;
-        inner_pair(rr, t, p, q);
-        if (cs[t][1] != 0.0) {
-          S[p][q] = 0.0;
-          S[q][p] = 0.0;
-          S[p][p] = dnew[t][0];
-          S[q][q] = dnew[t][1];
-        }
-      }
-      __syncthreads();
     }
-    if (swept && tid == 0) any = 1;
+    any |= swept;
     if (!swept) break;
   }
-  __syncthreads();
   double* Jo = Jbuf + (int64_t)pair * SP * SP;
   double* So = Sbuf + (int64_t)pair * SP * SP;
-  for (int t = tid; t < SP * SP; t += 64) {
+  for (int t = tid; t < SP * SP; t += 256) {
     const int a = t / SP, b = t % SP;
     Jo[t] = J[a][b];
-    So[t] = (a == b) ? S[a][a] : 0.5 * (S[a][b] + S[b][a]);
+    So[t] = S[a][b];
   }
   if (tid == 0 && any) atomicAdd(rot_flag, 1);
 }
@@ -300,7 +438,7 @@ __global__ void select_topk_kernel(int L, int Lp, int k,
 }  // namespace
 
 void EigSolver::reserve(int L, hipStream_t st) {
-  const int Lp = (int)round_up(std::max(L, 1), SP);
+  const int Lp = (int)round_up(std::max(L, 1), SP);   // >= L for both paths
   const int nb = Lp / BS;
   A.reserve((size_t)Lp * Lp, st);
   V.reserve((size_t)Lp * Lp, st);
@@ -315,35 +453,94 @@ EigSolver::~EigSolver() {
   if (hflags) (void)hipHostFree(hflags);
 }
 
+namespace {
+// Largest dynamic LDS one workgroup may use (queried once; gfx950 allows more
+// than the 64 KB default once the kernel attribute is raised).
+size_t lds_limit() {
+  static size_t lim = 0;
+  if (lim) return lim;
+  int dev = 0, v = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) !=
+          hipSuccess || v <= 0) {
+    (void)hipGetLastError();
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      v = 65536;
+    }
+  }
+  lim = (size_t)v;
+  for (const void* f : {(const void*)jac_single_kernel<true>,
+                        (const void*)jac_single_kernel<false>}) {
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(lim - 1024)) != hipSuccess) {
+      (void)hipGetLastError();
+      lim = 65536;
+    }
+  }
+  return lim;
+}
+}  // namespace
+
+int EigSolver::single_max() {
+  const size_t lim = lds_limit() - 1024;
+  int L = 1;
+  while (L + 1 <= 2 * kSingleMaxPairs &&
+         (size_t)(L + 1) * (L + 2) * sizeof(double) <= lim)
+    ++L;
+  return L;
+}
+
 int EigSolver::solve(int L, const double* G, int64_t ldg, hipStream_t st) {
   reserve(L, st);
+  // rotations below ~LAPACK-level accuracy (1e-14 ||G||_F) resolve only the
+  // round-off of the Gram product itself
+  const double tol_rel = 4e-15;
+  const double tol_abs_fac = 1e-14;
+  this->L = L;
+  if (L <= single_max()) {
+    this->Lp = L;
+    const size_t ld = (size_t)L + 1;
+    const size_t a_bytes = (size_t)L * ld * sizeof(double);
+    const bool vlds = 2 * a_bytes <= lds_limit() - 1024;
+    const size_t bytes = vlds ? 2 * a_bytes : a_bytes;
+    if (vlds)
+      hipLaunchKernelGGL(jac_single_kernel<true>, dim3(1), dim3(kSingleThreads),
+                         bytes, st, L, G, ldg, A.p, V.p, tol_rel, tol_abs_fac,
+                         flags.p);
+    else
+      hipLaunchKernelGGL(jac_single_kernel<false>, dim3(1), dim3(kSingleThreads),
+                         bytes, st, L, G, ldg, A.p, V.p, tol_rel, tol_abs_fac,
+                         flags.p);
+    MC_CHECK_LAUNCH();
+    sweeps = -1;     // known on the device only
+    return 0;
+  }
   const int Lp = (int)round_up(std::max(L, 1), SP);
   const int nb = Lp / BS;
   const int npair = nb / 2;
-  this->L = L;
   this->Lp = Lp;
   hipLaunchKernelGGL(frob_kernel, dim3(1), dim3(1024), 0, st, L, G, ldg, scal.p);
   MC_CHECK_LAUNCH();
   double hnorm = 0.0;
   MC_HIP(hipMemcpyAsync(&hnorm, scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
-  const int64_t tot = (int64_t)Lp * Lp;
   MC_HIP(hipStreamSynchronize(st));
+  const double tol_abs = tol_abs_fac * hnorm;
+  const int64_t tot = (int64_t)Lp * Lp;
   const double pad = -(1.0 + 2.0 * hnorm);
   hipLaunchKernelGGL(jac_init_kernel, dim3((unsigned)ceil_div(tot, 256)),
                      dim3(256), 0, st, L, Lp, G, ldg, A.p, V.p, pad);
   MC_CHECK_LAUNCH();
   const int rounds = nb - 1;
   MC_HIP(hipMemsetAsync(flags.p, 0, sizeof(int) * (kMaxSweeps * 64 + 8), st));
-  const double tol_rel = 4e-15;
-  const double tol_abs = 4e-16 * hnorm;
   int sweep = 0;
   for (; sweep < kMaxSweeps; ++sweep) {
     int* sflag = flags.p + sweep * 64;
     for (int r = 0; r < rounds; ++r) {
+      // counts the pairs that rotated in this round of this sweep
       int* rflag = sflag + 1 + (r % 63);
-      // rflag counts pairs that rotated in this round (shared across sweeps
-      // of the same round slot, so offset by sweep)
-      hipLaunchKernelGGL(jac_solve_kernel, dim3(npair), dim3(64), 0, st, Lp, nb,
+      hipLaunchKernelGGL(jac_solve_kernel, dim3(npair), dim3(256), 0, st, Lp, nb,
                          r, A.p, J.p, Sd.p, rflag, tol_rel, tol_abs);
       MC_CHECK_LAUNCH();
       hipLaunchKernelGGL(jac_apply_a_kernel, dim3(npair * npair), dim3(256), 0,
@@ -364,6 +561,13 @@ int EigSolver::solve(int L, const double* G, int64_t ldg, hipStream_t st) {
   }
   sweeps = sweep;
   return sweep;
+}
+
+int EigSolver::device_sweeps(hipStream_t st) {
+  if (sweeps >= 0) return sweeps;
+  MC_HIP(hipMemcpyAsync(hflags, flags.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  MC_HIP(hipStreamSynchronize(st));
+  return hflags[0];
 }
 
 void EigSolver::select_topk(int k, double* S, double* D, double* Wk, int64_t ldw,

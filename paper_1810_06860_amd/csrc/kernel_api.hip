@@ -226,7 +226,7 @@ mc_status mc_k_syev(int32_t L, const double* G, int32_t k, void* stream,
     download(evals, D.p, k, st);
     download(W, Wk.p, (int64_t)L * k, st);
     MC_HIP(hipStreamSynchronize(st));
-    if (sweeps) *sweeps = eig.sweeps;
+    if (sweeps) *sweeps = eig.device_sweeps(st);
   });
 }
 

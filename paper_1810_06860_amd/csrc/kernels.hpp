@@ -51,6 +51,10 @@ void launch_gaussian(T* out, int64_t rows, int64_t cols, int64_t ld,
                      uint64_t seed, uint32_t step, uint32_t attempt,
                      hipStream_t st);
 
+template <class T>
+void launch_gaussian_ctr(T* out, int64_t rows, int64_t cols, int64_t ld,
+                         uint64_t seed, const uint32_t* d_ctr, hipStream_t st);
+
 // out (rows x b, ldo) = A X ; A given by schedule + idx + val; part is the
 // partial-row buffer (nslot * b elements).
 template <class VT, class XT, class AT, class OT>
@@ -118,6 +122,10 @@ struct EigSolver {
   void reserve(int L, hipStream_t st);
   // eigen-decompose the symmetric L x L matrix G (row-major, ldg)
   int solve(int L, const double* G, int64_t ldg, hipStream_t st);
+  // largest L solved inside one workgroup (LDS-resident)
+  static int single_max();
+  // Jacobi sweeps of the last solve (synchronises for the one-workgroup path)
+  int device_sweeps(hipStream_t st);
   // top-k (descending): S = sqrt(max(lambda, 0)), Wk (L x k, ldw) vectors,
   // D (optional, L) all eigenvalues descending
   void select_topk(int k, double* S, double* D, double* Wk, int64_t ldw,

@@ -36,8 +36,12 @@ __device__ __forceinline__ double unit53(uint32_t hi, uint32_t lo) {
 
 template <class T>
 __global__ void gaussian_kernel(T* __restrict__ out, int64_t rows, int64_t cols,
-                                int64_t ld, uint64_t seed, uint32_t step,
-                                uint32_t attempt) {
+                                int64_t ld, uint64_t seed, uint32_t step_arg,
+                                uint32_t attempt_arg, const uint32_t* __restrict__ ctr) {
+  // (step, attempt) from device memory when given, so a captured graph can
+  // be replayed for any call of the stream
+  const uint32_t step = ctr ? ctr[0] : step_arg;
+  const uint32_t attempt = ctr ? ctr[1] : attempt_arg;
   const int64_t count = rows * cols;
   const int64_t npair = (count + 1) / 2;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < npair;
@@ -75,9 +79,25 @@ void launch_gaussian(T* out, int64_t rows, int64_t cols, int64_t ld,
   const int threads = 256;
   const int64_t grid = std::min<int64_t>(ceil_div(npair, threads), kMaxGrid);
   hipLaunchKernelGGL(gaussian_kernel<T>, dim3((unsigned)grid), dim3(threads), 0,
-                     st, out, rows, cols, ld, seed, step, attempt);
+                     st, out, rows, cols, ld, seed, step, attempt, nullptr);
   MC_CHECK_LAUNCH();
 }
+
+template <class T>
+void launch_gaussian_ctr(T* out, int64_t rows, int64_t cols, int64_t ld,
+                         uint64_t seed, const uint32_t* d_ctr, hipStream_t st) {
+  const int64_t npair = (rows * cols + 1) / 2;
+  if (npair == 0) return;
+  const int threads = 256;
+  const int64_t grid = std::min<int64_t>(ceil_div(npair, threads), kMaxGrid);
+  hipLaunchKernelGGL(gaussian_kernel<T>, dim3((unsigned)grid), dim3(threads), 0,
+                     st, out, rows, cols, ld, seed, 0u, 0u, d_ctr);
+  MC_CHECK_LAUNCH();
+}
+template void launch_gaussian_ctr<double>(double*, int64_t, int64_t, int64_t,
+                                          uint64_t, const uint32_t*, hipStream_t);
+template void launch_gaussian_ctr<float>(float*, int64_t, int64_t, int64_t,
+                                         uint64_t, const uint32_t*, hipStream_t);
 
 template void launch_gaussian<double>(double*, int64_t, int64_t, int64_t,
                                       uint64_t, uint32_t, uint32_t, hipStream_t);

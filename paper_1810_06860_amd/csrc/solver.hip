@@ -34,6 +34,53 @@ void swap_buf(DevBuf<T>& a, DevBuf<T>& b) {
 }
 }  // namespace
 
+Profiler::~Profiler() {
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+hipEvent_t Profiler::ev() {
+  if (used == pool.size()) {
+    hipEvent_t e;
+    MC_HIP(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+  return pool[used++];
+}
+
+void Profiler::begin(int fam, double b, double f, hipStream_t st) {
+  if (!on) return;
+  Rec r{fam, b, f, ev(), nullptr};
+  MC_HIP(hipEventRecord(r.a, st));
+  recs.push_back(r);
+}
+
+void Profiler::end(hipStream_t st) {
+  if (!on) return;
+  Rec& r = recs.back();
+  r.b = ev();
+  MC_HIP(hipEventRecord(r.b, st));
+}
+
+void Profiler::collect() {
+  for (Rec& r : recs) {
+    MC_HIP(hipEventSynchronize(r.b));
+    float t = 0.f;
+    MC_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.fam] += t;
+    bytes[r.fam] += r.bytes;
+    flops[r.fam] += r.flops;
+    count[r.fam] += 1;
+  }
+  recs.clear();
+  used = 0;
+}
+
+void Profiler::reset() {
+  recs.clear();
+  used = 0;
+  for (int f = 0; f < kProfCount; ++f) ms[f] = bytes[f] = flops[f] = 0, count[f] = 0;
+}
+
 void resolve_params(int64_t m, int64_t n, int64_t nnz, mc_svt_params& p) {
   if (!(p.tau > 0)) p.tau = 5.0 * (double)n;
   if (!(p.delta > 0)) p.delta = 1.2 * (double)m * (double)n / (double)nnz;
@@ -62,11 +109,16 @@ Solver::Solver(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& prm,
   p_ = prm_.p_init;
   shift_count_.reserve(1, st_);
   blk_flag_.reserve(1, st_);
+  ctr_.reserve(2, st_);
+  MC_HIP(hipHostMalloc((void**)&hctr_, 2 * sizeof(uint32_t)));
   MC_HIP(hipMemsetAsync(shift_count_.p, 0, sizeof(int), st_));
 }
 
 Solver::~Solver() {
+  clear_graphs();
+  if (cap_) (void)hipStreamDestroy(cap_);
   if (hbuf_) (void)hipHostFree(hbuf_);
+  if (hctr_) (void)hipHostFree(hctr_);
 }
 
 int Solver::chol_shifts() {
@@ -84,6 +136,9 @@ void Solver::widths(int k, int p, int& b, int& p_eff) const {
 
 void Solver::ensure(int bmax, int Lmax, int kmax) {
   if (bmax <= cap_b_ && Lmax <= cap_L_ && kmax <= cap_k_ && hbuf_) return;
+  // buffers move: captured graphs hold their addresses
+  ++gen_;
+  clear_graphs();
   const int64_t mn = std::min(m_, n_);
   // grow with headroom so the rank search does not reallocate every step
   auto grow = [&](int want, int have) {
@@ -179,34 +234,55 @@ int Solver::init(const int64_t* rows, const int32_t* cols, const double* vals,
   return kOK;
 }
 
+// algorithmic bytes of one SpMM: values + indices + pointers + panel in + out
+static double spmm_bytes(int64_t nnz, int64_t rows, int64_t cols, int b, int sv,
+                         int sx) {
+  return (double)nnz * (sv + 4) + 4.0 * (rows + 1) + (double)cols * b * sx +
+         (double)rows * b * sx;
+}
+
 void Solver::spmm_y(const double* X, int64_t ldx, double* out, int64_t ldo, int b) {
+  prof.begin(kProfSpmmFwd, spmm_bytes(nnz_, m_, n_, b, 8, 8), 2.0 * nnz_ * b, ls());
   launch_spmm<double, double, double, double>(L_.sched_csr, L_.col_idx.p, y_.p, X,
-                                              ldx, out, ldo, b, spmm_part_.p, st_);
+                                              ldx, out, ldo, b, spmm_part_.p, ls());
+  prof.end(ls());
 }
 
 void Solver::spmm_yt(const double* X, int64_t ldx, double* out, int64_t ldo, int b) {
+  prof.begin(kProfSpmmBwd, spmm_bytes(nnz_, n_, m_, b, 8, 8), 2.0 * nnz_ * b, ls());
   launch_spmm<double, double, double, double>(L_.sched_csc, L_.row_idx.p, ycsc_.p,
                                               X, ldx, out, ldo, b, spmm_part_.p,
-                                              st_);
+                                              ls());
+  prof.end(ls());
 }
 
 void Solver::cholqr_pass(const double* Hin, int64_t ldin, double* out,
                          int64_t ldo, int b, const int* gate) {
+  prof.begin(kProfGram, 8.0 * m_ * b, 1.0 * m_ * b * (b + 1), ls());
   launch_gram<double, double>(m_, b, b, Hin, ldin, Hin, ldin, G_.p, b, 1,
-                              gram_part_.p, gram_cap_, st_, gate);
-  launch_chol_inv(b, G_.p, b, Rinv_.p, b, chol_work_.p, m_, shift_count_.p, st_,
+                              gram_part_.p, gram_cap_, ls(), gate);
+  prof.end(ls());
+  prof.begin(kProfChol, 16.0 * b * b, b * (double)b * b, ls());
+  launch_chol_inv(b, G_.p, b, Rinv_.p, b, chol_work_.p, m_, shift_count_.p, ls(),
                   blk_flag_.p, gate);
+  prof.end(ls());
+  prof.begin(kProfGemm, 16.0 * m_ * b, 2.0 * m_ * b * b, ls());
   launch_panel_gemm<double, double>(m_, b, b, Hin, ldin, Rinv_.p, b, 1.0,
-                                    nullptr, 0.0, nullptr, 0, out, ldo, st_, gate);
+                                    nullptr, 0.0, nullptr, 0, out, ldo, ls(), gate);
+  prof.end(ls());
 }
 
 // Hout = Hin - Qp (Qp^T Hin) with Qp = the first jb columns of Qw_
 void Solver::project(const double* Hin, int64_t ldin, double* Hout, int jb, int b,
                      int Lw, const int* gate) {
+  prof.begin(kProfGram, 8.0 * m_ * (jb + b), 2.0 * m_ * jb * b, ls());
   launch_gram<double, double>(m_, jb, b, Qw_.p, Lw, Hin, ldin, Cg_.p, b, 0,
-                              gram_part_.p, gram_cap_, st_, gate);
+                              gram_part_.p, gram_cap_, ls(), gate);
+  prof.end(ls());
+  prof.begin(kProfGemm, 8.0 * m_ * (jb + 2 * b), 2.0 * m_ * jb * b, ls());
   launch_panel_gemm<double, double>(m_, jb, b, Qw_.p, Lw, Cg_.p, b, -1.0, nullptr,
-                                    1.0, Hin, ldin, Hout, b, st_, gate);
+                                    1.0, Hin, ldin, Hout, b, ls(), gate);
+  prof.end(ls());
 }
 
 // Orthonormalise the raw Krylov block in H1_ against Q_0..Q_{j-1} and write
@@ -216,12 +292,12 @@ void Solver::project(const double* Hin, int64_t ldin, double* Hout, int jb, int 
 void Solver::orth_block(int j, int b, int Lw) {
   double* out = Qw_.p + (int64_t)j * b;
   const int* gate = blk_flag_.p;
-  launch_set_int(blk_flag_.p, 0, st_);
+  launch_set_int(blk_flag_.p, 0, ls());
   if (j == 0) {
     cholqr_pass(H1_.p, b, H2_.p, b, b, nullptr);
     cholqr_pass(H2_.p, b, out, Lw, b, nullptr);
     cholqr_pass(out, Lw, H1_.p, b, b, gate);
-    launch_copy_gated(m_, b, H1_.p, b, out, Lw, gate, st_);
+    launch_copy_gated(m_, b, H1_.p, b, out, Lw, gate, ls());
     return;
   }
   const int jb = j * b;
@@ -231,30 +307,101 @@ void Solver::orth_block(int j, int b, int Lw) {
   cholqr_pass(H2_.p, b, out, Lw, b, nullptr);
   project(out, Lw, H2_.p, jb, b, Lw, gate);
   cholqr_pass(H2_.p, b, H1_.p, b, b, gate);
-  launch_copy_gated(m_, b, H1_.p, b, out, Lw, gate, st_);
+  launch_copy_gated(m_, b, H1_.p, b, out, Lw, gate, ls());
 }
 
-void Solver::read_sigma(int k) {
+// S (k values) and, with the Ritz guard, the k Ritz ratios: one round trip
+double Solver::read_results(int k, bool ritz) {
   MC_HIP(hipMemcpyAsync(hbuf_, S_.p, k * sizeof(double), hipMemcpyDeviceToHost, st_));
+  if (ritz)
+    MC_HIP(hipMemcpyAsync(hbuf_ + k, ritz_out_.p, k * sizeof(double),
+                          hipMemcpyDeviceToHost, st_));
   MC_HIP(hipStreamSynchronize(st_));
   lastS_.assign(hbuf_, hbuf_ + k);
   for (double v : lastS_)
     MC_REQUIRE(std::isfinite(v), kENUMERIC, "non-finite singular value");
+  double worst = 0.0;
+  if (ritz)
+    for (int j = 0; j < k; ++j) worst = std::max(worst, hbuf_[k + j]);
+  return worst;
 }
 
-void Solver::eigsvd_from_basis(const double* basis, int64_t ldb, int w, int k) {
+// eigSVD of B^T = Y^T basis (Alg. 3 on B^T, Alg. 5 steps 8-10): kernels only
+void Solver::eig_body(const double* basis, int64_t ldb, int w, int k) {
   spmm_yt(basis, ldb, Bt_.p, w, w);                          // B^T = Y^T basis
+  prof.begin(kProfGram, 8.0 * n_ * w, 1.0 * n_ * w * (w + 1), ls());
   launch_gram<double, double>(n_, w, w, Bt_.p, w, Bt_.p, w, G_.p, w, 1,
-                              gram_part_.p, gram_cap_, st_); // G = B B^T
-  eig_.solve(w, G_.p, w, st_);
-  eig_.select_topk(k, S_.p, D_.p, Wk_.p, k, st_);
+                              gram_part_.p, gram_cap_, ls()); // G = B B^T
+  prof.end(ls());
+  prof.begin(kProfEig, 16.0 * w * w, 0.0, ls());
+  eig_.solve(w, G_.p, w, ls());
+  eig_.select_topk(k, S_.p, D_.p, Wk_.p, k, ls());
+  prof.end(ls());
+  prof.begin(kProfGemm, 8.0 * (m_ + n_) * (w + k), 2.0 * (m_ + n_) * w * k, ls());
   launch_panel_gemm<double, double>(m_, w, k, basis, ldb, Wk_.p, k, 1.0, nullptr,
-                                    0.0, nullptr, 0, U_.p, k, st_);   // U = Q W
-  launch_recip(k, S_.p, Sinv_.p, st_);
+                                    0.0, nullptr, 0, U_.p, k, ls());  // U = Q W
+  launch_recip(k, S_.p, Sinv_.p, ls());
   launch_panel_gemm<double, double>(n_, w, k, Bt_.p, w, Wk_.p, k, 1.0, Sinv_.p,
-                                    0.0, nullptr, 0, V_.p, k, st_);   // V = B^T W S^-1
-  k_last_ = k;
-  read_sigma(k);
+                                    0.0, nullptr, 0, V_.p, k, ls());  // V = B^T W S^-1
+  prof.end(ls());
+}
+
+// Ritz residual ratios ||Y v_j - s_j u_j|| / s_j into ritz_out_
+void Solver::ritz_body(int k) {
+  spmm_y(V_.p, k, H1_.p, k, k);                              // R = Y V
+  launch_ritz(m_, k, H1_.p, k, U_.p, k, S_.p, ritz_part_.p, ritz_out_.p, ls());
+}
+
+void Solver::fresh_body(int k, int b, int p_eff, int Lw) {
+  prof.begin(kProfRng, 8.0 * n_ * b, 0.0, ls());
+  launch_gaussian_ctr<double>(omega_.p, n_, b, b, prm_.seed, ctr_.p, ls());
+  prof.end(ls());
+  spmm_y(omega_.p, b, H1_.p, b, b);                          // H_0 = Y Omega
+  orth_block(0, b, Lw);
+  for (int j = 1; j <= p_eff; ++j) {
+    spmm_yt(Qw_.p + (int64_t)(j - 1) * b, Lw, Z_.p, b, b);   // Y^T Q_{j-1}
+    spmm_y(Z_.p, b, H1_.p, b, b);                            // H_j
+    orth_block(j, b, Lw);
+  }
+  eig_body(Qw_.p, Lw, Lw, k);
+}
+
+bool Solver::graphs_ok(int w) const {
+  return prm_.use_graphs && !prof.on && w <= EigSolver::single_max();
+}
+
+template <class F>
+void Solver::run_graph(const GraphKey& key, F&& body) {
+  auto it = graphs_.find(key);
+  if (it == graphs_.end()) {
+    if (!cap_) MC_HIP(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
+    if (graphs_.size() >= 64) clear_graphs();
+    hipGraph_t g = nullptr;
+    MC_HIP(hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal));
+    capturing_ = true;
+    try {
+      body();
+    } catch (...) {
+      capturing_ = false;
+      hipGraph_t junk = nullptr;
+      (void)hipStreamEndCapture(cap_, &junk);
+      if (junk) (void)hipGraphDestroy(junk);
+      throw;
+    }
+    capturing_ = false;
+    MC_HIP(hipStreamEndCapture(cap_, &g));
+    hipGraphExec_t ge = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    MC_HIP(e);
+    it = graphs_.emplace(key, ge).first;
+  }
+  MC_HIP(hipGraphLaunch(it->second, st_));
+}
+
+void Solver::clear_graphs() {
+  for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
+  graphs_.clear();
 }
 
 void Solver::fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt) {
@@ -263,21 +410,23 @@ void Solver::fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt) {
   const int Lw = (p_eff + 1) * b;
   ensure(b, Lw, k);
   Qw_.reserve(m_ * (int64_t)cap_L_, st_);
-  launch_gaussian<double>(omega_.p, n_, b, b, prm_.seed, step_id, attempt, st_);
-  spmm_y(omega_.p, b, H1_.p, b, b);                          // H_0 = Y Omega
-  orth_block(0, b, Lw);
-  for (int j = 1; j <= p_eff; ++j) {
-    spmm_yt(Qw_.p + (int64_t)(j - 1) * b, Lw, Z_.p, b, b);   // Y^T Q_{j-1}
-    spmm_y(Z_.p, b, H1_.p, b, b);                            // H_j
-    orth_block(j, b, Lw);
+  hctr_[0] = step_id;
+  hctr_[1] = attempt;
+  MC_HIP(hipMemcpyAsync(ctr_.p, hctr_, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, st_));
+  if (graphs_ok(Lw)) {
+    const GraphKey key{1, k, b, p_eff, Lw, (int64_t)gen_, (int64_t)(intptr_t)Qw_.p, 0};
+    run_graph(key, [&] { fresh_body(k, b, p_eff, Lw); });
+  } else {
+    fresh_body(k, b, p_eff, Lw);
   }
-  eigsvd_from_basis(Qw_.p, Lw, Lw, k);
+  k_last_ = k;
+  read_results(k, false);
   if (prm_.recycle == 1) {
     swap_buf(Qw_, basis_);
     basis_ld_ = Lw;
     basis_cols_ = Lw;
   } else if (prm_.recycle == 2) {
-    basis_.reserve(m_ * (int64_t)k, st_);
+    if (basis_.n < (size_t)(m_ * (int64_t)k)) basis_.reserve(m_ * (int64_t)cap_k_, st_);
     MC_HIP(hipMemcpyAsync(basis_.p, U_.p, m_ * (int64_t)k * sizeof(double),
                           hipMemcpyDeviceToDevice, st_));
     basis_ld_ = k;
@@ -286,20 +435,25 @@ void Solver::fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt) {
   q_ = 0;
 }
 
-void Solver::recycled_svd(int k) {
-  ensure(std::min<int>(k + prm_.s, (int)std::min(m_, n_)), basis_cols_, k);
-  eigsvd_from_basis(basis_.p, basis_ld_, basis_cols_, k);
-}
-
-double Solver::ritz_ratio(int k) {
-  spmm_y(V_.p, k, H1_.p, k, k);                              // R = Y V
-  launch_ritz(m_, k, H1_.p, k, U_.p, k, S_.p, ritz_part_.p, ritz_out_.p, st_);
-  MC_HIP(hipMemcpyAsync(hbuf_, ritz_out_.p, k * sizeof(double),
-                        hipMemcpyDeviceToHost, st_));
-  MC_HIP(hipStreamSynchronize(st_));
-  double worst = 0.0;
-  for (int j = 0; j < k; ++j) worst = std::max(worst, hbuf_[j]);
-  return worst;
+// Recycled SVD from the saved basis (Sec. IV.B); returns the worst Ritz
+// ratio when the guard is on (else 0).
+double Solver::recycled_svd(int k) {
+  const int w = basis_cols_;
+  ensure(std::min<int>(k + prm_.s, (int)std::min(m_, n_)), w, k);
+  const bool ritz = prm_.ritz_tol > 0;
+  auto body = [&] {
+    eig_body(basis_.p, basis_ld_, w, k);
+    if (ritz) ritz_body(k);
+  };
+  if (graphs_ok(w)) {
+    const GraphKey key{2, k, w, (int)basis_ld_, ritz ? 1 : 0, (int64_t)gen_,
+                       (int64_t)(intptr_t)basis_.p, 0};
+    run_graph(key, body);
+  } else {
+    body();
+  }
+  k_last_ = k;
+  return read_results(k, ritz);
 }
 
 void Solver::rsvd(int k, int p, uint32_t step_id, uint32_t attempt) {
@@ -327,10 +481,10 @@ StepInfo Solver::step() {
     bool use_fresh = prm_.recycle == 0 || i_ < prm_.i_reuse ||
                      q_ == prm_.q_reuse || basis_cols_ == 0 || k > basis_cols_;
     if (!use_fresh) {
-      recycled_svd(k);
+      const double ratio = recycled_svd(k);
       ++q_;
       ++info.recycled;
-      if (prm_.ritz_tol > 0 && ritz_ratio(k) > prm_.ritz_tol) {
+      if (prm_.ritz_tol > 0 && ratio > prm_.ritz_tol) {
         use_fresh = true;
         ++info.rejected;
       }
@@ -350,9 +504,14 @@ StepInfo Solver::step() {
   for (int j = 0; j < r; ++j) hs[j] = sig_host_[j] = lastS_[j] - prm_.tau;
   if (r > 0)
     MC_HIP(hipMemcpyAsync(sig_.p, hs, r * sizeof(double), hipMemcpyHostToDevice, st_));
+  // bytes: row, col, invperm (4 each), M, Y in, Y out, Y^T out (8 each), and
+  // the r-wide factor rows of U and V
+  prof.begin(kProfSddmm, (double)nnz_ * (3 * 4 + 4 * 8) + 8.0 * (m_ + n_) * r,
+             2.0 * nnz_ * r, st_);
   launch_sddmm_update<double>(L_, mvals_.p, y_.p, ycsc_.p, U_.p, k_last_, V_.p,
                               k_last_, sig_.p, r, prm_.delta, 1, sdd_part_.p,
                               scal_.p, st_);
+  prof.end(st_);
   MC_HIP(hipMemcpyAsync(hbuf_, scal_.p, sizeof(double), hipMemcpyDeviceToHost, st_));
   MC_HIP(hipStreamSynchronize(st_));
   const double res = std::sqrt(hbuf_[0]) / mnorm_;

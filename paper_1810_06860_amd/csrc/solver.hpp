@@ -1,6 +1,8 @@
 // Host-side state machine of fast SVT (Alg. 6) over the device kernels.
 #pragma once
 
+#include <array>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -13,6 +15,35 @@ struct StepInfo {
   int i = 0, r = 0, k = 0, p = 0, fresh = 0, recycled = 0, rejected = 0;
   int converged = 0;
   double res = 0.0, sigma_max = 0.0;
+};
+
+// Event-based timing of kernel families on the solve's own stream.
+enum ProfFamily : int {
+  kProfSpmmFwd = 0,   // Y X       (CSR)
+  kProfSpmmBwd = 1,   // Y^T X     (CSC)
+  kProfSddmm = 2,     // fused SDDMM + residual + update
+  kProfGram = 3,      // Gram / cross-Gram
+  kProfGemm = 4,      // panel GEMMs
+  kProfChol = 5,      // Cholesky + inverse
+  kProfEig = 6,       // whole eigensolve (kernels + convergence checks)
+  kProfRng = 7,       // Gaussian test matrix
+  kProfCount = 8
+};
+
+struct Profiler {
+  bool on = false;
+  struct Rec { int fam; double bytes, flops; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  double ms[kProfCount] = {}, bytes[kProfCount] = {}, flops[kProfCount] = {};
+  int64_t count[kProfCount] = {};
+  ~Profiler();
+  hipEvent_t ev();
+  void begin(int fam, double bytes, double flops, hipStream_t st);
+  void end(hipStream_t st);
+  void collect();           // synchronises, folds records into the totals
+  void reset();
 };
 
 class Solver {
@@ -54,6 +85,7 @@ class Solver {
   int chol_shifts();
 
   std::string last_error;
+  Profiler prof;
 
  private:
   // workspace sizing
@@ -62,11 +94,19 @@ class Solver {
   void widths(int k, int p, int& b, int& p_eff) const;
 
   void fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt);
-  void recycled_svd(int k);
+  double recycled_svd(int k);
   // eigSVD of B^T = Y^T basis (basis: m x w, leading dim ldb), keep top k;
-  // U = basis Wk, V = B^T Wk S^-1, S on the device and in lastS_.
-  void eigsvd_from_basis(const double* basis, int64_t ldb, int w, int k);
-  double ritz_ratio(int k);
+  // U = basis Wk, V = B^T Wk S^-1, S on the device (kernels only).
+  void eig_body(const double* basis, int64_t ldb, int w, int k);
+  void fresh_body(int k, int b, int p_eff, int Lw);
+  void ritz_body(int k);
+  double read_results(int k, bool ritz);
+  // kernels go to the capture stream while a graph is being recorded
+  hipStream_t ls() const { return capturing_ ? cap_ : st_; }
+  bool graphs_ok(int w) const;
+  using GraphKey = std::array<int64_t, 8>;
+  template <class F> void run_graph(const GraphKey& key, F&& body);
+  void clear_graphs();
   void orth_block(int j, int b, int Lw);
   void cholqr_pass(const double* Hin, int64_t ldin, double* out, int64_t ldo,
                    int b, const int* gate);
@@ -74,7 +114,6 @@ class Solver {
                int Lw, const int* gate);
   void spmm_y(const double* X, int64_t ldx, double* out, int64_t ldo, int b);
   void spmm_yt(const double* X, int64_t ldx, double* out, int64_t ldo, int b);
-  void read_sigma(int k);
 
   int64_t m_, n_, nnz_;
   mc_svt_params prm_;
@@ -89,6 +128,12 @@ class Solver {
       chol_work_, gram_part_, spmm_part_, U_, V_, S_, Sinv_, D_, Wk_, sig_,
       sdd_part_, scal_, ritz_part_, ritz_out_, obs_;
   DevBuf<int> shift_count_, blk_flag_;
+  DevBuf<uint32_t> ctr_;          // (step, attempt) of the Gaussian stream
+  uint32_t* hctr_ = nullptr;      // pinned staging for ctr_
+  std::map<GraphKey, hipGraphExec_t> graphs_;
+  hipStream_t cap_ = nullptr;
+  bool capturing_ = false;
+  uint64_t gen_ = 0;
   int64_t gram_cap_ = 0;
   EigSolver eig_;
   double* hbuf_ = nullptr;       // pinned host scratch

@@ -235,8 +235,9 @@ int build_layout(int64_t m, int64_t n, int64_t nnz, const int64_t* d_rows,
 void build_schedule(const int32_t* ptr, int64_t rows, Schedule& S,
                     hipStream_t st) {
   const int64_t nnz = ptr[rows];
-  const int64_t avg = rows ? ceil_div(nnz, rows) : 0;
-  const int64_t cap = std::max<int64_t>(1024, 8 * avg);
+  // segment length: about 16K segments in flight fill the chip (256 CUs x
+  // several waves), capped so long rows of power-law matrices are split
+  const int64_t cap = std::min<int64_t>(1024, std::max<int64_t>(64, ceil_div(nnz, 16384)));
   std::vector<int4> segs;
   std::vector<int4> fix;
   segs.reserve(rows + 16);
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(256) void spmm_kernel(
     const int32_t* __restrict__ idx, const VT* __restrict__ val,
     const XT* __restrict__ X, int64_t ldx, OT* __restrict__ out, int64_t ldo,
     AT* __restrict__ part, int b) {
-  constexpr int G = 64 / BW;
+  constexpr int G = 64 / BW;       // nonzeros processed side by side
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (wave >= nseg) return;
@@ -335,18 +336,21 @@ __global__ __launch_bounds__(256) void spmm_kernel(
   for (int c0 = 0; c0 < b; c0 += BW) {
     const int col = c0 + c;
     const bool active = col < b;
+    const int colc = active ? col : b - 1;   // in-bounds address, weight 0
     AT acc = 0;
     for (int base = sg.y; base < sg.z; base += 64) {
       const int e = base + lane;
       const bool ok = e < sg.z;
+      // lanes past the segment carry index 0 and value 0
       const int my_idx = ok ? idx[e] : 0;
       const AT my_val = ok ? (AT)val[e] : (AT)0;
-      const int cnt = min(64, sg.z - base);
-      for (int jj = 0; jj < cnt; jj += G) {
-        const int j = jj + g;
-        const int jc = __shfl(my_idx, j);
-        const AT jv = __shfl(my_val, j);
-        if (active && j < cnt) acc += jv * (AT)X[(int64_t)jc * ldx + col];
+      // fixed trip count: the gathers of one chunk are independent, so they
+      // are issued back to back
+#pragma unroll
+      for (int jj = 0; jj < 64; jj += G) {
+        const int jc = __shfl(my_idx, jj + g);
+        const AT jv = __shfl(my_val, jj + g);
+        acc += jv * (AT)X[(int64_t)jc * ldx + colc];
       }
     }
 #pragma unroll

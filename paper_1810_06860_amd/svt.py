@@ -9,8 +9,8 @@ import ctypes as C
 
 import numpy as np
 
-from ._ffi import (MC_EDONE, MC_ENOTCONV, MC_OK, PRECISIONS, MCError, Params,
-                   Result, StepInfo, check, lib)
+from ._ffi import (MC_EDONE, MC_ENOTCONV, MC_OK, PRECISIONS, PROF_FAMILIES,
+                   MCError, Params, ProfEntry, Result, StepInfo, check, lib)
 
 _PARAM_KEYS = [f for f, _ in Params._fields_]
 
@@ -111,6 +111,17 @@ class SVT:
         res = Result()
         check(lib().mc_svt_get_result(self._h, C.byref(res)), self._h)
         return res.as_dict()
+
+    # -- measurement ------------------------------------------------------
+    def profile(self, on=True):
+        check(lib().mc_svt_profile(self._h, int(bool(on))), self._h)
+
+    def get_profile(self):
+        arr = (ProfEntry * len(PROF_FAMILIES))()
+        check(lib().mc_svt_get_profile(self._h, arr, len(PROF_FAMILIES)), self._h)
+        return {name: dict(launches=arr[j].launches, ms=arr[j].ms,
+                           bytes=arr[j].bytes, flops=arr[j].flops)
+                for j, name in enumerate(PROF_FAMILIES)}
 
     # -- outputs ----------------------------------------------------------
     def factors(self):

@@ -134,8 +134,8 @@ def test_cholqr2_orthonormal_same_range(K, N, b, kappa):
     assert np.linalg.norm(Q @ (Q.T @ Qr) - Qr) < 1e-8 * max(1.0, kappa * 1e-8)
 
 
-@pytest.mark.parametrize("L,k", [(5, 3), (21, 5), (32, 32), (84, 11), (130, 40),
-                                 (330, 110)])
+@pytest.mark.parametrize("L,k", [(5, 3), (21, 5), (32, 32), (64, 64), (84, 11),
+                                 (130, 40), (150, 20), (330, 110)])
 def test_syev_matches_eigh(K, L, k):
     rng = np.random.default_rng(L)
     A = rng.standard_normal((4 * L, L)) * np.logspace(0, -3, L)

@@ -91,3 +91,24 @@ def test_svt_full_solve_planted500_vs_exact_oracle():
     assert abs(out["iters"] - ex.iters) <= 3
     M = prob.truth_dense()
     assert np.linalg.norm(Xg - M) / np.linalg.norm(M) < 1e-3
+
+
+def test_graph_replay_matches_eager_launches():
+    # the same solve with captured graphs and with kernel-by-kernel launches:
+    # every step (each graph replayed many times, with host work in between)
+    # must give bit-identical results
+    from paper_1810_06860_amd import SVT
+    prob = synth.planted(300, 240, 5, 0.35, seed_data=31, seed_phi=131)
+    prm = dict(eps=1e-5, i_max=60, recycle=1, i_reuse=15, q_reuse=3)
+    a = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, dict(prm, use_graphs=1))
+    b = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, dict(prm, use_graphs=0))
+    for _ in range(40):
+        ia, ib = a.step(), b.step()
+        assert ia == ib
+        assert np.array_equal(a.sigma(), b.sigma())
+        if ia["converged"]:
+            break
+    Ua, sa, Va = a.factors()
+    Ub, sb, Vb = b.factors()
+    assert np.array_equal(Ua, Ub) and np.array_equal(sa, sb) and np.array_equal(Va, Vb)
+    assert np.array_equal(a.y(), b.y())
