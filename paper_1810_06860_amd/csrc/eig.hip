@@ -39,30 +39,42 @@ __device__ __forceinline__ int sub_index(int bi, int bj, int a) {
   return a < BS ? bi * BS + a : bj * BS + (a - BS);
 }
 
-// Whole eigenproblem in one workgroup (L <= single-workgroup limit): A in
-// LDS (row stride L + 1), V in LDS when it fits too, else in global memory.
-// Cyclic Jacobi with the round-robin ordering of all L indices (a dummy
-// index pads odd L).  A round has two phases: the rotations of its L/2
-// disjoint pairs are computed, then every 2 x 2 block (pair i rows, pair j
-// columns) of A is replaced by R_i^T A_ij R_j in place, the diagonal blocks
-// set exactly to diag(a_pp - t a_pq, a_qq + t a_pq), and V's columns rotated.
+// Whole eigenproblem in one workgroup (L <= single-workgroup limit).
+// Cyclic Jacobi with the round-robin ordering of all L indices (a dummy index
+// pads odd L) on the upper triangle of A in LDS.  A round: (1) the rotations
+// of its L/2 disjoint pairs are computed and logged (c, s) to global memory,
+// (2) every 2 x 2 block (pair i rows, pair j columns, i <= j) of A is
+// replaced by R_i^T A_ij R_j in place, the diagonal blocks set exactly to
+// diag(a_pp - t a_pq, a_qq + t a_pq).  After convergence the eigenvalues are
+// ranked, and the eigenvectors of the k largest are formed by applying the
+// logged rounds in reverse order to the k unit vectors e_j (V = R_1 ... R_N,
+// so V e_j = R_1 (... (R_N e_j))): only k columns are ever rotated.
 constexpr int kSingleMaxPairs = 96;
 constexpr int kSingleThreads = 512;
+constexpr int kSingleMaxSweeps = 40;
 
-template <bool VLDS>
-__global__ __launch_bounds__(kSingleThreads) void jac_single_kernel(
-    int L, const double* __restrict__ G, int64_t ldg, double* __restrict__ Aout,
-    double* __restrict__ Vg, double tol_rel, double tol_abs_fac,
+__device__ __forceinline__ int rr_pos(int j, int rr, int n2) {
+  if (j == 0) return 0;
+  int x = j - 1 + rr;            // < 2 (n2 - 1)
+  if (x >= n2 - 1) x -= n2 - 1;
+  return 1 + x;
+}
+
+__global__ __launch_bounds__(kSingleThreads) void jac_topk_kernel(
+    int L, const double* __restrict__ G, int64_t ldg, int k,
+    double* __restrict__ S_out, double* __restrict__ D_out,
+    double* __restrict__ W_out, int64_t ldw, double2* __restrict__ cs_log,
+    int* __restrict__ rr_log, double tol_rel, double tol_abs_fac,
     int* __restrict__ sweeps_out) {
   extern __shared__ double lds[];
   const int ld = L + 1;
-  double* A = lds;
-  double* V = VLDS ? lds + (size_t)L * ld : Vg;
-  const int ldv = VLDS ? ld : L;
+  double* A = lds;                 // upper triangle: A[min * ld + max]
   __shared__ int P[kSingleMaxPairs], Q[kSingleMaxPairs];
   __shared__ double Cc[kSingleMaxPairs], Ss[kSingleMaxPairs];
   __shared__ double D0[kSingleMaxPairs], D1[kSingleMaxPairs];
   __shared__ double red[kSingleThreads];
+  __shared__ double dsh[2 * kSingleMaxPairs];
+  __shared__ int idx[2 * kSingleMaxPairs];
   const int tid = threadIdx.x;
   const int tx = tid % 32, ty = tid / 32;          // 32 x 16 thread grid
   const int n2 = L + (L & 1);
@@ -70,33 +82,32 @@ __global__ __launch_bounds__(kSingleThreads) void jac_single_kernel(
   double ss = 0.0;
   for (int t = tid; t < L * L; t += kSingleThreads) {
     const int i = t / L, j = t % L;
-    const double x = G[(int64_t)i * ldg + j], y = G[(int64_t)j * ldg + i];
-    const double a = (i == j) ? x : 0.5 * (x + y);
+    if (i > j) continue;
+    const double a = (i == j) ? G[(int64_t)i * ldg + i]
+                              : 0.5 * (G[(int64_t)i * ldg + j] + G[(int64_t)j * ldg + i]);
     A[i * ld + j] = a;
-    ss += a * a;
-    V[(int64_t)i * ldv + j] = (i == j) ? 1.0 : 0.0;
+    ss += (i == j) ? a * a : 2.0 * a * a;
   }
   red[tid] = ss;
   __syncthreads();
-  for (int s = kSingleThreads / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] += red[tid + s];
+  for (int w = kSingleThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
     __syncthreads();
   }
   const double tol_abs = tol_abs_fac * sqrt(red[0]);
-  int sweep = 0;
-  for (; sweep < 60; ++sweep) {
+  const double tol_abs2 = tol_abs * tol_abs, tol_rel2 = tol_rel * tol_rel;
+  int nlog = 0, sweep = 0;
+  for (; sweep < kSingleMaxSweeps; ++sweep) {
     int swept = 0;
     for (int rr = 0; rr < n2 - 1; ++rr) {
       int mine = 0;
       if (tid < np) {
-        int p = tid == 0 ? 0 : 1 + ((tid - 1 + rr) % (n2 - 1));
-        const int jj = n2 - 1 - tid;
-        int q = jj == 0 ? 0 : 1 + ((jj - 1 + rr) % (n2 - 1));
+        int p = rr_pos(tid, rr, n2), q = rr_pos(n2 - 1 - tid, rr, n2);
         if (p > q) { const int x = p; p = q; q = x; }
         double c = 1.0, s = 0.0, d0 = 0.0, d1 = 0.0;
         if (q < L) {
           const double apq = A[p * ld + q], app = A[p * ld + p], aqq = A[q * ld + q];
-          if (fabs(apq) > fmax(tol_rel * sqrt(fabs(app * aqq)), tol_abs)) {
+          if (apq * apq > fmax(tol_rel2 * fabs(app * aqq), tol_abs2)) {
             const double theta = (aqq - app) / (2.0 * apq);
             const double tt =
                 (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
@@ -113,10 +124,12 @@ __global__ __launch_bounds__(kSingleThreads) void jac_single_kernel(
         Ss[tid] = s;
         D0[tid] = d0;
         D1[tid] = d1;
+        cs_log[(int64_t)nlog * np + tid] = make_double2(c, s);
       }
       if (!__syncthreads_or(mine)) continue;
       swept = 1;
-      // A <- R^T A R, one 2 x 2 block (pair ti rows, pair tj cols) per item
+      if (tid == 0) rr_log[nlog] = rr;
+      ++nlog;
       for (int ti = ty; ti < np; ti += kSingleThreads / 32) {
         const int p1 = P[ti], q1 = Q[ti];
         const double c1 = Cc[ti], s1 = Ss[ti];
@@ -128,51 +141,73 @@ __global__ __launch_bounds__(kSingleThreads) void jac_single_kernel(
             A[p1 * ld + p1] = D0[ti];
             A[q1 * ld + q1] = D1[ti];
             A[p1 * ld + q1] = 0.0;
-            A[q1 * ld + p1] = 0.0;
             continue;
           }
           const int p2 = P[tj], q2 = Q[tj];
           const double c2 = Cc[tj];
           const bool vq1 = q1 < L, vq2 = q2 < L;
-          double a = A[p1 * ld + p2];
-          double b = vq2 ? A[p1 * ld + q2] : 0.0;
-          double c = vq1 ? A[q1 * ld + p2] : 0.0;
-          double d = (vq1 && vq2) ? A[q1 * ld + q2] : 0.0;
-          // rows (pair ti)
-          double a1 = c1 * a - s1 * c, b1 = c1 * b - s1 * d;
-          double c1r = s1 * a + c1 * c, d1r = s1 * b + c1 * d;
-          // cols (pair tj)
-          a = c2 * a1 - s2 * b1;
-          b = s2 * a1 + c2 * b1;
-          c = c2 * c1r - s2 * d1r;
-          d = s2 * c1r + c2 * d1r;
-          A[p1 * ld + p2] = a;
-          A[p2 * ld + p1] = a;
-          if (vq2) { A[p1 * ld + q2] = b; A[q2 * ld + p1] = b; }
-          if (vq1) { A[q1 * ld + p2] = c; A[p2 * ld + q1] = c; }
-          if (vq1 && vq2) { A[q1 * ld + q2] = d; A[q2 * ld + q1] = d; }
-        }
-      }
-      // V <- V R
-      for (int j = ty; j < L; j += kSingleThreads / 32) {
-        for (int t = tx; t < np; t += 32) {
-          const double s = Ss[t];
-          if (s == 0.0) continue;
-          const int p = P[t], q = Q[t];
-          const double c = Cc[t];
-          const double a = V[(int64_t)j * ldv + p], b = V[(int64_t)j * ldv + q];
-          V[(int64_t)j * ldv + p] = c * a - s * b;
-          V[(int64_t)j * ldv + q] = s * a + c * b;
+          // upper-triangle addresses of the four entries
+          const int ia = p1 < p2 ? p1 * ld + p2 : p2 * ld + p1;
+          const int ib = p1 < q2 ? p1 * ld + q2 : q2 * ld + p1;
+          const int ic = q1 < p2 ? q1 * ld + p2 : p2 * ld + q1;
+          const int id = q1 < q2 ? q1 * ld + q2 : q2 * ld + q1;
+          double a = A[ia];
+          double b = vq2 ? A[ib] : 0.0;
+          double c = vq1 ? A[ic] : 0.0;
+          double d = (vq1 && vq2) ? A[id] : 0.0;
+          const double a1 = c1 * a - s1 * c, b1 = c1 * b - s1 * d;
+          const double c1r = s1 * a + c1 * c, d1r = s1 * b + c1 * d;
+          A[ia] = c2 * a1 - s2 * b1;
+          if (vq2) A[ib] = s2 * a1 + c2 * b1;
+          if (vq1) A[ic] = c2 * c1r - s2 * d1r;
+          if (vq1 && vq2) A[id] = s2 * c1r + c2 * d1r;
         }
       }
       __syncthreads();
     }
     if (!swept) break;
   }
-  for (int j = tid; j < L; j += kSingleThreads) Aout[(int64_t)j * L + j] = A[j * ld + j];
-  if (VLDS)
-    for (int t = tid; t < L * L; t += kSingleThreads) Vg[t] = V[(t / L) * ld + (t % L)];
   if (tid == 0 && sweeps_out) *sweeps_out = sweep + 1;
+  // eigenvalues: rank by (value descending, index ascending)
+  for (int j = tid; j < L; j += kSingleThreads) dsh[j] = A[j * ld + j];
+  __syncthreads();
+  for (int j = tid; j < L; j += kSingleThreads) {
+    const double dj = dsh[j];
+    int rank = 0;
+    for (int i = 0; i < L; ++i) rank += (dsh[i] > dj) || (dsh[i] == dj && i < j);
+    if (D_out) D_out[rank] = dj;
+    if (rank < k) {
+      idx[rank] = j;
+      S_out[rank] = sqrt(fmax(dj, 0.0));
+    }
+  }
+  __syncthreads();
+  // eigenvectors of the k largest: replay the logged rounds in reverse on
+  // Z = [e_idx[0] .. e_idx[k-1]] (L x k, row stride k, in A's space)
+  double* Z = lds;
+  for (int t = tid; t < L * k; t += kSingleThreads) {
+    const int i = t / k, c = t % k;
+    Z[t] = (i == idx[c]) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int r = nlog - 1; r >= 0; --r) {
+    const int rr = rr_log[r];
+    const double2* cs = cs_log + (int64_t)r * np;
+    for (int t = ty; t < np; t += kSingleThreads / 32) {
+      const double2 v = cs[t];
+      if (v.y == 0.0) continue;
+      int p = rr_pos(t, rr, n2), q = rr_pos(n2 - 1 - t, rr, n2);
+      if (p > q) { const int x = p; p = q; q = x; }
+      for (int c = tx; c < k; c += 32) {
+        const double zp = Z[p * k + c], zq = Z[q * k + c];
+        Z[p * k + c] = v.x * zp + v.y * zq;
+        Z[q * k + c] = -v.y * zp + v.x * zq;
+      }
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < L * k; t += kSingleThreads)
+    W_out[(int64_t)(t / k) * ldw + (t % k)] = Z[t];
 }
 
 __global__ void jac_init_kernel(int L, int Lp, const double* __restrict__ G,
@@ -444,6 +479,13 @@ void EigSolver::reserve(int L, hipStream_t st) {
   V.reserve((size_t)Lp * Lp, st);
   J.reserve((size_t)(nb / 2) * SP * SP, st);
   Sd.reserve((size_t)(nb / 2) * SP * SP, st);
+  {
+    // rotation log of the one-workgroup solver: every round of every sweep
+    const int n2 = L + (L & 1);
+    const size_t rounds = (size_t)kSingleMaxSweeps * std::max(n2 - 1, 1);
+    cslog.reserve(2 * rounds * std::max(n2 / 2, 1), st);
+    rrlog.reserve(rounds, st);
+  }
   flags.reserve(kMaxSweeps * 64 + 8, st);
   scal.reserve(4, st);
   if (!hflags) MC_HIP(hipHostMalloc((void**)&hflags, sizeof(int) * 64));
@@ -454,6 +496,8 @@ EigSolver::~EigSolver() {
 }
 
 namespace {
+constexpr size_t kStaticLdsReserve = 12288;   // static LDS of jac_topk_kernel
+
 // Largest dynamic LDS one workgroup may use (queried once; gfx950 allows more
 // than the 64 KB default once the kernel attribute is raised).
 size_t lds_limit() {
@@ -471,10 +515,9 @@ size_t lds_limit() {
     }
   }
   lim = (size_t)v;
-  for (const void* f : {(const void*)jac_single_kernel<true>,
-                        (const void*)jac_single_kernel<false>}) {
+  for (const void* f : {(const void*)jac_topk_kernel}) {
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(lim - 1024)) != hipSuccess) {
+                            (int)(lim - kStaticLdsReserve)) != hipSuccess) {
       (void)hipGetLastError();
       lim = 65536;
     }
@@ -484,12 +527,31 @@ size_t lds_limit() {
 }  // namespace
 
 int EigSolver::single_max() {
-  const size_t lim = lds_limit() - 1024;
+  // dynamic LDS holds A (L x (L + 1)); the kernel's own arrays take the rest
+  const size_t lim = lds_limit() - kStaticLdsReserve;
   int L = 1;
   while (L + 1 <= 2 * kSingleMaxPairs &&
          (size_t)(L + 1) * (L + 2) * sizeof(double) <= lim)
     ++L;
   return L;
+}
+
+void EigSolver::solve_topk(int L, const double* G, int64_t ldg, int k, double* S,
+                           double* D, double* Wk, int64_t ldw, hipStream_t st) {
+  if (L <= single_max()) {
+    reserve(L, st);
+    this->L = L;
+    this->Lp = L;
+    const size_t bytes = (size_t)L * (L + 1) * sizeof(double);
+    hipLaunchKernelGGL(jac_topk_kernel, dim3(1), dim3(kSingleThreads), bytes, st, L,
+                       G, ldg, k, S, D, Wk, ldw, (double2*)cslog.p, rrlog.p,
+                       4e-15, 1e-14, flags.p);
+    MC_CHECK_LAUNCH();
+    sweeps = -1;     // known on the device only
+    return;
+  }
+  solve(L, G, ldg, st);
+  select_topk(k, S, D, Wk, ldw, st);
 }
 
 int EigSolver::solve(int L, const double* G, int64_t ldg, hipStream_t st) {
@@ -499,24 +561,6 @@ int EigSolver::solve(int L, const double* G, int64_t ldg, hipStream_t st) {
   const double tol_rel = 4e-15;
   const double tol_abs_fac = 1e-14;
   this->L = L;
-  if (L <= single_max()) {
-    this->Lp = L;
-    const size_t ld = (size_t)L + 1;
-    const size_t a_bytes = (size_t)L * ld * sizeof(double);
-    const bool vlds = 2 * a_bytes <= lds_limit() - 1024;
-    const size_t bytes = vlds ? 2 * a_bytes : a_bytes;
-    if (vlds)
-      hipLaunchKernelGGL(jac_single_kernel<true>, dim3(1), dim3(kSingleThreads),
-                         bytes, st, L, G, ldg, A.p, V.p, tol_rel, tol_abs_fac,
-                         flags.p);
-    else
-      hipLaunchKernelGGL(jac_single_kernel<false>, dim3(1), dim3(kSingleThreads),
-                         bytes, st, L, G, ldg, A.p, V.p, tol_rel, tol_abs_fac,
-                         flags.p);
-    MC_CHECK_LAUNCH();
-    sweeps = -1;     // known on the device only
-    return 0;
-  }
   const int Lp = (int)round_up(std::max(L, 1), SP);
   const int nb = Lp / BS;
   const int npair = nb / 2;

@@ -221,8 +221,7 @@ mc_status mc_k_syev(int32_t L, const double* G, int32_t k, void* stream,
     D.reserve(L, st);
     Wk.reserve((int64_t)L * k, st);
     mcsvt::EigSolver eig;
-    eig.solve(L, dG.p, L, st);
-    eig.select_topk(k, S.p, D.p, Wk.p, k, st);
+    eig.solve_topk(L, dG.p, L, k, S.p, D.p, Wk.p, k, st);
     download(evals, D.p, k, st);
     download(W, Wk.p, (int64_t)L * k, st);
     MC_HIP(hipStreamSynchronize(st));

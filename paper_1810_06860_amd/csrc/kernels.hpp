@@ -114,7 +114,8 @@ void launch_ritz(int64_t m, int k, const double* R, int64_t ldr, const double* U
 // Block-Jacobi symmetric eigensolver (FP64).
 struct EigSolver {
   static constexpr int kMaxSweeps = 30;
-  DevBuf<double> A, V, J, Sd, scal;
+  DevBuf<double> A, V, J, Sd, scal, cslog;
+  DevBuf<int> rrlog;
   DevBuf<int> flags;
   int* hflags = nullptr;
   int L = 0, Lp = 0, sweeps = 0;
@@ -126,8 +127,12 @@ struct EigSolver {
   static int single_max();
   // Jacobi sweeps of the last solve (synchronises for the one-workgroup path)
   int device_sweeps(hipStream_t st);
-  // top-k (descending): S = sqrt(max(lambda, 0)), Wk (L x k, ldw) vectors,
-  // D (optional, L) all eigenvalues descending
+  // eigenpairs of the k largest eigenvalues (descending): S = sqrt(max(
+  // lambda, 0)), Wk (L x k, ldw) vectors, D (optional, L) all eigenvalues
+  // descending; one kernel without host round trips when L <= single_max()
+  void solve_topk(int L, const double* G, int64_t ldg, int k, double* S,
+                  double* D, double* Wk, int64_t ldw, hipStream_t st);
+  // top-k of the last solve() (block path)
   void select_topk(int k, double* S, double* D, double* Wk, int64_t ldw,
                    hipStream_t st);
 };

@@ -334,8 +334,7 @@ void Solver::eig_body(const double* basis, int64_t ldb, int w, int k) {
                               gram_part_.p, gram_cap_, ls()); // G = B B^T
   prof.end(ls());
   prof.begin(kProfEig, 16.0 * w * w, 0.0, ls());
-  eig_.solve(w, G_.p, w, ls());
-  eig_.select_topk(k, S_.p, D_.p, Wk_.p, k, ls());
+  eig_.solve_topk(w, G_.p, w, k, S_.p, D_.p, Wk_.p, k, ls());
   prof.end(ls());
   prof.begin(kProfGemm, 8.0 * (m_ + n_) * (w + k), 2.0 * (m_ + n_) * w * k, ls());
   launch_panel_gemm<double, double>(m_, w, k, basis, ldb, Wk_.p, k, 1.0, nullptr,
