@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -9,7 +10,7 @@
 #include "solver.hpp"
 
 struct mc_svt {
-  mcsvt::Solver* solver = nullptr;
+  std::unique_ptr<mcsvt::Solver> solver;
   std::string err;
 };
 
@@ -210,17 +211,14 @@ mc_status mc_svt_init(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
     std::vector<int64_t> expanded = coo_rows(m, nnz, rows, is_csr);
     const int64_t* r = is_csr ? expanded.data() : rows;
     h = new mc_svt();
-    h->solver = new mcsvt::Solver(m, n, nnz, prm, (hipStream_t)stream);
+    h->solver = mcsvt::make_solver(m, n, nnz, prm, (hipStream_t)stream);
     const int s = h->solver->init(r, cols, vals, true);
     if (s == mcsvt::kERANGE) throw mcsvt::Error(s, "index out of range");
     if (s == mcsvt::kEDUP) throw mcsvt::Error(s, "duplicate cell in Phi");
     if (s != mcsvt::kOK) throw mcsvt::Error(s, "invalid input");
   });
   if (st != MC_OK) {
-    if (h) {
-      delete h->solver;
-      delete h;
-    }
+    delete h;
     return st;
   }
   *out = h;
@@ -357,10 +355,7 @@ mc_status mc_svt_get_profile(mc_svt_t h, mc_prof_entry* out, int32_t cap) {
 
 mc_status mc_svt_destroy(mc_svt_t h) {
   if (!h) return MC_OK;
-  mc_status st = guarded(nullptr, [&] {
-    delete h->solver;
-    h->solver = nullptr;
-  });
+  mc_status st = guarded(nullptr, [&] { h->solver.reset(); });
   delete h;
   return st;
 }
@@ -390,7 +385,8 @@ mc_status mc_rsvd_bki(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
     prm.seed = seed;
     prm.precision = precision;
     prm.p_init = prm.p_min = prm.p_max = p;
-    mcsvt::Solver solver(m, n, nnz, prm, (hipStream_t)stream);
+    auto holder = mcsvt::make_solver(m, n, nnz, prm, (hipStream_t)stream);
+    mcsvt::Solver& solver = *holder;
     const int st = solver.init(rows, cols, vals, false);
     if (st == mcsvt::kERANGE) throw mcsvt::Error(st, "index out of range");
     if (st == mcsvt::kEDUP) throw mcsvt::Error(st, "duplicate cell");

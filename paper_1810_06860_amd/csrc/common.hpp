@@ -75,6 +75,30 @@ struct DevBuf {
   size_t bytes() const { return n * sizeof(T); }
 };
 
+// bfloat16 storage (1 sign, 8 exponent, 7 mantissa bits): the upper half of
+// an IEEE binary32; conversion from float rounds to nearest, ties to even.
+struct bf16_t {
+  uint16_t bits;
+  __host__ __device__ bf16_t() : bits(0) {}
+  __host__ __device__ explicit bf16_t(float f) {
+    uint32_t u;
+    __builtin_memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) {
+      bits = (uint16_t)((u >> 16) | 0x0040u);     // quiet NaN
+    } else {
+      u += 0x7FFFu + ((u >> 16) & 1u);
+      bits = (uint16_t)(u >> 16);
+    }
+  }
+  __host__ __device__ explicit bf16_t(double d) : bf16_t((float)d) {}
+  __host__ __device__ operator float() const {
+    const uint32_t u = (uint32_t)bits << 16;
+    float f;
+    __builtin_memcpy(&f, &u, 4);
+    return f;
+  }
+};
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
 

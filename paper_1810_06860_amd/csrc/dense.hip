@@ -211,8 +211,9 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(
 
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
 
-__global__ void copy_gated_kernel(int64_t rows, int cols, const double* __restrict__ src,
-                                  int64_t lds_, double* __restrict__ dst, int64_t ldd,
+template <class T>
+__global__ void copy_gated_kernel(int64_t rows, int cols, const T* __restrict__ src,
+                                  int64_t lds_, T* __restrict__ dst, int64_t ldd,
                                   const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -229,9 +230,10 @@ __global__ void recip_kernel(int k, const double* __restrict__ S,
 }
 
 // partial[blk * k + j] = sum over the block's rows of (R_ij - S_j U_ij)^2
+template <class T>
 __global__ __launch_bounds__(256) void ritz_partial_kernel(
-    int64_t m, int k, const double* __restrict__ R, int64_t ldr,
-    const double* __restrict__ U, int64_t ldu, const double* __restrict__ S,
+    int64_t m, int k, const T* __restrict__ R, int64_t ldr,
+    const T* __restrict__ U, int64_t ldu, const double* __restrict__ S,
     int64_t rows_per_block, double* __restrict__ partial) {
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
   const int64_t r1 = min(m, r0 + rows_per_block);
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(256) void ritz_partial_kernel(
     const double s = S[j];
     double acc = 0.0;
     for (int64_t i = r0; i < r1; ++i) {
-      const double d = R[i * ldr + j] - s * U[i * ldu + j];
+      const double d = (double)R[i * ldr + j] - s * (double)U[i * ldu + j];
       acc += d * d;
     }
     partial[(int64_t)blockIdx.x * k + j] = acc;
@@ -339,14 +341,19 @@ void launch_set_int(int* p, int v, hipStream_t st) {
   MC_CHECK_LAUNCH();
 }
 
-void launch_copy_gated(int64_t rows, int cols, const double* src, int64_t lds_,
-                       double* dst, int64_t ldd, const int* gate, hipStream_t st) {
+template <class T>
+void launch_copy_gated(int64_t rows, int cols, const T* src, int64_t lds_, T* dst,
+                       int64_t ldd, const int* gate, hipStream_t st) {
   const int64_t tot = rows * cols;
   if (tot <= 0) return;
-  hipLaunchKernelGGL(copy_gated_kernel, dim3((unsigned)ceil_div(tot, 256)), dim3(256),
-                     0, st, rows, cols, src, lds_, dst, ldd, gate);
+  hipLaunchKernelGGL(copy_gated_kernel<T>, dim3((unsigned)ceil_div(tot, 256)),
+                     dim3(256), 0, st, rows, cols, src, lds_, dst, ldd, gate);
   MC_CHECK_LAUNCH();
 }
+template void launch_copy_gated<double>(int64_t, int, const double*, int64_t,
+                                        double*, int64_t, const int*, hipStream_t);
+template void launch_copy_gated<float>(int64_t, int, const float*, int64_t, float*,
+                                       int64_t, const int*, hipStream_t);
 
 void launch_recip(int k, const double* S, double* out, hipStream_t st) {
   hipLaunchKernelGGL(recip_kernel, dim3((unsigned)ceil_div(k, 128)), dim3(128), 0,
@@ -356,17 +363,24 @@ void launch_recip(int k, const double* S, double* out, hipStream_t st) {
 
 int ritz_blocks(int64_t m) { return (int)std::min<int64_t>(256, std::max<int64_t>(1, ceil_div(m, 64))); }
 
-void launch_ritz(int64_t m, int k, const double* R, int64_t ldr, const double* U,
+template <class T>
+void launch_ritz(int64_t m, int k, const T* R, int64_t ldr, const T* U,
                  int64_t ldu, const double* S, double* partial, double* out,
                  hipStream_t st) {
   const int nblk = ritz_blocks(m);
   const int64_t rpb = ceil_div(m, nblk);
-  hipLaunchKernelGGL(ritz_partial_kernel, dim3(nblk), dim3(256), 0, st, m, k, R,
+  hipLaunchKernelGGL(ritz_partial_kernel<T>, dim3(nblk), dim3(256), 0, st, m, k, R,
                      ldr, U, ldu, S, rpb, partial);
   MC_CHECK_LAUNCH();
   hipLaunchKernelGGL(ritz_reduce_kernel, dim3((unsigned)ceil_div(k, 128)),
                      dim3(128), 0, st, nblk, k, partial, S, out);
   MC_CHECK_LAUNCH();
 }
+template void launch_ritz<double>(int64_t, int, const double*, int64_t,
+                                  const double*, int64_t, const double*, double*,
+                                  double*, hipStream_t);
+template void launch_ritz<float>(int64_t, int, const float*, int64_t, const float*,
+                                 int64_t, const double*, double*, double*,
+                                 hipStream_t);
 
 }  // namespace mcsvt

@@ -203,7 +203,7 @@ mc_status mc_k_cholqr2(int64_t N, int32_t b, const double* H, void* stream,
       if (pass < 2) std::swap(in, outp);
     }
     // after the loop `in` holds pass 2's result; pass 3 (if it ran) wrote outp
-    mcsvt::launch_copy_gated(N, b, outp, b, in, b, flag.p, st);
+    mcsvt::launch_copy_gated<double>(N, b, outp, b, in, b, flag.p, st);
     download(Q, in, N * b, st);
     MC_HIP(hipStreamSynchronize(st));
   });
@@ -266,8 +266,9 @@ mc_status mc_k_sddmm(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
     } else {
       MC_HIP(hipMemsetAsync(dx.p, 0, nnz * sizeof(double), st));
     }
-    mcsvt::launch_sddmm_update<double>(L, m_csr.p, y_csr.p, ycsc.p, dU.p, r, dV.p,
-                                       r, dsig.p, r, delta, 1, part.p, scal.p, st);
+    mcsvt::launch_sddmm_update<double, double, double, double>(
+        L, m_csr.p, y_csr.p, (double*)nullptr, ycsc.p, (double*)nullptr,
+        (double*)nullptr, dU.p, r, dV.p, r, dsig.p, r, delta, 1, part.p, scal.p, st);
     mcsvt::launch_scatter(nnz, L.order.p, y_csr.p, dy.p, st);
     download(x, dx.p, nnz, st);
     download(y_new, dy.p, nnz, st);

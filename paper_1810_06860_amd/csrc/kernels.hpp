@@ -63,11 +63,13 @@ void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
                  AT* part, hipStream_t st);
 
 int64_t sddmm_partials(int64_t nnz);
-template <class FT>
-void launch_sddmm_update(const Layout& L, const double* mvals, double* y,
-                         double* ycsc, const FT* U, int64_t ldu, const FT* V,
-                         int64_t ldv, const double* sig, int r, double delta,
-                         int apply, double* partial, double* out_sum,
+// FT factor type, AT accumulator, VT / WT types of the operator copies of Y
+// (Krylov / Rayleigh-Ritz products); null copies are skipped
+template <class FT, class AT, class VT, class WT>
+void launch_sddmm_update(const Layout& L, const double* mvals, double* y, VT* yv,
+                         VT* ycv, WT* yw, WT* ycw, const FT* U, int64_t ldu,
+                         const FT* V, int64_t ldv, const double* sig, int r,
+                         double delta, int apply, double* partial, double* out_sum,
                          hipStream_t st);
 template <class FT>
 void launch_eval_observed(const Layout& L, const FT* U, int64_t ldu,
@@ -101,13 +103,15 @@ void launch_chol_inv(int b, const double* G, int64_t ldg, double* Rinv,
                      hipStream_t st, int* flag = nullptr,
                      const int* gate = nullptr);
 void launch_set_int(int* p, int v, hipStream_t st);
-void launch_copy_gated(int64_t rows, int cols, const double* src, int64_t lds_,
-                       double* dst, int64_t ldd, const int* gate, hipStream_t st);
+template <class T>
+void launch_copy_gated(int64_t rows, int cols, const T* src, int64_t lds_, T* dst,
+                       int64_t ldd, const int* gate, hipStream_t st);
 
 void launch_recip(int k, const double* S, double* out, hipStream_t st);
 // out[j] = ||R_j - S_j U_j|| / S_j  (Ritz residual ratios, k columns)
 int ritz_blocks(int64_t m);
-void launch_ritz(int64_t m, int k, const double* R, int64_t ldr, const double* U,
+template <class T>
+void launch_ritz(int64_t m, int k, const T* R, int64_t ldr, const T* U,
                  int64_t ldu, const double* S, double* partial, double* out,
                  hipStream_t st);
 

@@ -3,6 +3,7 @@
 
 #include <array>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -46,24 +47,31 @@ struct Profiler {
   void reset();
 };
 
+// The control of Alg. 6 (rank search, adaptive p, recycling gate, Ritz
+// guard, stop test) -- independent of the arithmetic precision.  The device
+// work of one SVD call and of the SDDMM update is supplied by SolverT.
 class Solver {
  public:
   Solver(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& prm,
          hipStream_t st);
-  ~Solver();
+  virtual ~Solver();
 
   // Phi and M_Phi from host arrays (COO rows, int32 cols).  Returns a status.
-  int init(const int64_t* rows, const int32_t* cols, const double* vals,
-           bool scale_for_svt);
+  virtual int init(const int64_t* rows, const int32_t* cols, const double* vals,
+                   bool scale_for_svt) = 0;
   StepInfo step();
   // truncated SVD of the current operator: one rSVD-BKI call (Alg. 5)
-  void rsvd(int k, int p, uint32_t step_id, uint32_t attempt);
+  void rsvd(int k, int p, uint32_t step_id, uint32_t attempt) {
+    fresh_svd(k, p, step_id, attempt);
+  }
 
   // results
-  void get_factors(double* U, double* sig, double* V, int64_t ldu, int64_t ldv);
-  void get_rsvd(double* U, double* S, double* V);
-  void get_observed(double* x_phi);
-  void get_y(double* y_host);
+  virtual void get_factors(double* U, double* sig, double* V, int64_t ldu,
+                           int64_t ldv) = 0;
+  virtual void get_rsvd(double* U, double* S, double* V) = 0;
+  virtual void get_observed(double* x_phi) = 0;
+  virtual void get_y(double* y_host) = 0;
+  virtual int chol_shifts() = 0;
 
   const mc_svt_params& params() const { return prm_; }
   int64_t m() const { return m_; }
@@ -81,69 +89,32 @@ class Solver {
   int rejected_total() const { return rejected_total_; }
   const std::vector<double>& last_sigma() const { return lastS_; }
   hipStream_t stream() const { return st_; }
-  int eig_sweeps() const { return eig_.sweeps; }
-  int chol_shifts();
 
   std::string last_error;
   Profiler prof;
 
- private:
-  // workspace sizing
-  void ensure(int bmax, int Lmax, int kmax);
-  int kcap() const { return kcap_; }
+ protected:
+  // one rSVD-BKI call: sets lastS_ (k, descending), k_last_, the recycling
+  // basis, q_ = 0
+  virtual void fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt) = 0;
+  // one recycled SVD from the saved basis: sets lastS_, k_last_; returns the
+  // worst Ritz ratio when the guard is on (else 0)
+  virtual double recycled_svd(int k) = 0;
+  // SDDMM + update with X = U[:, :r] diag(sig_host_) V[:, :r]^T; returns the
+  // sum of squared residuals on Phi
+  virtual double sddmm(int r) = 0;
   void widths(int k, int p, int& b, int& p_eff) const;
-
-  void fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt);
-  double recycled_svd(int k);
-  // eigSVD of B^T = Y^T basis (basis: m x w, leading dim ldb), keep top k;
-  // U = basis Wk, V = B^T Wk S^-1, S on the device (kernels only).
-  void eig_body(const double* basis, int64_t ldb, int w, int k);
-  void fresh_body(int k, int b, int p_eff, int Lw);
-  void ritz_body(int k);
-  double read_results(int k, bool ritz);
-  // kernels go to the capture stream while a graph is being recorded
-  hipStream_t ls() const { return capturing_ ? cap_ : st_; }
-  bool graphs_ok(int w) const;
-  using GraphKey = std::array<int64_t, 8>;
-  template <class F> void run_graph(const GraphKey& key, F&& body);
-  void clear_graphs();
-  void orth_block(int j, int b, int Lw);
-  void cholqr_pass(const double* Hin, int64_t ldin, double* out, int64_t ldo,
-                   int b, const int* gate);
-  void project(const double* Hin, int64_t ldin, double* Hout, int jb, int b,
-               int Lw, const int* gate);
-  void spmm_y(const double* X, int64_t ldx, double* out, int64_t ldo, int b);
-  void spmm_yt(const double* X, int64_t ldx, double* out, int64_t ldo, int b);
 
   int64_t m_, n_, nnz_;
   mc_svt_params prm_;
   hipStream_t st_;
   int kcap_ = 1;
 
-  Layout L_;
-  DevBuf<double> mvals_, y_, ycsc_;
-  // workspace
-  int cap_b_ = 0, cap_L_ = 0, cap_k_ = 0;
-  DevBuf<double> omega_, Qw_, basis_, H1_, H2_, Z_, Bt_, G_, Cg_, Rinv_,
-      chol_work_, gram_part_, spmm_part_, U_, V_, S_, Sinv_, D_, Wk_, sig_,
-      sdd_part_, scal_, ritz_part_, ritz_out_, obs_;
-  DevBuf<int> shift_count_, blk_flag_;
-  DevBuf<uint32_t> ctr_;          // (step, attempt) of the Gaussian stream
-  uint32_t* hctr_ = nullptr;      // pinned staging for ctr_
-  std::map<GraphKey, hipGraphExec_t> graphs_;
-  hipStream_t cap_ = nullptr;
-  bool capturing_ = false;
-  uint64_t gen_ = 0;
-  int64_t gram_cap_ = 0;
-  EigSolver eig_;
-  double* hbuf_ = nullptr;       // pinned host scratch
-  size_t hbuf_n_ = 0;
-
   // Alg. 6 state
   int i_ = 0, r_ = 0, q_ = 0, p_ = 3, streak_ = 0;
   int basis_cols_ = 0;
   int64_t basis_ld_ = 0;
-  int k_last_ = 0;              // columns of U_, V_, S_ (last SVD)
+  int k_last_ = 0;              // columns of U, V, S of the last SVD call
   std::vector<double> err_hist_;
   std::vector<double> lastS_;
   std::vector<double> sig_host_;
@@ -151,6 +122,10 @@ class Solver {
   double c_ = 0.0, norm2_ = 0.0, mnorm_ = 0.0;
   int fresh_total_ = 0, recycled_total_ = 0, rejected_total_ = 0;
 };
+
+// FP64, FP32 or BF16-value solver according to prm.precision
+std::unique_ptr<Solver> make_solver(int64_t m, int64_t n, int64_t nnz,
+                                    const mc_svt_params& prm, hipStream_t st);
 
 void resolve_params(int64_t m, int64_t n, int64_t nnz, mc_svt_params& p);
 size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz,

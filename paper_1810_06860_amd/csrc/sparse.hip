@@ -289,6 +289,8 @@ void launch_cast(int64_t n, const S* src, D* dst, hipStream_t st) {
 }
 template void launch_cast<double, float>(int64_t, const double*, float*, hipStream_t);
 template void launch_cast<float, double>(int64_t, const float*, double*, hipStream_t);
+template void launch_cast<double, bf16_t>(int64_t, const double*, bf16_t*, hipStream_t);
+template void launch_cast<double, double>(int64_t, const double*, double*, hipStream_t);
 
 template <class T>
 void launch_gather(int64_t nnz, const int32_t* idx, const T* src, T* dst,
@@ -414,6 +416,9 @@ template void launch_spmm<double, double, double, double>(
 template void launch_spmm<float, float, float, float>(
     const Schedule&, const int32_t*, const float*, const float*, int64_t,
     float*, int64_t, int, float*, hipStream_t);
+template void launch_spmm<bf16_t, float, float, float>(
+    const Schedule&, const int32_t*, const bf16_t*, const float*, int64_t,
+    float*, int64_t, int, float*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Fused SDDMM + residual + update.
@@ -437,31 +442,40 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-template <class FT>
+// x = sum_t (u_t sig_t) v_t accumulated in AT; e = M - x and the update of the
+// FP64 master Y in double; the operator copies of Y are refreshed from the
+// master: CSR / CSC copies of type VT (Krylov products) and WT (Rayleigh-Ritz
+// products); a null pointer skips a copy (e.g. when the master serves).
+template <class FT, class AT, class VT, class WT>
 __global__ __launch_bounds__(kSddmmThreads) void sddmm_update_kernel(
     int64_t nnz, const int32_t* __restrict__ row_of,
     const int32_t* __restrict__ col_idx, const double* __restrict__ mvals,
-    double* __restrict__ y, double* __restrict__ ycsc,
+    double* __restrict__ y, VT* __restrict__ yv, VT* __restrict__ ycv,
+    WT* __restrict__ yw, WT* __restrict__ ycw,
     const int32_t* __restrict__ invperm, const FT* __restrict__ U, int64_t ldu,
     const FT* __restrict__ V, int64_t ldv, const double* __restrict__ sig,
     int r, double delta, int apply, double* __restrict__ partial) {
-  __shared__ double ssig[kMaxRankLds];
+  __shared__ AT ssig[kMaxRankLds];
   __shared__ double sh[kSddmmThreads];
-  for (int t = threadIdx.x; t < r; t += blockDim.x) ssig[t] = sig[t];
+  for (int t = threadIdx.x; t < r; t += blockDim.x) ssig[t] = (AT)sig[t];
   __syncthreads();
   const int64_t e = blockIdx.x * (int64_t)kSddmmThreads + threadIdx.x;
   double d2 = 0.0;
   if (e < nnz) {
     const FT* u = U + (int64_t)row_of[e] * ldu;
     const FT* v = V + (int64_t)col_idx[e] * ldv;
-    double x = 0.0;
-    for (int t = 0; t < r; ++t) x += ((double)u[t] * ssig[t]) * (double)v[t];
-    const double d = mvals[e] - x;
+    AT x = 0;
+    for (int t = 0; t < r; ++t) x += ((AT)u[t] * ssig[t]) * (AT)v[t];
+    const double d = mvals[e] - (double)x;
     d2 = d * d;
     if (apply) {
       const double yn = y[e] + delta * d;
       y[e] = yn;
-      ycsc[invperm[e]] = yn;
+      const int32_t ec = invperm[e];
+      if (yv) yv[e] = (VT)yn;
+      if (ycv) ycv[ec] = (VT)yn;
+      if (yw) yw[e] = (WT)yn;
+      if (ycw) ycw[ec] = (WT)yn;
     }
   }
   const double s = block_sum<kSddmmThreads>(d2, sh);
@@ -516,33 +530,35 @@ __global__ void scale_kernel(int64_t n, const double* __restrict__ a,
 
 int64_t sddmm_partials(int64_t nnz) { return ceil_div(nnz, kSddmmThreads); }
 
-template <class FT>
-void launch_sddmm_update(const Layout& L, const double* mvals, double* y,
-                         double* ycsc, const FT* U, int64_t ldu, const FT* V,
-                         int64_t ldv, const double* sig, int r, double delta,
-                         int apply, double* partial, double* out_sum,
+template <class FT, class AT, class VT, class WT>
+void launch_sddmm_update(const Layout& L, const double* mvals, double* y, VT* yv,
+                         VT* ycv, WT* yw, WT* ycw, const FT* U, int64_t ldu,
+                         const FT* V, int64_t ldv, const double* sig, int r,
+                         double delta, int apply, double* partial, double* out_sum,
                          hipStream_t st) {
   MC_REQUIRE(r <= kMaxRankLds, kEINVAL, "rank exceeds the SDDMM limit");
   const int64_t nb = sddmm_partials(L.nnz);
-  hipLaunchKernelGGL(sddmm_update_kernel<FT>, dim3((unsigned)nb),
+  hipLaunchKernelGGL((sddmm_update_kernel<FT, AT, VT, WT>), dim3((unsigned)nb),
                      dim3(kSddmmThreads), 0, st, L.nnz, L.row_of.p,
-                     L.col_idx.p, mvals, y, ycsc, L.invperm.p, U, ldu, V, ldv,
-                     sig, r, delta, apply, partial);
+                     L.col_idx.p, mvals, y, yv, ycv, yw, ycw, L.invperm.p, U, ldu,
+                     V, ldv, sig, r, delta, apply, partial);
   MC_CHECK_LAUNCH();
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, nb, partial,
                      out_sum);
   MC_CHECK_LAUNCH();
 }
-template void launch_sddmm_update<double>(const Layout&, const double*, double*,
-                                          double*, const double*, int64_t,
-                                          const double*, int64_t, const double*,
-                                          int, double, int, double*, double*,
-                                          hipStream_t);
-template void launch_sddmm_update<float>(const Layout&, const double*, double*,
-                                         double*, const float*, int64_t,
-                                         const float*, int64_t, const double*,
-                                         int, double, int, double*, double*,
-                                         hipStream_t);
+template void launch_sddmm_update<double, double, double, double>(
+    const Layout&, const double*, double*, double*, double*, double*, double*,
+    const double*, int64_t, const double*, int64_t, const double*, int, double, int,
+    double*, double*, hipStream_t);
+template void launch_sddmm_update<float, float, float, float>(
+    const Layout&, const double*, double*, float*, float*, float*, float*,
+    const float*, int64_t, const float*, int64_t, const double*, int, double, int,
+    double*, double*, hipStream_t);
+template void launch_sddmm_update<float, float, bf16_t, float>(
+    const Layout&, const double*, double*, bf16_t*, bf16_t*, float*, float*,
+    const float*, int64_t, const float*, int64_t, const double*, int, double, int,
+    double*, double*, hipStream_t);
 
 template <class FT>
 void launch_eval_observed(const Layout& L, const FT* U, int64_t ldu,
