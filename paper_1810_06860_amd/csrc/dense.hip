@@ -61,21 +61,34 @@ __global__ __launch_bounds__(256) void gram_kernel(
   if (i0 + 1 < p && j0 + 1 < q) out[(int64_t)(i0 + 1) * q + j0 + 1] = acc11;
 }
 
+// Sum of the split partials.  `lanes` consecutive threads (a power of two
+// dividing 64, so they sit in one wavefront) share an output: lane j adds the
+// splits j, j + lanes, ... in order, then the lanes are combined by a fixed
+// butterfly, so the result does not depend on scheduling.
 template <class AT>
-__global__ void gram_reduce_kernel(int p, int q, int nsplit,
-                                   const AT* __restrict__ part,
-                                   double* __restrict__ C, int64_t ldc,
-                                   int sym, const int* __restrict__ gate) {
+__global__ __launch_bounds__(256) void gram_reduce_kernel(
+    int p, int q, int nsplit, int lanes, const AT* __restrict__ part,
+    double* __restrict__ C, int64_t ldc, int sym, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= (int64_t)p * q) return;
-  int i = (int)(t / q), j = (int)(t % q);
-  int si = i, sj = j;
-  if (sym && (i / GT) > (j / GT)) { si = j; sj = i; }   // mirrored tile
+  const int per_block = 256 / lanes;
+  const int lane = threadIdx.x % lanes;
+  const int64_t t = blockIdx.x * (int64_t)per_block + threadIdx.x / lanes;
+  const int64_t tot = (int64_t)p * q;
+  const bool live = t < tot;
+  int si = 0, sj = 0, i = 0, j = 0;
+  if (live) {
+    i = (int)(t / q);
+    j = (int)(t % q);
+    si = i;
+    sj = j;
+    if (sym && (i / GT) > (j / GT)) { si = j; sj = i; }   // mirrored tile
+  }
   double acc = 0.0;
-  for (int s = 0; s < nsplit; ++s)
-    acc += (double)part[(int64_t)s * p * q + (int64_t)si * q + sj];
-  C[(int64_t)i * ldc + j] = acc;
+  if (live)
+    for (int s = lane; s < nsplit; s += lanes)
+      acc += (double)part[(int64_t)s * tot + (int64_t)si * q + sj];
+  for (int w = 1; w < lanes; w <<= 1) acc += __shfl_xor(acc, w, 64);
+  if (live && lane == 0) C[(int64_t)i * ldc + j] = acc;
 }
 
 // C = beta*C0 + alpha * X W diag(colscale)
@@ -284,8 +297,12 @@ void launch_gram(int64_t N, int p, int q, const IT* A, int64_t lda, const IT* B,
                      lda, B, ldb, part, rps, sym, gate);
   MC_CHECK_LAUNCH();
   const int64_t tot = (int64_t)p * q;
-  hipLaunchKernelGGL((gram_reduce_kernel<AT>), dim3((unsigned)ceil_div(tot, 256)),
-                     dim3(256), 0, st, p, q, (int)splits, part, C, ldc, sym, gate);
+  int lanes = 1;   // threads per output: about 16 splits each, at most 64
+  while (lanes < 64 && lanes * 16 < splits) lanes <<= 1;
+  const int64_t per_block = 256 / lanes;
+  hipLaunchKernelGGL((gram_reduce_kernel<AT>), dim3((unsigned)ceil_div(tot, per_block)),
+                     dim3(256), 0, st, p, q, (int)splits, lanes, part, C, ldc, sym,
+                     gate);
   MC_CHECK_LAUNCH();
 }
 template void launch_gram<double, double>(int64_t, int, int, const double*,

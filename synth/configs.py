@@ -1,14 +1,21 @@
 """Named workloads and the solver settings each one is run with.
 
 The settings are plain numbers handed to both the oracle and the HIP
-library: tau = 5n (Sec. II.C), delta = 1.2 * m*n/|Phi| (the step-size choice
-"1.2/ratio" of the planted workload, applied to every workload), l = 5, s = 10,
-and the recycling settings the paper uses for images (strategy 2,
+library: tau = 5n (Sec. II.C), l = 5, s = 10, and the step size
+delta = 1.2 * m*n/|Phi| ("1.2/ratio") for the uniformly sampled workloads.
+Under the power-law sampling of the rating workloads that step diverges at
+the first step (the heavy rows are observed almost completely, so the update
+overshoots there by a factor close to delta); they use delta = 1.9, inside the
+0 < delta < 2 range for which SVT is known to converge.  Also
+the recycling settings the paper uses for images (strategy 2,
 i_reuse = 100, q_reuse = 10, Sec. V.B) and ratings (strategy 1, i_reuse = 50,
 q_reuse = 10, Sec. V.C).
 """
 
 from .problems import planted, image_like, ratings
+
+
+RATINGS_DELTA = 1.9
 
 
 def _base(m, n, nnz, **kw):
@@ -41,28 +48,28 @@ CONFIGS = {
         make=lambda: ratings(70000, 10700, 10_000_000, 20, seed_data=3,
                              name="ratings70k"),
         shape=(70000, 10700, 10_000_000),
-        params=lambda m, n, nnz: _base(m, n, nnz, eps=0.16, i_max=400,
+        params=lambda m, n, nnz: _base(m, n, nnz, eps=0.16, i_max=400, delta=RATINGS_DELTA,
                                        recycle=1, i_reuse=50, q_reuse=10)),
     # 1/10-scaled instance of the same generator (m, n / 10, nnz / 100).
     "ratings70k_s10": dict(
         make=lambda: ratings(7000, 1070, 100_000, 20, seed_data=3,
                              name="ratings70k_s10"),
         shape=(7000, 1070, 100_000),
-        params=lambda m, n, nnz: _base(m, n, nnz, eps=0.16, i_max=400,
+        params=lambda m, n, nnz: _base(m, n, nnz, eps=0.16, i_max=400, delta=RATINGS_DELTA,
                                        recycle=1, i_reuse=50, q_reuse=10)),
     # 140,000 x 27,000, 2e7 ratings, rank cap 100.
     "ratings140k": dict(
         make=lambda: ratings(140000, 27000, 20_000_000, 30, seed_data=5,
                              name="ratings140k"),
         shape=(140000, 27000, 20_000_000),
-        params=lambda m, n, nnz: _base(m, n, nnz, eps=0.16, i_max=400,
+        params=lambda m, n, nnz: _base(m, n, nnz, eps=0.16, i_max=400, delta=RATINGS_DELTA,
                                        recycle=1, i_reuse=50, q_reuse=10,
                                        k_max=100)),
     "ratings140k_s10": dict(
         make=lambda: ratings(14000, 2700, 200_000, 30, seed_data=5,
                              name="ratings140k_s10"),
         shape=(14000, 2700, 200_000),
-        params=lambda m, n, nnz: _base(m, n, nnz, eps=0.16, i_max=400,
+        params=lambda m, n, nnz: _base(m, n, nnz, eps=0.16, i_max=400, delta=RATINGS_DELTA,
                                        recycle=1, i_reuse=50, q_reuse=10,
                                        k_max=100)),
 }
