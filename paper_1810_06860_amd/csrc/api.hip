@@ -239,18 +239,42 @@ mc_status mc_svt_step_many(mc_svt_t* hs, int32_t count, mc_svt_step_info* info,
     mcsvt::t_err = "bad handle array";
     return MC_EINVAL;
   }
+  // Every live solve enqueues the first SVD call of its step; then the
+  // host goes round the solves and advances each one whose last enqueued
+  // work has finished, so the device work of solves on different streams
+  // overlaps while the host handles their read-backs in turn.
+  std::vector<mc_status> st(count, MC_OK);
+  std::vector<char> live(count, 0);
+  int pending = 0;
+  for (int32_t j = 0; j < count; ++j) {
+    if (!hs[j] || !hs[j]->solver) {
+      st[j] = MC_EINVAL;
+    } else if (hs[j]->solver->converged()) {
+      st[j] = MC_EDONE;
+    } else {
+      st[j] = guarded(hs[j], [&] { hs[j]->solver->step_begin(); });
+      if (st[j] == MC_OK) {
+        live[j] = 1;
+        ++pending;
+      }
+    }
+  }
+  while (pending > 0) {
+    for (int32_t j = 0; j < count; ++j) {
+      if (!live[j]) continue;
+      bool done = false;
+      st[j] = guarded(hs[j], [&] { done = hs[j]->solver->step_poll(false); });
+      if (st[j] != MC_OK || done) {
+        if (st[j] == MC_OK) fill_info(hs[j]->solver->step_result(), info ? &info[j] : nullptr);
+        live[j] = 0;
+        --pending;
+      }
+    }
+  }
   mc_status worst = MC_OK;
   for (int32_t j = 0; j < count; ++j) {
-    mc_status s;
-    if (!hs[j] || !hs[j]->solver) {
-      s = MC_EINVAL;
-    } else if (hs[j]->solver->converged()) {
-      s = MC_EDONE;
-    } else {
-      s = mc_svt_step(hs[j], info ? &info[j] : nullptr);
-    }
-    if (status) status[j] = s;
-    if (s != MC_OK && s != MC_EDONE && worst == MC_OK) worst = s;
+    if (status) status[j] = st[j];
+    if (st[j] != MC_OK && st[j] != MC_EDONE && worst == MC_OK) worst = st[j];
   }
   return worst;
 }

@@ -488,6 +488,9 @@ void EigSolver::reserve(int L, hipStream_t st) {
   }
   flags.reserve(kMaxSweeps * 64 + 8, st);
   scal.reserve(4, st);
+  // tridiagonal path: reflector rows (allocated here, outside any stream
+  // capture)
+  hh.reserve((size_t)L * L, st);
   if (!hflags) MC_HIP(hipHostMalloc((void**)&hflags, sizeof(int) * 64));
 }
 
@@ -515,12 +518,13 @@ size_t lds_limit() {
     }
   }
   lim = (size_t)v;
-  for (const void* f : {(const void*)jac_topk_kernel}) {
-    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(lim - kStaticLdsReserve)) != hipSuccess) {
-      (void)hipGetLastError();
-      lim = 65536;
-    }
+  if (hipFuncSetAttribute((const void*)jac_topk_kernel,
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(lim - kStaticLdsReserve)) != hipSuccess ||
+      hipFuncSetAttribute(tri_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)lim) != hipSuccess) {
+    (void)hipGetLastError();
+    lim = 65536;
   }
   return lim;
 }
@@ -538,6 +542,14 @@ int EigSolver::single_max() {
 
 void EigSolver::solve_topk(int L, const double* G, int64_t ldg, int k, double* S,
                            double* D, double* Wk, int64_t ldw, hipStream_t st) {
+  if (tri_fits(L, k, lds_limit())) {
+    reserve(L, st);
+    this->L = L;
+    this->Lp = L;
+    launch_tri_topk(L, G, ldg, k, S, D, Wk, ldw, hh.p, lds_limit(), st);
+    sweeps = 0;      // no sweeps: a direct method
+    return;
+  }
   if (L <= single_max()) {
     reserve(L, st);
     this->L = L;

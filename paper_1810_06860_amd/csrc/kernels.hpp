@@ -116,9 +116,16 @@ void launch_ritz(int64_t m, int k, const T* R, int64_t ldr, const T* U,
                  hipStream_t st);
 
 // Block-Jacobi symmetric eigensolver (FP64).
+// one-workgroup tridiagonal top-k eigensolver (tridiag.hip)
+bool tri_fits(int L, int k, size_t lds_bytes);
+const void* tri_kernel_ptr();
+void launch_tri_topk(int L, const double* G, int64_t ldg, int k, double* S, double* D,
+                     double* W, int64_t ldw, double* hh, size_t lds_bytes,
+                     hipStream_t st);
+
 struct EigSolver {
   static constexpr int kMaxSweeps = 30;
-  DevBuf<double> A, V, J, Sd, scal, cslog;
+  DevBuf<double> A, V, J, Sd, scal, cslog, hh;
   DevBuf<int> rrlog;
   DevBuf<int> flags;
   int* hflags = nullptr;

@@ -91,7 +91,9 @@ Solver::Solver(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& prm,
   p_ = prm_.p_init;
 }
 
-Solver::~Solver() = default;
+Solver::~Solver() {
+  if (done_ev_) (void)hipEventDestroy(done_ev_);
+}
 
 void Solver::widths(int k, int p, int& b, int& p_eff) const {
   const int64_t mn = std::min(m_, n_);
@@ -99,11 +101,52 @@ void Solver::widths(int k, int p, int& b, int& p_eff) const {
   p_eff = (int)std::max<int64_t>(0, std::min<int64_t>(p, mn / b - 1));
 }
 
-StepInfo Solver::step() {
+void Solver::mark() {
+  if (!done_ev_) MC_HIP(hipEventCreateWithFlags(&done_ev_, hipEventDisableTiming));
+  MC_HIP(hipEventRecord(done_ev_, st_));
+}
+
+void Solver::wait() { MC_HIP(hipEventSynchronize(done_ev_)); }
+
+void Solver::fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt) {
+  fresh_launch(k, p, step_id, attempt);
+  mark();
+  wait();
+  fresh_finish(k);
+}
+
+double Solver::sddmm(int r) {
+  sddmm_launch(r);
+  mark();
+  wait();
+  return sddmm_finish();
+}
+
+// Enqueue the next SVD call of the rank search: recycled when the gate of
+// Alg. 6 allows it (Sec. IV.B), fresh otherwise.
+void Solver::launch_svd(bool force_fresh) {
+  const int k = k_cur_;
+  const bool fresh = force_fresh || prm_.recycle == 0 || i_ < prm_.i_reuse ||
+                     q_ == prm_.q_reuse || basis_cols_ == 0 || k > basis_cols_;
+  if (fresh) {
+    fresh_launch(k, p_, (uint32_t)i_, attempt_++);
+    ++cur_.fresh;
+  } else {
+    recycled_launch(k);
+    ++q_;
+    ++cur_.recycled;
+  }
+  cur_recycled_ = !fresh;
+  mark();
+  phase_ = kSvd;
+}
+
+void Solver::step_begin() {
   MC_REQUIRE(!converged_, kEDONE, "the solve has already converged");
-  StepInfo info;
+  MC_REQUIRE(phase_ == kIdle, kEINVAL, "a step of this solve is in progress");
+  cur_ = StepInfo();
   ++i_;
-  int k = std::min(r_ + 1, kcap_);
+  k_cur_ = std::min(r_ + 1, kcap_);
   if (prm_.adaptive_p && err_hist_.size() >= 2) {           // Sec. IV.C
     const size_t h = err_hist_.size();
     if (err_hist_[h - 1] > err_hist_[h - 2]) {
@@ -115,46 +158,78 @@ StepInfo Solver::step() {
     }
     p_ = std::min(std::max(p_, prm_.p_min), prm_.p_max);
   }
-  uint32_t attempt = 0;
-  while (true) {
-    bool use_fresh = prm_.recycle == 0 || i_ < prm_.i_reuse ||
-                     q_ == prm_.q_reuse || basis_cols_ == 0 || k > basis_cols_;
-    if (!use_fresh) {
-      const double ratio = recycled_svd(k);
-      ++q_;
-      ++info.recycled;
-      if (prm_.ritz_tol > 0 && ratio > prm_.ritz_tol) {
-        use_fresh = true;
-        ++info.rejected;
-      }
-    }
-    if (use_fresh) {
-      fresh_svd(k, p_, (uint32_t)i_, attempt++);
-      ++info.fresh;
-    }
-    if (lastS_[k - 1] <= prm_.tau || k >= kcap_) break;
-    k = std::min(k + prm_.l, kcap_);
+  attempt_ = 0;
+  try {
+    launch_svd(false);
+  } catch (...) {
+    phase_ = kIdle;
+    throw;
   }
-  int r = 0;
-  while (r < k && lastS_[r] > prm_.tau) ++r;
-  r_ = r;
-  sig_host_.assign(r, 0.0);
-  for (int j = 0; j < r; ++j) sig_host_[j] = lastS_[j] - prm_.tau;
-  const double res = std::sqrt(sddmm(r)) / mnorm_;
-  MC_REQUIRE(std::isfinite(res), kENUMERIC, "non-finite residual");
-  err_hist_.push_back(res);
-  fresh_total_ += info.fresh;
-  recycled_total_ += info.recycled;
-  rejected_total_ += info.rejected;
-  converged_ = res < prm_.eps;
-  info.i = i_;
-  info.r = r;
-  info.k = k;
-  info.p = p_;
-  info.res = res;
-  info.converged = converged_ ? 1 : 0;
-  info.sigma_max = lastS_.empty() ? 0.0 : lastS_[0];
-  return info;
+}
+
+bool Solver::step_poll(bool block) {
+  if (phase_ == kIdle) return true;
+  if (block) {
+    wait();
+  } else {
+    const hipError_t e = hipEventQuery(done_ev_);
+    if (e == hipErrorNotReady) return false;
+    MC_HIP(e);
+  }
+  try {
+    if (phase_ == kSvd) {
+      if (cur_recycled_) {
+        const double ratio = recycled_finish(k_cur_);
+        if (prm_.ritz_tol > 0 && ratio > prm_.ritz_tol) {    // guard: redo fresh
+          ++cur_.rejected;
+          launch_svd(true);
+          return false;
+        }
+      } else {
+        fresh_finish(k_cur_);
+      }
+      if (lastS_[k_cur_ - 1] > prm_.tau && k_cur_ < kcap_) {  // rank search
+        k_cur_ = std::min(k_cur_ + prm_.l, kcap_);
+        launch_svd(false);
+        return false;
+      }
+      int r = 0;
+      while (r < k_cur_ && lastS_[r] > prm_.tau) ++r;
+      r_ = r;
+      sig_host_.assign(r, 0.0);
+      for (int j = 0; j < r; ++j) sig_host_[j] = lastS_[j] - prm_.tau;
+      sddmm_launch(r);
+      mark();
+      phase_ = kSddmm;
+      return false;
+    }
+    const double res = std::sqrt(sddmm_finish()) / mnorm_;
+    MC_REQUIRE(std::isfinite(res), kENUMERIC, "non-finite residual");
+    err_hist_.push_back(res);
+    fresh_total_ += cur_.fresh;
+    recycled_total_ += cur_.recycled;
+    rejected_total_ += cur_.rejected;
+    converged_ = res < prm_.eps;
+    cur_.i = i_;
+    cur_.r = r_;
+    cur_.k = k_cur_;
+    cur_.p = p_;
+    cur_.res = res;
+    cur_.converged = converged_ ? 1 : 0;
+    cur_.sigma_max = lastS_.empty() ? 0.0 : lastS_[0];
+    phase_ = kIdle;
+    return true;
+  } catch (...) {
+    phase_ = kIdle;
+    throw;
+  }
+}
+
+StepInfo Solver::step() {
+  step_begin();
+  while (!step_poll(true)) {
+  }
+  return cur_;
 }
 
 size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& p) {

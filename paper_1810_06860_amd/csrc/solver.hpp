@@ -59,7 +59,17 @@ class Solver {
   // Phi and M_Phi from host arrays (COO rows, int32 cols).  Returns a status.
   virtual int init(const int64_t* rows, const int32_t* cols, const double* vals,
                    bool scale_for_svt) = 0;
+  // One step, waiting for each device round trip.
   StepInfo step();
+  // The same step split at its device round trips, so the host can drive
+  // many solves at once: step_begin() makes the step's host decisions and
+  // enqueues its first SVD call; step_poll() advances the step whenever the
+  // last enqueued work has finished (blocking when `block`) and returns true
+  // once the step is complete, its result in step_result().
+  void step_begin();
+  bool step_poll(bool block);
+  bool step_busy() const { return phase_ != kIdle; }
+  const StepInfo& step_result() const { return cur_; }
   // truncated SVD of the current operator: one rSVD-BKI call (Alg. 5)
   void rsvd(int k, int p, uint32_t step_id, uint32_t attempt) {
     fresh_svd(k, p, step_id, attempt);
@@ -94,16 +104,34 @@ class Solver {
   Profiler prof;
 
  protected:
-  // one rSVD-BKI call: sets lastS_ (k, descending), k_last_, the recycling
-  // basis, q_ = 0
-  virtual void fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt) = 0;
-  // one recycled SVD from the saved basis: sets lastS_, k_last_; returns the
-  // worst Ritz ratio when the guard is on (else 0)
-  virtual double recycled_svd(int k) = 0;
-  // SDDMM + update with X = U[:, :r] diag(sig_host_) V[:, :r]^T; returns the
-  // sum of squared residuals on Phi
-  virtual double sddmm(int r) = 0;
+  // One rSVD-BKI call: enqueues the device work and the copy of its k
+  // singular values to the host, sets k_last_, the recycling basis, q_ = 0.
+  virtual void fresh_launch(int k, int p, uint32_t step_id, uint32_t attempt) = 0;
+  // after the enqueued work finished: lastS_ (k, descending)
+  virtual void fresh_finish(int k) = 0;
+  // One recycled SVD from the saved basis (enqueue), then lastS_ and the
+  // worst Ritz ratio when the guard is on (else 0).
+  virtual void recycled_launch(int k) = 0;
+  virtual double recycled_finish(int k) = 0;
+  // SDDMM + update with X = U[:, :r] diag(sig_host_) V[:, :r]^T (enqueue),
+  // then the sum of squared residuals on Phi
+  virtual void sddmm_launch(int r) = 0;
+  virtual double sddmm_finish() = 0;
+  // blocking forms
+  void fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt);
+  double sddmm(int r);
   void widths(int k, int p, int& b, int& p_eff) const;
+  void mark();                  // record the completion event on the stream
+  void wait();                  // wait for it
+
+  enum Phase { kIdle, kSvd, kSddmm };
+  Phase phase_ = kIdle;
+  StepInfo cur_;
+  int k_cur_ = 0;
+  bool cur_recycled_ = false;
+  uint32_t attempt_ = 0;
+  hipEvent_t done_ev_ = nullptr;
+  void launch_svd(bool force_fresh);
 
   int64_t m_, n_, nnz_;
   mc_svt_params prm_;

@@ -83,9 +83,12 @@ class SolverT final : public Solver {
   }
 
  protected:
-  void fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt) override;
-  double recycled_svd(int k) override;
-  double sddmm(int r) override;
+  void fresh_launch(int k, int p, uint32_t step_id, uint32_t attempt) override;
+  void fresh_finish(int k) override;
+  void recycled_launch(int k) override;
+  double recycled_finish(int k) override;
+  void sddmm_launch(int r) override;
+  double sddmm_finish() override;
 
  private:
   using GraphKey = std::array<int64_t, 8>;
@@ -93,7 +96,8 @@ class SolverT final : public Solver {
   void eig_body(const P* basis, int64_t ldb, int w, int k);
   void fresh_body(int k, int b, int p_eff, int Lw);
   void ritz_body(int k);
-  double read_results(int k, bool ritz);
+  void read_launch(int k, bool ritz);
+  double read_finish(int k, bool ritz);
   hipStream_t ls() const { return capturing_ ? cap_ : st_; }
   bool graphs_ok(int w) const {
     return prm_.use_graphs && !prof.on && w <= EigSolver::single_max();
@@ -359,14 +363,18 @@ void SolverT<P, VT, AT>::orth_block(int j, int b, int Lw) {
   launch_copy_gated<P>(m_, b, H1_.p, b, out, Lw, gate, ls());
 }
 
-// S (k values) and, with the Ritz guard, the k Ritz ratios: one round trip
+// S (k values) and, with the Ritz guard, the k Ritz ratios: enqueued copies
+// to pinned host memory, read once the stream has reached them
 template <class P, class VT, class AT>
-double SolverT<P, VT, AT>::read_results(int k, bool ritz) {
+void SolverT<P, VT, AT>::read_launch(int k, bool ritz) {
   MC_HIP(hipMemcpyAsync(hbuf_, S_.p, k * sizeof(double), hipMemcpyDeviceToHost, st_));
   if (ritz)
     MC_HIP(hipMemcpyAsync(hbuf_ + k, ritz_out_.p, k * sizeof(double),
                           hipMemcpyDeviceToHost, st_));
-  MC_HIP(hipStreamSynchronize(st_));
+}
+
+template <class P, class VT, class AT>
+double SolverT<P, VT, AT>::read_finish(int k, bool ritz) {
   lastS_.assign(hbuf_, hbuf_ + k);
   for (double v : lastS_)
     MC_REQUIRE(std::isfinite(v), kENUMERIC, "non-finite singular value");
@@ -450,7 +458,7 @@ void SolverT<P, VT, AT>::run_graph(const GraphKey& key, F&& body) {
 }
 
 template <class P, class VT, class AT>
-void SolverT<P, VT, AT>::fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt) {
+void SolverT<P, VT, AT>::fresh_launch(int k, int p, uint32_t step_id, uint32_t attempt) {
   int b, p_eff;
   widths(k, p, b, p_eff);
   const int Lw = (p_eff + 1) * b;
@@ -466,7 +474,7 @@ void SolverT<P, VT, AT>::fresh_svd(int k, int p, uint32_t step_id, uint32_t atte
     fresh_body(k, b, p_eff, Lw);
   }
   k_last_ = k;
-  read_results(k, false);
+  read_launch(k, false);
   if (prm_.recycle == 1) {
     swap_buf(Qw_, basis_);
     basis_ld_ = Lw;
@@ -481,10 +489,15 @@ void SolverT<P, VT, AT>::fresh_svd(int k, int p, uint32_t step_id, uint32_t atte
   q_ = 0;
 }
 
-// Recycled SVD from the saved basis (Sec. IV.B); returns the worst Ritz
-// ratio when the guard is on (else 0).
 template <class P, class VT, class AT>
-double SolverT<P, VT, AT>::recycled_svd(int k) {
+void SolverT<P, VT, AT>::fresh_finish(int k) {
+  read_finish(k, false);
+}
+
+// Recycled SVD from the saved basis (Sec. IV.B); the finish returns the
+// worst Ritz ratio when the guard is on (else 0).
+template <class P, class VT, class AT>
+void SolverT<P, VT, AT>::recycled_launch(int k) {
   const int w = basis_cols_;
   ensure(std::min<int>(k + prm_.s, (int)std::min(m_, n_)), w, k);
   const bool ritz = prm_.ritz_tol > 0;
@@ -500,11 +513,16 @@ double SolverT<P, VT, AT>::recycled_svd(int k) {
     body();
   }
   k_last_ = k;
-  return read_results(k, ritz);
+  read_launch(k, ritz);
 }
 
 template <class P, class VT, class AT>
-double SolverT<P, VT, AT>::sddmm(int r) {
+double SolverT<P, VT, AT>::recycled_finish(int k) {
+  return read_finish(k, prm_.ritz_tol > 0);
+}
+
+template <class P, class VT, class AT>
+void SolverT<P, VT, AT>::sddmm_launch(int r) {
   double* hs = hbuf_ + hbuf_n_ / 2;
   for (int j = 0; j < r; ++j) hs[j] = sig_host_[j];
   if (r > 0)
@@ -524,7 +542,10 @@ double SolverT<P, VT, AT>::sddmm(int r) {
                                     scal_.p, st_);
   prof.end(st_);
   MC_HIP(hipMemcpyAsync(hbuf_, scal_.p, sizeof(double), hipMemcpyDeviceToHost, st_));
-  MC_HIP(hipStreamSynchronize(st_));
+}
+
+template <class P, class VT, class AT>
+double SolverT<P, VT, AT>::sddmm_finish() {
   return hbuf_[0];
 }
 

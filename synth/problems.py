@@ -56,7 +56,10 @@ def planted(m, n, rank, ratio, seed_data, seed_phi, name="planted"):
     V = rng.standard_normal((n, rank))
     K = int(np.floor(ratio * m * n + 0.5))
     rows, cols = cells_to_coo(sample_cells(m, n, K, seed_phi), n)
-    vals = np.einsum("ij,ij->i", U[rows], V[cols])
+    vals = np.empty(K)
+    for a in range(0, K, 1 << 18):            # chunks keep the gathers small
+        b = min(K, a + (1 << 18))
+        vals[a:b] = np.einsum("ij,ij->i", U[rows[a:b]], V[cols[a:b]])
     return Problem(m, n, rows, cols, vals, name=name, U=U, V=V,
                    meta=dict(rank=rank, ratio=ratio, seed_data=seed_data,
                              seed_phi=seed_phi))
