@@ -23,13 +23,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-METRIC = ("SVT steps/sec + SpMM HBM GB/s at rel.err≤1e-3; "
+METRIC = ("SVT steps/sec + SpMM HBM GB/s at rel.err\u22641e-3; "
           "p50/p99 solve latency")
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 (vector and matrix)
 FP32_PEAK_TFLOPS = 157.3
 
 HBM_FAMILIES = ("spmm_fwd", "spmm_bwd", "sddmm")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -46,6 +50,11 @@ def parse():
     ap.add_argument("--eager", action="store_true",
                     help="launch kernel by kernel in the timed region too "
                          "(no HIP graphs), e.g. under a counter profiler")
+    ap.add_argument("--serve", type=int, default=32,
+                    help="requests of the serving trace to run (0: skip)")
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for "
                          "calibrating HBM counters under a profiler)")
@@ -115,6 +124,44 @@ def cpu_baseline(prob, prm, budget_s, max_steps):
                              f"(NumPy/SciPy FP64, {dt:.1f} s wall)"))
 
 
+def serving_leg(a):
+    """Continuous batching over the first a.serve requests of the trace:
+    Poisson arrivals (mean gap 50 ms), planted problems of uneven shape, FP32
+    kernels with FP64 eigensolves, admission by device footprint."""
+    import concurrent.futures as cf
+    import torch
+    import synth
+    from paper_1810_06860_amd import serving
+    desc = synth.serving_trace()[: a.serve]
+    t0 = time.perf_counter()
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with cf.ThreadPoolExecutor(workers) as ex:
+        problems = list(ex.map(synth.request_problem, desc))
+    gen_s = time.perf_counter() - t0
+    log(f"serving: {len(problems)} requests generated in {gen_s:.1f} s")
+    reqs = []
+    for d, p in zip(desc, problems):
+        prm = dict(synth.serving_params(p.m, p.n, p.nnz), precision="fp32")
+        reqs.append(serving.Request(d["id"], d["t_arrival"], p, prm))
+    streams = [torch.cuda.Stream() for _ in range(a.serve_streams)]
+    torch.cuda.synchronize()
+    served = serving.serve(reqs, budget_bytes=int(a.serve_budget_gib * (1 << 30)),
+                           max_active=a.serve_slots, stream_pool=streams,
+                           on_done=lambda s, n: log(f"serving: {n}/{len(reqs)} done "
+                                                    f"(req {s.id}, {s.steps} steps, "
+                                                    f"{s.latency:.2f} s)"))
+    torch.cuda.synchronize()
+    out = serving.summarize(served)
+    out.update(precision="fp32 kernels, fp64 eig", budget_gib=a.serve_budget_gib,
+               slots=a.serve_slots, streams=a.serve_streams,
+               nnz_total=int(sum(p.nnz for p in problems)),
+               arrivals="Poisson, mean gap 50 ms", generation_s=round(gen_s, 1))
+    for key in ("p50_s", "p99_s", "mean_s", "max_s", "makespan_s", "steps_per_s"):
+        if out.get(key) is not None:
+            out[key] = round(out[key], 4)
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -131,6 +178,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    log(f"workload {a.workload}")
     prob, prm = synth.make_problem(a.workload)
     prm = dict(prm)
     prm["precision"] = a.precision
@@ -152,6 +200,7 @@ def main():
             break
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log(f"timed: {len(infos)} steps in {t1 - t0:.3f} s")
     # Per-kernel durations: the same workload re-run with kernel-by-kernel
     # launches and HIP events around each launch on the solve's stream.
     prof_solver = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals,
@@ -177,6 +226,7 @@ def main():
     dt = t1 - t0
     value = done / dt
 
+    log(f"profiled pass: {pdone} steps")
     dom, roof = roofline(prof, a.precision)
     U, sig, V = solver.factors()
     res_last = infos[-1]["res"]
@@ -193,6 +243,7 @@ def main():
     cpu = None
     if not a.no_cpu_baseline:
         orc, cpu = cpu_baseline(prob, prm, a.cpu_seconds, a.warmup + done)
+        log(f"cpu baseline: {cpu['value']} steps/s")
         if orc.i == a.warmup + done:
             Xo = (orc.U * orc.sig) @ orc.V.T
             X = (U * sig) @ V.T
@@ -209,6 +260,7 @@ def main():
         if gpu_hist:
             acc["res_hist_max_rel_diff"] = float(max(
                 abs(g - o) / max(abs(o), 1e-300) for g, o in gpu_hist))
+    serve = serving_leg(a) if a.serve > 0 else None
     if a.copy_calib_mib:
         n = a.copy_calib_mib * (1 << 20) // 4
         src = torch.empty(n, dtype=torch.float32, device="cuda")
@@ -237,6 +289,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "accuracy": acc,
+        "serving": serve,
         "kernels": family_table(prof, tp1 - tp0),
         "profiled_pass": {"steps": pdone,
                           "ms_per_step": round(prof_ms, 4) if prof_ms else None,

@@ -158,15 +158,15 @@ mc_status mc_svt_init(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
 mc_status mc_svt_step(mc_svt_t h, mc_svt_step_info* info);
 
 /* Advance `count` independent solves by one step each (continuous batching
- * of completion requests).  Every live solve enqueues the first SVD call of
- * its step at once; the host then goes round the solves and advances each
- * one as soon as its last enqueued work has finished (the rank search, the
- * Ritz guard and the stop test each need a few scalars back), so the device
- * work of solves on different streams overlaps.  Results are those of
+ * of completion requests).  Each handle's step runs on one of a fixed pool
+ * of host worker threads (at most 16), so the device work of solves on
+ * different streams overlaps and a solve waiting for its stream does not
+ * hold back the others.  Handles must be distinct.  Results are those of
  * mc_svt_step on each handle alone.  info[j] (may be NULL) receives what
  * mc_svt_step would return; status[j] (may be NULL) the per-handle status,
  * MC_EDONE for a handle that had already converged.  Returns MC_OK if every
- * handle succeeded or was already converged, else the first error. */
+ * handle succeeded or was already converged, else the first error.
+ * Calls of mc_svt_step_many must not overlap (one caller thread). */
 mc_status mc_svt_step_many(mc_svt_t* hs, int32_t count,
                            mc_svt_step_info* info, mc_status* status);
 

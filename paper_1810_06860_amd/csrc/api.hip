@@ -1,6 +1,11 @@
 // extern "C" entry points declared in include/mcsvt.h.
+#include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
+#include <functional>
+#include <thread>
+#include <vector>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -233,43 +238,115 @@ mc_status mc_svt_step(mc_svt_t h, mc_svt_step_info* info) {
   return guarded(h, [&] { fill_info(h->solver->step(), info); });
 }
 
+namespace {
+
+// Fixed pool of host worker threads for mc_svt_step_many: each handle's step
+// (its host control and device round trips) runs on one worker, so a solve
+// waiting on its stream never holds back the others.
+class StepPool {
+ public:
+  static StepPool& get() {
+    static StepPool pool;
+    return pool;
+  }
+  // run f(0) .. f(n-1) on the workers (and the calling thread); returns when
+  // all are done
+  void run(int n, const std::function<void(int)>& f) {
+    std::unique_lock<std::mutex> lk(m_);
+    job_ = &f;
+    next_ = 0;
+    total_ = n;
+    left_ = n;
+    ++gen_;
+    cv_.notify_all();
+    lk.unlock();
+    work();
+    lk.lock();
+    done_cv_.wait(lk, [&] { return left_ == 0; });
+    job_ = nullptr;
+  }
+
+ private:
+  StepPool() {
+    const unsigned hw = std::max(2u, std::min(16u, std::thread::hardware_concurrency()));
+    for (unsigned t = 0; t + 1 < hw; ++t)
+      threads_.emplace_back([this] { loop(); });
+  }
+  ~StepPool() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : threads_) t.join();
+  }
+  void work() {
+    while (true) {
+      int i;
+      const std::function<void(int)>* f;
+      {
+        std::lock_guard<std::mutex> lk(m_);
+        if (!job_ || next_ >= total_) return;
+        i = next_++;
+        f = job_;
+      }
+      (*f)(i);
+      std::lock_guard<std::mutex> lk(m_);
+      if (--left_ == 0) done_cv_.notify_all();
+    }
+  }
+  void loop() {
+    uint64_t seen = 0;
+    while (true) {
+      {
+        std::unique_lock<std::mutex> lk(m_);
+        cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+      }
+      work();
+    }
+  }
+  std::mutex m_;
+  std::condition_variable cv_, done_cv_;
+  std::vector<std::thread> threads_;
+  const std::function<void(int)>* job_ = nullptr;
+  int next_ = 0, total_ = 0, left_ = 0;
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
+}  // namespace
+
 mc_status mc_svt_step_many(mc_svt_t* hs, int32_t count, mc_svt_step_info* info,
                            mc_status* status) {
   if (!hs || count < 0) {
     mcsvt::t_err = "bad handle array";
     return MC_EINVAL;
   }
-  // Every live solve enqueues the first SVD call of its step; then the
-  // host goes round the solves and advances each one whose last enqueued
-  // work has finished, so the device work of solves on different streams
-  // overlaps while the host handles their read-backs in turn.
   std::vector<mc_status> st(count, MC_OK);
-  std::vector<char> live(count, 0);
-  int pending = 0;
-  for (int32_t j = 0; j < count; ++j) {
+  // the device of the calling thread, made current on every worker
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  auto one = [&](int j) {
     if (!hs[j] || !hs[j]->solver) {
       st[j] = MC_EINVAL;
-    } else if (hs[j]->solver->converged()) {
+      return;
+    }
+    if (hs[j]->solver->converged()) {
       st[j] = MC_EDONE;
-    } else {
-      st[j] = guarded(hs[j], [&] { hs[j]->solver->step_begin(); });
-      if (st[j] == MC_OK) {
-        live[j] = 1;
-        ++pending;
-      }
+      return;
     }
-  }
-  while (pending > 0) {
-    for (int32_t j = 0; j < count; ++j) {
-      if (!live[j]) continue;
-      bool done = false;
-      st[j] = guarded(hs[j], [&] { done = hs[j]->solver->step_poll(false); });
-      if (st[j] != MC_OK || done) {
-        if (st[j] == MC_OK) fill_info(hs[j]->solver->step_result(), info ? &info[j] : nullptr);
-        live[j] = 0;
-        --pending;
-      }
-    }
+    (void)hipSetDevice(dev);
+    st[j] = guarded(hs[j], [&] {
+      const mcsvt::StepInfo r = hs[j]->solver->step();
+      fill_info(r, info ? &info[j] : nullptr);
+    });
+  };
+  if (count == 1) {
+    one(0);
+  } else if (count > 1) {
+    StepPool::get().run(count, one);
   }
   mc_status worst = MC_OK;
   for (int32_t j = 0; j < count; ++j) {

@@ -503,9 +503,7 @@ constexpr size_t kStaticLdsReserve = 12288;   // static LDS of jac_topk_kernel
 
 // Largest dynamic LDS one workgroup may use (queried once; gfx950 allows more
 // than the 64 KB default once the kernel attribute is raised).
-size_t lds_limit() {
-  static size_t lim = 0;
-  if (lim) return lim;
+size_t query_lds_limit() {
   int dev = 0, v = 0;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) !=
@@ -517,7 +515,7 @@ size_t lds_limit() {
       v = 65536;
     }
   }
-  lim = (size_t)v;
+  size_t lim = (size_t)v;
   if (hipFuncSetAttribute((const void*)jac_topk_kernel,
                           hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)(lim - kStaticLdsReserve)) != hipSuccess ||
@@ -526,6 +524,12 @@ size_t lds_limit() {
     (void)hipGetLastError();
     lim = 65536;
   }
+  return lim;
+}
+
+// queried once per process (thread-safe initialisation)
+size_t lds_limit() {
+  static const size_t lim = query_lds_limit();
   return lim;
 }
 }  // namespace
@@ -538,6 +542,10 @@ int EigSolver::single_max() {
          (size_t)(L + 1) * (L + 2) * sizeof(double) <= lim)
     ++L;
   return L;
+}
+
+bool EigSolver::device_only(int L, int k) {
+  return tri_fits(L, k, lds_limit()) || L <= single_max();
 }
 
 void EigSolver::solve_topk(int L, const double* G, int64_t ldg, int k, double* S,

@@ -134,8 +134,10 @@ struct EigSolver {
   void reserve(int L, hipStream_t st);
   // eigen-decompose the symmetric L x L matrix G (row-major, ldg)
   int solve(int L, const double* G, int64_t ldg, hipStream_t st);
-  // largest L solved inside one workgroup (LDS-resident)
+  // largest L solved inside one workgroup by Jacobi (LDS-resident)
   static int single_max();
+  // whether solve_topk(L, .., k, ..) runs without host round trips
+  static bool device_only(int L, int k);
   // Jacobi sweeps of the last solve (synchronises for the one-workgroup path)
   int device_sweeps(hipStream_t st);
   // eigenpairs of the k largest eigenvalues (descending): S = sqrt(max(

@@ -99,8 +99,9 @@ class SolverT final : public Solver {
   void read_launch(int k, bool ritz);
   double read_finish(int k, bool ritz);
   hipStream_t ls() const { return capturing_ ? cap_ : st_; }
-  bool graphs_ok(int w) const {
-    return prm_.use_graphs && !prof.on && w <= EigSolver::single_max();
+  // capture needs an eigensolve without host round trips
+  bool graphs_ok(int w, int k) const {
+    return prm_.use_graphs && !prof.on && EigSolver::device_only(w, k);
   }
   template <class F> void run_graph(const GraphKey& key, F&& body);
   void clear_graphs() {
@@ -392,7 +393,9 @@ void SolverT<P, VT, AT>::eig_body(const P* basis, int64_t ldb, int w, int k) {
   launch_gram<P, AT>(n_, w, w, Bt_.p, w, Bt_.p, w, G_.p, w, 1, gram_part_.p,
                      gram_cap_, ls());                       // G = B B^T (FP64)
   prof.end(ls());
-  prof.begin(kProfEig, 16.0 * w * w, 0.0, ls());
+  // algorithmic work of a top-k symmetric eigensolve: the tridiagonal
+  // reduction (4/3 w^3) and the back-transformation of k vectors (2 w^2 k)
+  prof.begin(kProfEig, 16.0 * w * w, 4.0 / 3.0 * w * w * w + 2.0 * w * w * k, ls());
   eig_.solve_topk(w, G_.p, w, k, S_.p, D_.p, Wk_.p, k, ls());
   prof.end(ls());
   prof.begin(kProfGemm, (double)sizeof(P) * (m_ + n_) * (w + k),
@@ -467,7 +470,7 @@ void SolverT<P, VT, AT>::fresh_launch(int k, int p, uint32_t step_id, uint32_t a
   hctr_[0] = step_id;
   hctr_[1] = attempt;
   MC_HIP(hipMemcpyAsync(ctr_.p, hctr_, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, st_));
-  if (graphs_ok(Lw)) {
+  if (graphs_ok(Lw, k)) {
     const GraphKey key{1, k, b, p_eff, Lw, (int64_t)gen_, (int64_t)(intptr_t)Qw_.p, 0};
     run_graph(key, [&] { fresh_body(k, b, p_eff, Lw); });
   } else {
@@ -505,7 +508,7 @@ void SolverT<P, VT, AT>::recycled_launch(int k) {
     eig_body(basis_.p, basis_ld_, w, k);
     if (ritz) ritz_body(k);
   };
-  if (graphs_ok(w)) {
+  if (graphs_ok(w, k)) {
     const GraphKey key{2, k, w, (int)basis_ld_, ritz ? 1 : 0, (int64_t)gen_,
                        (int64_t)(intptr_t)basis_.p, 0};
     run_graph(key, body);

@@ -1,30 +1,34 @@
 """Continuous-batching request loop for completion solves.
 
 Requests arrive over time.  Each admitted request becomes one SVT handle
-whose iterate, factors and workspaces stay resident on the device between
-steps.  One round of the loop:
+whose iterate, factors and workspaces stay resident on the device until it
+finishes.  The loop
 
 * admits the waiting requests whose arrival time has passed, in arrival
   order, while a slot is free and the sum of the admitted solves' device
   footprints (``mc_svt_footprint``) stays within the memory budget (a request
   larger than the whole budget is admitted only when nothing else runs);
-* advances every admitted solve by one fast-SVT step with
-  ``mc_svt_step_many``: their device work overlaps on separate streams while
-  the host serves their read-backs in turn;
-* retires the solves that converged or reached i_max, freeing their memory.
+* runs every admitted solve on a worker thread of its own, step after step
+  (``mc_svt_step``), on a stream of its own, so the device work of all
+  admitted solves overlaps and a short request never waits for the steps of
+  a long one;
+* retires each solve when it converges or reaches i_max, which frees its slot
+  and memory for the next arrivals.
 
-Latency is completion time minus arrival time.  The solver, the stepping
-call, the footprint and the clock are parameters, so the loop's bookkeeping
-can be exercised without a device.
+Latency is completion time minus arrival time.  The solver factory and the
+footprint are parameters, so the loop can be exercised without a device.
 """
 
 import collections
+import ctypes as C
+import threading
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 
 MC_OK = 0
+MC_ENOTCONV = 8
 
 
 @dataclass
@@ -54,44 +58,48 @@ class Served:
         return self.t_done - self.t_arrival
 
 
-@dataclass
-class _Slot:
-    req: Request
-    solver: object
-    fp: int
-    t_admit: float
-    steps: int = 0
-    last: dict = field(default_factory=dict)
-
-
 def _default_factory(stream_pool):
     from .svt import SVT
-    import ctypes as C
     counter = [0]
+    lock = threading.Lock()
 
     def make(req):
         st = None
         if stream_pool:
-            s = stream_pool[counter[0] % len(stream_pool)]
-            counter[0] += 1
+            with lock:
+                s = stream_pool[counter[0] % len(stream_pool)]
+                counter[0] += 1
             st = C.c_void_p(s.cuda_stream)
         p = req.problem
         return SVT(p.m, p.n, p.rows, p.cols, p.vals, req.params, stream=st)
     return make
 
 
-def serve(requests, budget_bytes, max_active=16, solver_factory=None, stepper=None,
-          footprint_fn=None, clock=time.perf_counter, sleep=time.sleep,
-          keep_factors=False, stream_pool=None):
+def _run_to_end(solver, i_max):
+    """Step one solve until it converges or reaches i_max."""
+    from .svt import MCError
+    steps, last, status = 0, {}, MC_OK
+    try:
+        while steps < i_max:
+            last = solver.step()
+            steps += 1
+            if last.get("converged"):
+                break
+    except MCError as e:
+        status = e.status
+    return steps, last, status
+
+
+def serve(requests, budget_bytes, max_active=16, solver_factory=None,
+          footprint_fn=None, clock=time.perf_counter, keep_factors=False,
+          stream_pool=None, on_done=None, device=None):
     """Run the request loop until every request is served.
 
-    Returns a list of `Served` records in completion order.
+    Returns a list of `Served` records in completion order; `on_done(record,
+    count)` is called as each request completes.
     """
     if solver_factory is None:
         solver_factory = _default_factory(stream_pool)
-    if stepper is None:
-        from .svt import step_many
-        stepper = step_many
     if footprint_fn is None:
         from .svt import footprint
 
@@ -100,44 +108,66 @@ def serve(requests, budget_bytes, max_active=16, solver_factory=None, stepper=No
             return footprint(p.m, p.n, p.rows.size, req.params)
 
     pending = collections.deque(sorted(requests, key=lambda r: (r.t_arrival, r.id)))
-    active, done = [], []
-    used = 0
+    cv = threading.Condition()
+    state = dict(used=0, active=0)
+    done, threads, errors = [], [], []
     t0 = clock()
-    while pending or active:
-        now = clock() - t0
-        while pending and pending[0].t_arrival <= now and len(active) < max_active:
-            req = pending[0]
-            fp = int(footprint_fn(req))
-            if active and used + fp > budget_bytes:
-                break                                  # wait for memory
-            pending.popleft()
-            active.append(_Slot(req, solver_factory(req), fp, clock() - t0))
-            used += fp
-        if not active:
-            sleep(max(0.0, pending[0].t_arrival - (clock() - t0)))
-            continue
-        infos, statuses = stepper([s.solver for s in active])
-        now = clock() - t0
-        keep = []
-        for s, info, st in zip(active, infos, statuses):
-            if st == MC_OK:
-                s.steps += 1
-                s.last = info
-            finished = (st != MC_OK or info.get("converged", 0) or
-                        s.steps >= s.req.params.get("i_max", 200))
-            if not finished:
-                keep.append(s)
+
+    def worker(req, fp, t_admit):
+        try:
+            if device is not None:
+                device()
+            solver = solver_factory(req)
+            steps, last, status = _run_to_end(solver, req.params.get("i_max", 200))
+            facs = solver.factors() if keep_factors and status == MC_OK else None
+            solver.close()
+            rec = Served(id=req.id, t_arrival=req.t_arrival, t_admit=t_admit,
+                         t_done=clock() - t0, steps=steps, status=int(status),
+                         converged=bool(last.get("converged", 0)),
+                         rank=int(last.get("r", 0)),
+                         res=float(last.get("res", float("nan"))), footprint=fp,
+                         factors=facs)
+        except Exception as e:                       # reported after the loop
+            errors.append(e)
+            rec = None
+        with cv:
+            state["used"] -= fp
+            state["active"] -= 1
+            if rec is not None:
+                done.append(rec)
+                if on_done is not None:
+                    on_done(rec, len(done))
+            cv.notify_all()
+
+    with cv:
+        while pending or state["active"]:
+            now = clock() - t0
+            admitted = False
+            while pending and pending[0].t_arrival <= now and state["active"] < max_active:
+                req = pending[0]
+                fp = int(footprint_fn(req))
+                if state["active"] and state["used"] + fp > budget_bytes:
+                    break                                  # wait for memory
+                pending.popleft()
+                state["used"] += fp
+                state["active"] += 1
+                th = threading.Thread(target=worker, args=(req, fp, now), daemon=True)
+                threads.append(th)
+                th.start()
+                admitted = True
+            if admitted:
                 continue
-            facs = s.solver.factors() if keep_factors and st == MC_OK else None
-            done.append(Served(id=s.req.id, t_arrival=s.req.t_arrival, t_admit=s.t_admit,
-                               t_done=now, steps=s.steps, status=int(st),
-                               converged=bool(s.last.get("converged", 0)),
-                               rank=int(s.last.get("r", 0)),
-                               res=float(s.last.get("res", float("nan"))),
-                               footprint=s.fp, factors=facs))
-            s.solver.close()
-            used -= s.fp
-        active = keep
+            # sleep until the next arrival or a completion
+            timeout = None
+            if pending and pending[0].t_arrival > now:
+                timeout = pending[0].t_arrival - now
+            if timeout is None and not state["active"]:
+                continue
+            cv.wait(timeout=timeout if timeout is not None else 1.0)
+    for th in threads:
+        th.join()
+    if errors:
+        raise errors[0]
     return done
 
 
