@@ -491,6 +491,8 @@ void EigSolver::reserve(int L, hipStream_t st) {
   // tridiagonal path: reflector rows (allocated here, outside any stream
   // capture)
   hh.reserve((size_t)L * L, st);
+  if (L <= tri_big_max())
+    big.reserve(TriBigWork::doubles(L, std::min(L, tri_big_kmax())), st);
   if (!hflags) MC_HIP(hipHostMalloc((void**)&hflags, sizeof(int) * 64));
 }
 
@@ -516,6 +518,7 @@ size_t query_lds_limit() {
     }
   }
   size_t lim = (size_t)v;
+  tri_set_lds_attributes(lim);
   if (hipFuncSetAttribute((const void*)jac_topk_kernel,
                           hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)(lim - kStaticLdsReserve)) != hipSuccess ||
@@ -545,7 +548,8 @@ int EigSolver::single_max() {
 }
 
 bool EigSolver::device_only(int L, int k) {
-  return tri_fits(L, k, lds_limit()) || L <= single_max();
+  return tri_fits(L, k, lds_limit()) || (L <= tri_big_max() && k <= tri_big_kmax()) ||
+         L <= single_max();
 }
 
 void EigSolver::solve_topk(int L, const double* G, int64_t ldg, int k, double* S,
@@ -556,6 +560,14 @@ void EigSolver::solve_topk(int L, const double* G, int64_t ldg, int k, double* S
     this->Lp = L;
     launch_tri_topk(L, G, ldg, k, S, D, Wk, ldw, hh.p, lds_limit(), st);
     sweeps = 0;      // no sweeps: a direct method
+    return;
+  }
+  if (L <= tri_big_max() && k <= tri_big_kmax()) {
+    reserve(L, st);
+    this->L = L;
+    this->Lp = L;
+    launch_tri_big(L, G, ldg, k, S, D, Wk, ldw, big.p, big.n, lds_limit(), st);
+    sweeps = 0;
     return;
   }
   if (L <= single_max()) {

@@ -119,13 +119,23 @@ void launch_ritz(int64_t m, int k, const T* R, int64_t ldr, const T* U,
 // one-workgroup tridiagonal top-k eigensolver (tridiag.hip)
 bool tri_fits(int L, int k, size_t lds_bytes);
 const void* tri_kernel_ptr();
+void tri_set_lds_attributes(size_t lds_bytes);
+// the multi-launch path for L up to tri_big_max() (tridiag.hip)
+int tri_big_max();
+int tri_big_kmax();
+struct TriBigWork {
+  static size_t doubles(int L, int k);   // workspace it needs
+};
+void launch_tri_big(int L, const double* G, int64_t ldg, int k, double* S, double* D,
+                    double* W, int64_t ldw, double* ws, size_t ws_doubles,
+                    size_t lds_bytes, hipStream_t st);
 void launch_tri_topk(int L, const double* G, int64_t ldg, int k, double* S, double* D,
                      double* W, int64_t ldw, double* hh, size_t lds_bytes,
                      hipStream_t st);
 
 struct EigSolver {
   static constexpr int kMaxSweeps = 30;
-  DevBuf<double> A, V, J, Sd, scal, cslog, hh;
+  DevBuf<double> A, V, J, Sd, scal, cslog, hh, big;
   DevBuf<int> rrlog;
   DevBuf<int> flags;
   int* hflags = nullptr;

@@ -123,17 +123,10 @@ struct TriSmem {
   int* cnt;
 };
 
-// doubles of the matrix region: A (L x L), later Z (L x k), C (k x k) and
-// the U factors of a batch of nb inverse iterations (3 L nb)
-__host__ __device__ inline size_t tri_region(int L, int k, int nb) {
-  const size_t a = (size_t)L * L, b = (size_t)L * k + (size_t)k * k + 3 * (size_t)L * nb;
-  return a > b ? a : b;
-}
-
-__device__ TriSmem tri_layout(double* sm, int L, int k, int nb) {
+__device__ TriSmem tri_layout_r(double* sm, int L, size_t region) {
   TriSmem s;
   s.A = sm;
-  double* q = sm + tri_region(L, k, nb);
+  double* q = sm + region;
   s.d = q;    q += L;
   s.e = q;    q += L;
   s.e2 = q;   q += L;
@@ -146,6 +139,17 @@ __device__ TriSmem tri_layout(double* sm, int L, int k, int nb) {
   s.xch = q;  q += 4 * kTWaves;
   s.cnt = (int*)q;
   return s;
+}
+
+// doubles of the matrix region: A (L x L), later Z (L x k), C (k x k) and
+// the U factors of a batch of nb inverse iterations (3 L nb)
+__host__ __device__ inline size_t tri_region(int L, int k, int nb) {
+  const size_t a = (size_t)L * L, b = (size_t)L * k + (size_t)k * k + 3 * (size_t)L * nb;
+  return a > b ? a : b;
+}
+
+__device__ TriSmem tri_layout(double* sm, int L, int k, int nb) {
+  return tri_layout_r(sm, L, tri_region(L, k, nb));
 }
 
 // Cholesky QR of the L x k block Z (row-major, ld k) in LDS: C = Z^T Z,
@@ -323,35 +327,29 @@ __device__ void invit_column(int L, int k, int j, const double* d, const double*
   }
 }
 
-__global__ __launch_bounds__(kTT) void tri_topk_kernel(
-    int L, const double* __restrict__ G, int64_t ldg, int k, double* __restrict__ S,
-    double* __restrict__ D, double* __restrict__ W, int64_t ldw,
-    double* __restrict__ hh, int nb) {
-  extern __shared__ double smem[];
-  const TriSmem s = tri_layout(smem, L, k, nb);
-  double* A = s.A;
+// Householder steps j = j0 .. L-3 of the reduction to tridiagonal form, on
+// the trailing block held in LDS: element (r, c), r, c >= j0, of the matrix
+// being reduced is Ab[(r - j0) * ldb + (c - j0)].  Writes d, e, hb, hr for
+// j >= j0 and the reflector rows to hh.
+__device__ void tri_steps(int L, int j0, double* __restrict__ Ab, int ldb,
+                          const TriSmem& s, double* __restrict__ hh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-  for (int t = tid; t < L * L; t += kTT) {
-    const int i = t / L, c = t % L;
-    A[t] = G[(int64_t)i * ldg + c];
-  }
-  __syncthreads();
-
-  // ---- 1. tridiagonalisation ----------------------------------------------
+  auto el = [&](int r, int c) -> double& { return Ab[(r - j0) * ldb + (c - j0)]; };
   {
     double sq = 0.0;
-    for (int c = 2 + tid; c < L; c += kTT) sq += A[c] * A[c];
+    if (j0 + 2 < L)
+      for (int c = j0 + 2 + tid; c < L; c += kTT) sq += el(j0, c) * el(j0, c);
     sq = wsum(sq);
     if (lane == 0) s.red2[wave] = sq;
   }
   __syncthreads();
-  for (int j = 0; j + 2 < L; ++j) {
+  for (int j = j0; j + 2 < L; ++j) {
     const int n = L - j - 1;            // trailing size
     const int o = j + 1;                // first trailing index
     double sig2 = 0.0;
     for (int w = 0; w < kTWaves; ++w) sig2 += s.red2[w];
-    const double alpha = A[j * L + o];
+    const double* __restrict__ hrow = &el(j, o);   // reflector data of step j
+    const double alpha = hrow[0];
     double beta = 0.0, rv = 0.0, mu = alpha;
     if (sig2 > 0.0) {
       mu = sqrt(alpha * alpha + sig2);
@@ -360,12 +358,12 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
       rv = 1.0 / v0;
     }
     if (tid == 0) {
-      s.d[j] = A[j * L + j];
+      s.d[j] = el(j, j);
       s.e[j] = mu;
       s.hb[j] = beta;
       s.hr[j] = rv;
     }
-    for (int t = tid; t < n; t += kTT) hh[(int64_t)j * L + o + t] = A[j * L + o + t];
+    for (int t = tid; t < n; t += kTT) hh[(int64_t)j * L + o + t] = hrow[t];
     // p = beta A22 v, lanes of a group of S share a row
     int S = 1;
     while (S < 8 && 2 * S * n <= kTT) S <<= 1;
@@ -373,11 +371,10 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
     double acc = 0.0;
     if (rowi < n) {
       const int i = o + rowi;
-      const double* __restrict__ hrow = A + j * L + o;      // reflector data
 #pragma unroll 4
       for (int c = part; c < n; c += S) {
         const double h = hrow[c];
-        const double a = A[(o + c) * L + i];
+        const double a = el(o + c, i);
         acc += a * (c == 0 ? 1.0 : h * rv);
       }
     }
@@ -385,7 +382,7 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
     double pv = 0.0;
     if (rowi < n && part == 0) {
       const double p = beta * acc;
-      const double h = A[j * L + o + rowi];
+      const double h = hrow[rowi];
       s.P[rowi] = p;
       pv = p * (rowi == 0 ? 1.0 : h * rv);
     }
@@ -400,14 +397,14 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
     double sq = 0.0;
     if (tid < step * n) {
       const int b = tid % n;
-      const double hb = A[j * L + o + b];
-      const double vb = b == 0 ? 1.0 : hb * rv;
+      const double hbv = hrow[b];
+      const double vb = b == 0 ? 1.0 : hbv * rv;
       const double wb = s.P[b] - K * vb;
 #pragma unroll 2
       for (int a = tid / n; a < n; a += step) {
-        const double ha = A[j * L + o + a];
+        const double ha = hrow[a];
         const double pa = s.P[a];
-        double* x = A + (o + a) * L + o + b;
+        double* x = &el(o + a, o + b);
         const double old = *x;
         const double va = a == 0 ? 1.0 : ha * rv;
         const double nv = old - (va * wb + (pa - K * va) * vb);
@@ -420,16 +417,20 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
     __syncthreads();
   }
   if (tid == 0) {
-    if (L >= 2) {
-      s.d[L - 2] = A[(L - 2) * L + L - 2];
-      s.e[L - 2] = A[(L - 2) * L + L - 1];
+    if (L >= 2 && L - 2 >= j0) {
+      s.d[L - 2] = el(L - 2, L - 2);
+      s.e[L - 2] = el(L - 2, L - 1);
     }
-    s.d[L - 1] = A[(L - 1) * L + L - 1];
+    s.d[L - 1] = el(L - 1, L - 1);
     s.e[L - 1] = 0.0;
   }
   __syncthreads();
+}
 
-  // ---- 2. eigenvalues by multisection ------------------------------------
+// The k largest eigenvalues of T = tridiag(e, d, e) into s.lam (descending)
+// by multisection on Sturm counts; returns ||T|| (Gershgorin).  All threads.
+__device__ double tri_eigvals(int L, int k, const TriSmem& s) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double tn = 0.0, glo = INFINITY, ghi = -INFINITY, emax = 0.0;
   for (int i = tid; i < L; i += kTT) {
     const double r = (i > 0 ? fabs(s.e[i - 1]) : 0.0) + (i + 1 < L ? fabs(s.e[i]) : 0.0);
@@ -503,6 +504,29 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
     if (live && gl == 0) s.lam[grp] = 0.5 * (lo + hi);
   }
   __syncthreads();
+
+  return tn;
+}
+
+__global__ __launch_bounds__(kTT) void tri_topk_kernel(
+    int L, const double* __restrict__ G, int64_t ldg, int k, double* __restrict__ S,
+    double* __restrict__ D, double* __restrict__ W, int64_t ldw,
+    double* __restrict__ hh, int nb) {
+  extern __shared__ double smem[];
+  const TriSmem s = tri_layout(smem, L, k, nb);
+  double* A = s.A;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  for (int t = tid; t < L * L; t += kTT) {
+    const int i = t / L, c = t % L;
+    A[t] = G[(int64_t)i * ldg + c];
+  }
+  __syncthreads();
+
+  // ---- 1. tridiagonalisation ----------------------------------------------
+  tri_steps(L, 0, A, L, s, hh);
+  // ---- 2. eigenvalues by multisection ------------------------------------
+  const double tn = tri_eigvals(L, k, s);
 
   // ---- 3. eigenvectors of T ---------------------------------------------
   double* Z = A;                       // L x k
@@ -580,6 +604,273 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
   }
 }
 
+// ---- matrices too large for one workgroup's LDS -----------------------------
+// The first j0 = L - Ls Householder steps run on a copy of G in global memory,
+// each as two launches over many workgroups; a one-workgroup kernel then
+// finishes the trailing Ls x Ls block in LDS and finds the eigenvalues.
+// Eigenvectors: one workgroup per vector for the inverse iteration, Cholesky
+// QR and a Newton-Schulz step with the Gram and panel kernels, and a
+// back-transformation kernel with each vector in registers.
+
+constexpr int kBigRows = 64;       // rows of the trailing block per workgroup
+
+// p = beta A22 v for 64 rows per workgroup (4 wavefronts split the sum), and
+// the workgroup's share of p^T v.  Every workgroup derives the reflector of
+// step j from row j itself; workgroup 0 records it.
+__global__ __launch_bounds__(256) void big_matvec_kernel(
+    int L, int j, const double* __restrict__ Ag, double* __restrict__ hh,
+    double* __restrict__ dg, double* __restrict__ eg, double* __restrict__ hbg,
+    double* __restrict__ hrg, double* __restrict__ Pg, double* __restrict__ part) {
+  __shared__ double red[4];
+  __shared__ double sacc[4][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int o = j + 1, n = L - o;
+  const double* __restrict__ hrow = Ag + (int64_t)j * L + o;
+  double sq = 0.0;
+  for (int c = 1 + tid; c < n; c += 256) sq += hrow[c] * hrow[c];
+  sq = wsum(sq);
+  if (lane == 0) red[wave] = sq;
+  __syncthreads();
+  const double sig2 = (red[0] + red[1]) + (red[2] + red[3]);
+  const double alpha = hrow[0];
+  double beta = 0.0, rv = 0.0, mu = alpha;
+  if (sig2 > 0.0) {
+    mu = sqrt(alpha * alpha + sig2);
+    const double v0 = alpha <= 0.0 ? alpha - mu : -sig2 / (alpha + mu);
+    beta = 2.0 * v0 * v0 / (sig2 + v0 * v0);
+    rv = 1.0 / v0;
+  }
+  if (blockIdx.x == 0) {
+    if (tid == 0) {
+      dg[j] = Ag[(int64_t)j * L + j];
+      eg[j] = mu;
+      hbg[j] = beta;
+      hrg[j] = rv;
+    }
+    for (int t = tid; t < n; t += 256) hh[(int64_t)j * L + o + t] = hrow[t];
+  }
+  const int r = blockIdx.x * kBigRows + lane;       // trailing row
+  double acc = 0.0;
+  if (r < n) {
+    const int i = o + r;
+#pragma unroll 4
+    for (int c = wave; c < n; c += 4) {
+      const double h = hrow[c];
+      acc += Ag[(int64_t)(o + c) * L + i] * (c == 0 ? 1.0 : h * rv);
+    }
+  }
+  sacc[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0) {
+    double pv = 0.0;
+    if (r < n) {
+      const double p = beta * ((sacc[0][lane] + sacc[1][lane]) + (sacc[2][lane] + sacc[3][lane]));
+      Pg[r] = p;
+      pv = p * (r == 0 ? 1.0 : hrow[r] * rv);
+    }
+    pv = wsum(pv);
+    if (lane == 0) part[blockIdx.x] = pv;
+  }
+}
+
+// A22 -= v w^T + w v^T, w = p - (beta/2)(p^T v) v, on 64 x 64 tiles
+__global__ __launch_bounds__(256) void big_update_kernel(
+    int L, int j, double* __restrict__ Ag, const double* __restrict__ Pg,
+    const double* __restrict__ part, int nparts, const double* __restrict__ hbg,
+    const double* __restrict__ hrg) {
+  const double beta = hbg[j];
+  if (beta == 0.0) return;
+  const double rv = hrg[j];
+  double pvt = 0.0;
+  for (int w = 0; w < nparts; ++w) pvt += part[w];
+  const double K = 0.5 * beta * pvt;
+  const int o = j + 1, n = L - o;
+  const double* __restrict__ hrow = Ag + (int64_t)j * L + o;
+  const int b = blockIdx.x * 64 + (threadIdx.x & 63);
+  if (b >= n) return;
+  const double vb = b == 0 ? 1.0 : hrow[b] * rv;
+  const double wb = Pg[b] - K * vb;
+  const int a0 = blockIdx.y * 64 + (threadIdx.x >> 6);
+  const int a1 = min(n, (int)(blockIdx.y + 1) * 64);
+#pragma unroll 4
+  for (int a = a0; a < a1; a += 4) {
+    const double va = a == 0 ? 1.0 : hrow[a] * rv;
+    const double wa = Pg[a] - K * va;
+    double* x = Ag + (int64_t)(o + a) * L + o + b;
+    *x -= va * wb + wa * vb;
+  }
+}
+
+// The trailing block (rows and columns j0 ..) in LDS: the remaining steps and
+// the eigenvalues.  Writes d, e, hb, hr for every step, the k eigenvalues
+// (descending) and ||T||.
+__global__ __launch_bounds__(kTT) void tri_tail_kernel(
+    int L, int j0, const double* __restrict__ Ag, double* __restrict__ hh,
+    double* __restrict__ dg, double* __restrict__ eg, double* __restrict__ hbg,
+    double* __restrict__ hrg, int k, double* __restrict__ lam,
+    double* __restrict__ tnorm) {
+  extern __shared__ double smem[];
+  const int Ls = L - j0;
+  const TriSmem s = tri_layout_r(smem, L, (size_t)Ls * Ls);
+  const int tid = threadIdx.x;
+  for (int t = tid; t < Ls * Ls; t += kTT) {
+    const int r = t / Ls, c = t % Ls;
+    s.A[t] = Ag[(int64_t)(j0 + r) * L + j0 + c];
+  }
+  for (int i = tid; i < j0; i += kTT) {
+    s.d[i] = dg[i];
+    s.e[i] = eg[i];
+    s.hb[i] = hbg[i];
+    s.hr[i] = hrg[i];
+  }
+  __syncthreads();
+  tri_steps(L, j0, s.A, Ls, s, hh);
+  const double tn = tri_eigvals(L, k, s);
+  for (int i = tid; i < L; i += kTT) {
+    dg[i] = s.d[i];
+    eg[i] = s.e[i];
+    hbg[i] = s.hb[i];
+    hrg[i] = s.hr[i];
+  }
+  for (int i = tid; i < k; i += kTT) lam[i] = s.lam[i];
+  if (tid == 0) tnorm[0] = tn;
+}
+
+// Two inverse-iteration steps for eigenvalue j (one workgroup per vector):
+// the column lands in Zg (L x k, row-major).
+__global__ __launch_bounds__(64) void big_invit_kernel(
+    int L, int k, const double* __restrict__ dg, const double* __restrict__ eg,
+    const double* __restrict__ lam, const double* __restrict__ tnorm,
+    double* __restrict__ Zg) {
+  extern __shared__ double smem[];
+  double* d = smem;
+  double* e = d + L;
+  double* z = e + L;
+  double* U = z + L;
+  const int j = blockIdx.x;
+  for (int i = threadIdx.x; i < L; i += 64) {
+    d[i] = dg[i];
+    e[i] = eg[i];
+    const uint64_t h = mix64(((uint64_t)(j + 1) << 32) ^ (uint64_t)i);
+    z[i] = (double)(h >> 11) * 0x1.0p-53 - 0.5;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) invit_column(L, 1, 0, d, e, lam[j], tnorm[0], z, U, 3);
+  __syncthreads();
+  for (int i = threadIdx.x; i < L; i += 64) Zg[(int64_t)i * k + j] = z[i];
+}
+
+// C (k x k, symmetric positive definite) -> R^{-1} (upper triangular, with
+// zeros below) for C = R^T R, in one workgroup.  The factorisation runs in
+// the first wavefront; each thread then forms one column of R^{-1} by back
+// substitution.  Pivots below 1e-28 are clamped (columns enter with unit norm).
+__global__ __launch_bounds__(256) void chol_rinv_kernel(int k, const double* __restrict__ Cg,
+                                                        double* __restrict__ Rinv) {
+  extern __shared__ double smem[];
+  double* C = smem;             // upper: Schur rows; lower: R^{-1} transposed
+  double* rd = C + (size_t)k * k;
+  const int tid = threadIdx.x;
+  for (int t = tid; t < k * k; t += 256) C[t] = Cg[t];
+  __syncthreads();
+  if (tid < 64) {
+    for (int c = 0; c < k; ++c) {
+      const double rp = rcp(fmax(C[c * k + c], 1e-28));
+      const int n = k - c - 1;
+      for (int t = tid; t < n * n; t += 64) {
+        const int a = c + 1 + t / n, b = c + 1 + t % n;
+        if (a > b) continue;
+        C[a * k + b] -= C[c * k + a] * C[c * k + b] * rp;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < k; t += 256) rd[t] = sqrt(fmax(C[t * k + t], 1e-28));
+  __syncthreads();
+  // column c of R^{-1}: X_cc = 1 / R_cc, X_lc = -(sum_{m=l+1..c} R_lm X_mc) / R_ll,
+  // with R_lm = C_lm / R_ll; X_lc is kept at C[c][l] (l <= c, lower part)
+  for (int c = tid; c < k; c += 256) {
+    C[c * k + c] = 0.0;                    // the diagonal is read only through rd
+    const double xcc = 1.0 / rd[c];
+    for (int l = c - 1; l >= 0; --l) {
+      double acc = C[l * k + c] / rd[l] * xcc;
+      for (int m = l + 1; m < c; ++m) acc += C[l * k + m] / rd[l] * C[c * k + m];
+      C[c * k + l] = -acc / rd[l];
+    }
+    C[c * k + c] = xcc;
+  }
+  __syncthreads();
+  for (int t = tid; t < k * k; t += 256) {
+    const int a = t / k, b = t % k;
+    Rinv[t] = a <= b ? C[b * k + a] : 0.0;
+  }
+}
+
+// M = (3 I - C) / 2 in place (C symmetric k x k)
+__global__ void ns_matrix_kernel(int k, double* __restrict__ C) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= k * k) return;
+  const int a = t / k, b = t % k;
+  C[t] = (a == b ? 1.5 : 0.0) - 0.5 * C[t];
+}
+
+// Rayleigh quotients on T and W = H_0 ... H_{L-3} Z: 16 lanes per vector,
+// vector entries vlane + 16 q in registers
+template <int R>
+__global__ __launch_bounds__(512) void big_back_kernel(
+    int L, int k, const double* __restrict__ Zg, const double* __restrict__ hh,
+    const double* __restrict__ hbg, const double* __restrict__ hrg,
+    const double* __restrict__ dg, const double* __restrict__ eg,
+    double* __restrict__ S, double* __restrict__ D, double* __restrict__ W,
+    int64_t ldw) {
+  const int tid = threadIdx.x, vlane = tid % kVecLanes;
+  const int col = blockIdx.x * (512 / kVecLanes) + tid / kVecLanes;
+  const bool act = col < k;
+  const int cc = act ? col : 0;
+  double z[R];
+  double rq = 0.0;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = vlane + kVecLanes * q;
+    const bool in = act && i < L;
+    const int ic = min(i, L - 1);
+    const double zi = in ? Zg[(int64_t)ic * k + cc] : 0.0;
+    const double zp = (in && i + 1 < L) ? Zg[(int64_t)(ic + 1) * k + cc] : 0.0;
+    z[q] = zi;
+    rq += zi * (dg[ic] * zi + 2.0 * eg[ic] * zp);
+  }
+  rq = group_sum(rq, kVecLanes);
+  if (act && vlane == 0) {
+    D[col] = rq;
+    S[col] = sqrt(fmax(rq, 0.0));
+  }
+  for (int j = L - 3; j >= 0; --j) {
+    const double beta = hbg[j];
+    const double rv = hrg[j];
+    double v[R];
+    double dot = 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = vlane + kVecLanes * q;
+      const double h = hh[(int64_t)j * L + min(i, L - 1)];
+      v[q] = i == j + 1 ? 1.0 : (i > j + 1 && i < L ? h * rv : 0.0);
+      dot += v[q] * z[q];
+    }
+    dot = group_sum(dot, kVecLanes) * beta;
+#pragma unroll
+    for (int q = 0; q < R; ++q) z[q] -= dot * v[q];
+  }
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int i = vlane + kVecLanes * q;
+      if (i < L) W[(int64_t)i * ldw + col] = z[q];
+    }
+  }
+}
+
 }  // namespace
 
 size_t tri_lds_bytes(int L, int k, int nb) {
@@ -600,6 +891,99 @@ bool tri_fits(int L, int k, size_t lds_bytes) {
 }
 
 const void* tri_kernel_ptr() { return (const void*)tri_topk_kernel; }
+
+void tri_set_lds_attributes(size_t lim) {
+  for (const void* f : {(const void*)tri_tail_kernel, (const void*)chol_rinv_kernel})
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lim) !=
+        hipSuccess)
+      (void)hipGetLastError();
+}
+
+int tri_big_max() { return kVecLanes * 40; }
+int tri_big_kmax() { return 140; }       // chol_rinv_kernel keeps k x k in LDS
+
+// trailing block solved in LDS by the tail kernel
+static int tail_block(int L, size_t lds_bytes) {
+  const size_t fixed = sizeof(double) * (7 * (size_t)L + 6 * kTWaves) + sizeof(int) * kTT;
+  int Ls = 1;
+  while (Ls + 1 <= L && fixed + sizeof(double) * (size_t)(Ls + 1) * (Ls + 1) <= lds_bytes)
+    ++Ls;
+  return Ls;
+}
+
+size_t TriBigWork::doubles(int L, int k) {
+  const size_t nparts = (size_t)(L + kBigRows - 1) / kBigRows;
+  const size_t splits = (size_t)gram_splits(L, k, k, 1);
+  return 2 * (size_t)L * L + 5 * (size_t)L + nparts + k + 8 + 2 * (size_t)L * k +
+         3 * (size_t)k * k + splits * k * k;
+}
+
+void launch_tri_big(int L, const double* G, int64_t ldg, int k, double* S, double* D,
+                    double* W, int64_t ldw, double* ws, size_t ws_doubles,
+                    size_t lds_bytes, hipStream_t st) {
+  MC_REQUIRE(L <= tri_big_max() && k >= 1 && k <= L && k <= tri_big_kmax(), kEINVAL,
+             "eigensolve size out of range");
+  MC_REQUIRE(TriBigWork::doubles(L, k) <= ws_doubles, kEINVAL, "eigensolver workspace");
+  const int nparts = (L + kBigRows - 1) / kBigRows;
+  double* Ag = ws;
+  double* hh = Ag + (size_t)L * L;
+  double* dg = hh + (size_t)L * L;
+  double* eg = dg + L;
+  double* hbg = eg + L;
+  double* hrg = hbg + L;
+  double* Pg = hrg + L;
+  double* part = Pg + L;
+  double* lam = part + nparts;
+  double* tn = lam + k;
+  double* Zg = tn + 8;
+  double* Z2 = Zg + (size_t)L * k;
+  double* C = Z2 + (size_t)L * k;
+  double* Ri = C + (size_t)k * k;
+  double* gpart = Ri + (size_t)k * k;
+  const int64_t gcap = gram_splits(L, k, k, 1) * (int64_t)k * k;
+  MC_HIP(hipMemcpy2DAsync(Ag, L * sizeof(double), G, ldg * sizeof(double),
+                          L * sizeof(double), L, hipMemcpyDeviceToDevice, st));
+  const int Ls = tail_block(L, lds_bytes);
+  const int j0 = L - Ls;
+  for (int j = 0; j < j0; ++j) {
+    const int n = L - j - 1;
+    const int nb = (n + kBigRows - 1) / kBigRows;
+    hipLaunchKernelGGL(big_matvec_kernel, dim3(nb), dim3(256), 0, st, L, j, Ag, hh, dg,
+                       eg, hbg, hrg, Pg, part);
+    MC_CHECK_LAUNCH();
+    hipLaunchKernelGGL(big_update_kernel, dim3(nb, nb), dim3(256), 0, st, L, j, Ag, Pg,
+                       part, nb, hbg, hrg);
+    MC_CHECK_LAUNCH();
+  }
+  const size_t tail_bytes = sizeof(double) * ((size_t)Ls * Ls + 7 * (size_t)L + 6 * kTWaves) +
+                            sizeof(int) * kTT;
+  hipLaunchKernelGGL(tri_tail_kernel, dim3(1), dim3(kTT), tail_bytes, st, L, j0, Ag, hh,
+                     dg, eg, hbg, hrg, k, lam, tn);
+  MC_CHECK_LAUNCH();
+  hipLaunchKernelGGL(big_invit_kernel, dim3(k), dim3(64), sizeof(double) * 6 * (size_t)L,
+                     st, L, k, dg, eg, lam, tn, Zg);
+  MC_CHECK_LAUNCH();
+  // Cholesky QR, then one Newton-Schulz step
+  launch_gram<double, double>(L, k, k, Zg, k, Zg, k, C, k, 1, gpart, gcap, st);
+  hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(256),
+                     sizeof(double) * ((size_t)k * k + k), st, k, C, Ri);
+  MC_CHECK_LAUNCH();
+  launch_panel_gemm<double, double>(L, k, k, Zg, k, Ri, k, 1.0, nullptr, 0.0, nullptr, 0,
+                                    Z2, k, st);
+  launch_gram<double, double>(L, k, k, Z2, k, Z2, k, C, k, 1, gpart, gcap, st);
+  hipLaunchKernelGGL(ns_matrix_kernel, dim3((k * k + 255) / 256), dim3(256), 0, st, k, C);
+  MC_CHECK_LAUNCH();
+  launch_panel_gemm<double, double>(L, k, k, Z2, k, C, k, 1.0, nullptr, 0.0, nullptr, 0, Zg,
+                                    k, st);
+  const dim3 grid((unsigned)((k + 512 / kVecLanes - 1) / (512 / kVecLanes)));
+  if (L <= kVecLanes * 24)
+    hipLaunchKernelGGL(big_back_kernel<24>, grid, dim3(512), 0, st, L, k, Zg, hh, hbg,
+                       hrg, dg, eg, S, D, W, ldw);
+  else
+    hipLaunchKernelGGL(big_back_kernel<40>, grid, dim3(512), 0, st, L, k, Zg, hh, hbg,
+                       hrg, dg, eg, S, D, W, ldw);
+  MC_CHECK_LAUNCH();
+}
 
 void launch_tri_topk(int L, const double* G, int64_t ldg, int k, double* S, double* D,
                      double* W, int64_t ldw, double* hh, size_t lds_bytes,

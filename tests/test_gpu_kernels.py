@@ -151,6 +151,32 @@ def test_syev_matches_eigh(K, L, k):
     assert sweeps < 30
 
 
+@pytest.mark.parametrize("L,k", [(200, 50), (480, 100), (600, 140)])
+def test_syev_large_multi_launch_path(K, L, k):
+    # beyond one workgroup's LDS: reduction over many workgroups, then LDS
+    rng = np.random.default_rng(L + 7)
+    A = rng.standard_normal((3 * L, L)) * np.logspace(0, -4, L)
+    A[:, 0] *= 50.0
+    G = A.T @ A
+    ev, W, sweeps = K.syev(G, k)
+    want = np.linalg.eigh(G)[0][::-1][:k]
+    assert np.allclose(ev, want, rtol=1e-12, atol=1e-14 * want[0])
+    assert np.linalg.norm(G @ W - W * ev) < 1e-12 * want[0] * np.sqrt(k)
+    assert np.linalg.norm(W.T @ W - np.eye(k)) < 2e-14 * L
+
+
+def test_syev_large_clustered(K):
+    rng = np.random.default_rng(3)
+    Q, _ = np.linalg.qr(rng.standard_normal((220, 220)))
+    lam = np.concatenate([[9.0] * 4, [4.0] * 3, np.linspace(2.0, 0.1, 213)])
+    G = (Q * lam) @ Q.T
+    G = 0.5 * (G + G.T)
+    ev, W, _ = K.syev(G, 10)
+    np.testing.assert_allclose(ev[:7], [9.0] * 4 + [4.0] * 3, rtol=1e-12)
+    assert np.linalg.norm(G @ W - W * ev) < 1e-12 * 9.0 * np.sqrt(10)
+    assert np.linalg.norm(W.T @ W - np.eye(10)) < 2e-14 * 220
+
+
 def test_syev_degenerate_and_diagonal(K):
     G = np.diag(np.arange(40, 0, -1.0))
     ev, W, _ = K.syev(G, 10)
