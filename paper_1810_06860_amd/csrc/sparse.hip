@@ -322,46 +322,84 @@ template void launch_scatter<double>(int64_t, const int32_t*, const double*,
 // ---------------------------------------------------------------------------
 namespace {
 
-template <class VT, class XT, class AT, class OT, int BW>
+// loads of data read once (non-temporal)
+template <class T>
+__device__ __forceinline__ T ld_stream(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <>
+__device__ __forceinline__ bf16_t ld_stream<bf16_t>(const bf16_t* p) {
+  bf16_t v;
+  v.bits = __builtin_nontemporal_load(reinterpret_cast<const uint16_t*>(p));
+  return v;
+}
+
+// One wavefront per segment.  BW lanes share one nonzero and cover BW
+// columns per load, each lane accumulating CPL columns (c, c + BW, ...), so a
+// nonzero's index and value are broadcast once for up to BW * CPL columns;
+// 64 / BW nonzeros are in flight side by side.  Columns beyond b read an
+// in-bounds address with weight zero.
+template <class VT, class XT, class AT, class OT, int BW, int CPL>
 __global__ __launch_bounds__(256) void spmm_kernel(
     int64_t nseg, const int4* __restrict__ segs,
     const int32_t* __restrict__ idx, const VT* __restrict__ val,
     const XT* __restrict__ X, int64_t ldx, OT* __restrict__ out, int64_t ldo,
     AT* __restrict__ part, int b) {
   constexpr int G = 64 / BW;       // nonzeros processed side by side
+  constexpr int CB = BW * CPL;     // columns per pass
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (wave >= nseg) return;
   const int4 sg = segs[wave];
   const int g = lane / BW;
   const int c = lane % BW;
-  for (int c0 = 0; c0 < b; c0 += BW) {
-    const int col = c0 + c;
-    const bool active = col < b;
-    const int colc = active ? col : b - 1;   // in-bounds address, weight 0
-    AT acc = 0;
+  for (int c0 = 0; c0 < b; c0 += CB) {
+    int colc[CPL];
+    AT acc[CPL];
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) {
+      const int col = c0 + c + t * BW;
+      colc[t] = col < b ? col : b - 1;
+      acc[t] = 0;
+    }
     for (int base = sg.y; base < sg.z; base += 64) {
       const int e = base + lane;
       const bool ok = e < sg.z;
-      // lanes past the segment carry index 0 and value 0
-      const int my_idx = ok ? idx[e] : 0;
-      const AT my_val = ok ? (AT)val[e] : (AT)0;
-      // fixed trip count: the gathers of one chunk are independent, so they
-      // are issued back to back
+      // lanes past the segment carry index 0 and value 0; the index and
+      // value streams are read once, so they bypass the caches that hold X
+      const int my_idx = ok ? ld_stream(idx + e) : 0;
+      const AT my_val = ok ? (AT)ld_stream(val + e) : (AT)0;
+      const int left = sg.z - base;            // nonzeros left in the segment
+      // two halves of 32 nonzeros: the gathers of a half are independent and
+      // issued back to back; a short tail skips the second half
 #pragma unroll
-      for (int jj = 0; jj < 64; jj += G) {
-        const int jc = __shfl(my_idx, jj + g);
-        const AT jv = __shfl(my_val, jj + g);
-        acc += jv * (AT)X[(int64_t)jc * ldx + colc];
+      for (int h = 0; h < 64; h += 32) {
+        if (h >= left) break;                  // uniform: the wave's segment
+#pragma unroll
+        for (int jj = h; jj < h + 32; jj += G) {
+          const int jc = __shfl(my_idx, jj + g);
+          const AT jv = __shfl(my_val, jj + g);
+          const XT* xr = X + (int64_t)jc * ldx;
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) acc[t] += jv * (AT)xr[colc[t]];
+        }
       }
     }
 #pragma unroll
-    for (int off = BW; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
-    if (g == 0 && active) {
-      if (sg.w < 0)
-        out[(int64_t)sg.x * ldo + col] = (OT)acc;
-      else
-        part[(int64_t)sg.w * b + col] = acc;
+    for (int t = 0; t < CPL; ++t) {
+#pragma unroll
+      for (int off = BW; off < 64; off <<= 1) acc[t] += __shfl_xor(acc[t], off);
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) {
+        const int col = c0 + c + t * BW;
+        if (col >= b) continue;
+        if (sg.w < 0)
+          out[(int64_t)sg.x * ldo + col] = (OT)acc[t];
+        else
+          part[(int64_t)sg.w * b + col] = acc[t];
+      }
     }
   }
 }
@@ -389,18 +427,22 @@ void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
   if (S.nseg == 0 || b <= 0) return;
   const int T = 256;
   const unsigned grid = (unsigned)ceil_div(S.nseg, T / 64);
+#define MC_SPMM(BW, CPL)                                                          \
+  hipLaunchKernelGGL((spmm_kernel<VT, XT, AT, OT, BW, CPL>), dim3(grid), dim3(T), 0, \
+                     st, S.nseg, S.segs.p, idx, val, X, ldx, out, ldo, part, b)
   if (b <= 8)
-    hipLaunchKernelGGL((spmm_kernel<VT, XT, AT, OT, 8>), dim3(grid), dim3(T), 0,
-                       st, S.nseg, S.segs.p, idx, val, X, ldx, out, ldo, part, b);
+    MC_SPMM(8, 1);
   else if (b <= 16)
-    hipLaunchKernelGGL((spmm_kernel<VT, XT, AT, OT, 16>), dim3(grid), dim3(T), 0,
-                       st, S.nseg, S.segs.p, idx, val, X, ldx, out, ldo, part, b);
+    MC_SPMM(16, 1);
   else if (b <= 32)
-    hipLaunchKernelGGL((spmm_kernel<VT, XT, AT, OT, 32>), dim3(grid), dim3(T), 0,
-                       st, S.nseg, S.segs.p, idx, val, X, ldx, out, ldo, part, b);
+    MC_SPMM(16, 2);
+  else if (b <= 64)
+    MC_SPMM(16, 4);
+  else if (b <= 128)
+    MC_SPMM(32, 4);
   else
-    hipLaunchKernelGGL((spmm_kernel<VT, XT, AT, OT, 64>), dim3(grid), dim3(T), 0,
-                       st, S.nseg, S.segs.p, idx, val, X, ldx, out, ldo, part, b);
+    MC_SPMM(64, 4);
+#undef MC_SPMM
   MC_CHECK_LAUNCH();
   if (S.nfix) {
     const int64_t work = S.nfix * b;
