@@ -151,17 +151,23 @@ __global__ __launch_bounds__(256) void panel_gemm_kernel(
 }
 
 // One workgroup: G (b x b, SPD) = R^T R, Rinv = R^-1 (upper triangular).
-// Breakdown (non-positive or tiny pivot) retries with G + shift I.
+// Breakdown (a pivot that is not positive or below 1e-13 of its original
+// diagonal) retries with G + shift I.  Right-looking on the upper triangle
+// without scaling (after step j row j holds R_jj^2 and R_jj R_jc), one
+// barrier per column; R^{-1} is formed in LDS, one thread per column, and
+// written out at the end.
 __global__ __launch_bounds__(1024) void chol_inv_kernel(
     int b, const double* __restrict__ G, int64_t ldg, double* __restrict__ Rinv,
     int64_t ldr, double* __restrict__ work, int64_t nrows,
     int* __restrict__ shifted, int* __restrict__ flag, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   extern __shared__ double lds[];
-  double* R = (b <= kCholLdsMax) ? lds : work;     // b x b, row-major
-  __shared__ int fail;
+  const bool in_lds = b <= kCholLdsMax;
+  double* R = in_lds ? lds : work;                   // b x b, row-major
+  double* X = in_lds ? lds + (size_t)b * b : work + (size_t)b * b;   // R^{-1}
   __shared__ double trace;
-  if (threadIdx.x == 0) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
     double t = 0.0;
     for (int i = 0; i < b; ++i) t += G[(int64_t)i * ldg + i];
     trace = t;
@@ -170,56 +176,62 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(
   const double u = 1.1102230246251565e-16;
   double shift = 0.0;
   for (int attempt = 0; attempt < 6; ++attempt) {
-    for (int t = threadIdx.x; t < b * b; t += blockDim.x) {
+    for (int t = tid; t < b * b; t += blockDim.x) {
       const int i = t / b, j = t % b;
       double v = (i <= j) ? G[(int64_t)i * ldg + j] : 0.0;
       if (i == j) v += shift;
       R[t] = v;
     }
-    if (threadIdx.x == 0) fail = 0;
     __syncthreads();
+    bool failed = false;
     for (int j = 0; j < b; ++j) {
-      if (threadIdx.x == 0) {
-        // a pivot below 1e-13 of its original diagonal means kappa(H) of
-        // order 1e6 or worse: Cholesky QR would lose all orthogonality
-        const double d = R[j * b + j];
-        const double gjj = G[(int64_t)j * ldg + j] + shift;
-        if (!(d > 1e-13 * gjj) || !(d > 1e-300)) fail = 1;
-        else R[j * b + j] = sqrt(d);
+      // a pivot below 1e-13 of its original diagonal means kappa(H) of
+      // order 1e6 or worse: Cholesky QR would lose all orthogonality
+      const double d = R[j * b + j];
+      const double gjj = G[(int64_t)j * ldg + j] + shift;
+      if (!(d > 1e-13 * gjj) || !(d > 1e-300)) {
+        failed = true;                               // the same for every thread
+        break;
       }
-      __syncthreads();
-      if (fail) break;
-      const double piv = R[j * b + j];
-      for (int c = j + 1 + threadIdx.x; c < b; c += blockDim.x) R[j * b + c] /= piv;
-      __syncthreads();
+      const double rd = 1.0 / d;
       const int rem = b - j - 1;
-      for (int t = threadIdx.x; t < rem * rem; t += blockDim.x) {
+      for (int t = tid; t < rem * rem; t += blockDim.x) {
         const int i = j + 1 + t / rem, c = j + 1 + t % rem;
-        if (c >= i) R[i * b + c] -= R[j * b + i] * R[j * b + c];
+        if (c >= i) R[i * b + c] -= R[j * b + i] * R[j * b + c] * rd;
       }
       __syncthreads();
     }
-    if (!fail) break;
+    if (!failed) break;
     // shifted Cholesky QR: s = 11 (N b + b (b + 1)) u ||X||^2, ||X||^2 <= tr G
     shift = (shift == 0.0)
                 ? 11.0 * ((double)nrows * b + (double)b * (b + 1)) * u *
                       fmax(trace, 1e-300)
                 : shift * 100.0;
-    if (threadIdx.x == 0 && shifted) atomicAdd(shifted, 1);
-    if (threadIdx.x == 0 && flag) *flag = 1;
+    if (tid == 0 && shifted) atomicAdd(shifted, 1);
+    if (tid == 0 && flag) *flag = 1;
     __syncthreads();
   }
-  // Rinv column c by back substitution (thread per column)
-  for (int c = threadIdx.x; c < b; c += blockDim.x) {
-    double* x = Rinv + c;  // column c with stride ldr
-    for (int i = b - 1; i > c; --i) x[(int64_t)i * ldr] = 0.0;
-    x[(int64_t)c * ldr] = 1.0 / R[c * b + c];
+  // scale: R_jj = sqrt(d_j), R_jc = (R_jj R_jc) / R_jj
+  for (int t = tid; t < b * b; t += blockDim.x) {
+    const int i = t / b, c = t % b;
+    if (c > i) R[t] = R[t] / sqrt(R[i * b + i]);
+  }
+  __syncthreads();
+  for (int i = tid; i < b; i += blockDim.x) R[i * b + i] = sqrt(R[i * b + i]);
+  __syncthreads();
+  // column c of R^{-1} by back substitution (thread per column), in LDS
+  for (int c = tid; c < b; c += blockDim.x) {
+    for (int i = b - 1; i > c; --i) X[i * b + c] = 0.0;
+    X[c * b + c] = 1.0 / R[c * b + c];
     for (int i = c - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int t = i + 1; t <= c; ++t) s += R[i * b + t] * x[(int64_t)t * ldr];
-      x[(int64_t)i * ldr] = -s / R[i * b + i];
+      double acc = 0.0;
+      for (int t = i + 1; t <= c; ++t) acc += R[i * b + t] * X[t * b + c];
+      X[i * b + c] = -acc / R[i * b + i];
     }
   }
+  __syncthreads();
+  for (int t = tid; t < b * b; t += blockDim.x)
+    Rinv[(int64_t)(t / b) * ldr + t % b] = X[t];
 }
 
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
@@ -347,7 +359,17 @@ template void launch_panel_gemm<float, double>(int64_t, int, int, const float*,
 void launch_chol_inv(int b, const double* G, int64_t ldg, double* Rinv,
                      int64_t ldr, double* work, int64_t nrows, int* shifted,
                      hipStream_t st, int* flag, const int* gate) {
-  const size_t lds = (b <= kCholLdsMax) ? (size_t)b * b * sizeof(double) : 0;
+  static const bool attr = [] {
+    // R and R^{-1} for b up to kCholLdsMax exceed the default 64 KB
+    if (hipFuncSetAttribute((const void*)chol_inv_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            2 * kCholLdsMax * kCholLdsMax * (int)sizeof(double)) !=
+        hipSuccess)
+      (void)hipGetLastError();
+    return true;
+  }();
+  (void)attr;
+  const size_t lds = (b <= kCholLdsMax) ? 2 * (size_t)b * b * sizeof(double) : 0;
   hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), lds, st, b, G, ldg,
                      Rinv, ldr, work, nrows, shifted, flag, gate);
   MC_CHECK_LAUNCH();

@@ -180,7 +180,7 @@ mc_status mc_k_cholqr2(int64_t N, int32_t b, const double* H, void* stream,
     d2.reserve(N * b, st);
     G.reserve((int64_t)b * b, st);
     Rinv.reserve((int64_t)b * b, st);
-    work.reserve((int64_t)b * b, st);
+    work.reserve(2 * (int64_t)b * b, st);
     shifted.reserve(1, st);
     MC_HIP(hipMemsetAsync(shifted.p, 0, sizeof(int), st));
     const int64_t cap = mcsvt::gram_splits(N, b, b, 1) * b * b;

@@ -96,8 +96,9 @@ void launch_panel_gemm(int64_t N, int p, int q, const XT* X, int64_t ldx,
                        int64_t ldc0, OT* C, int64_t ldc, hipStream_t st,
                        const int* gate = nullptr);
 
-constexpr int kCholLdsMax = 90;   // b*b doubles in LDS up to this size
+constexpr int kCholLdsMax = 90;   // R and R^-1 (2 b*b doubles) in LDS up to this b
 // flag (optional) is set to 1 when a diagonal shift was needed
+// work: 2 b*b doubles, used when b > kCholLdsMax
 void launch_chol_inv(int b, const double* G, int64_t ldg, double* Rinv,
                      int64_t ldr, double* work, int64_t nrows, int* shifted,
                      hipStream_t st, int* flag = nullptr,

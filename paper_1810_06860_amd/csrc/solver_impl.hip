@@ -178,7 +178,7 @@ void SolverT<P, VT, AT>::ensure(int bmax, int Lmax, int kmax) {
   G_.reserve(Lc * Lc, st_);
   Cg_.reserve(Lc * b, st_);
   Rinv_.reserve(b * b, st_);
-  chol_work_.reserve(b * b, st_);
+  chol_work_.reserve(2 * b * b, st_);
   const int64_t mx = std::max(m_, n_);
   gram_cap_ = std::max({gram_splits(mx, (int)Lc, (int)Lc, 1) * Lc * Lc,
                         gram_splits(m_, (int)b, (int)b, 1) * b * b,
