@@ -112,3 +112,30 @@ def test_graph_replay_matches_eager_launches():
     Ub, sb, Vb = b.factors()
     assert np.array_equal(Ua, Ub) and np.array_equal(sa, sb) and np.array_equal(Va, Vb)
     assert np.array_equal(a.y(), b.y())
+
+
+@pytest.mark.parametrize("name,steps", [("ratings70k_s10", 60), ("ratings140k_s10", 30)])
+def test_svt_steps_match_oracle_ratings_scaled(name, steps):
+    # power-law sampled integer ratings at 1/10 scale (m, n / 10, nnz / 100):
+    # strategy-1 recycling from step 50 with the Ritz guard, adaptive p
+    prob, prm = synth.make_problem(name)
+    orc = FastSVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    from paper_1810_06860_amd import SVT
+    g = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    assert g.result()["c"] == orc.c
+    worst = 0.0
+    for i in range(steps):
+        oi = orc.step()
+        gi = g.step()
+        assert (gi["r"], gi["k"], gi["p"], gi["fresh"], gi["recycled"], gi["rejected"]) == \
+            (oi.r, oi.k, oi.p, oi.fresh, oi.recycled, oi.rejected), i
+        worst = max(worst, abs(gi["res"] - oi.res) / oi.res)
+        np.testing.assert_allclose(g.sigma(), oi.S, rtol=1e-7)
+    U, sig, V = g.factors()
+    Xg = (U * sig) @ V.T
+    Xo = (orc.U * orc.sig) @ orc.V.T
+    rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
+    print(f"{name}: {steps} steps, rank {g.result()['rank']}, res {gi['res']:.4f}, "
+          f"max res rel diff {worst:.1e}, X rel diff {rel:.1e}")
+    assert worst < 1e-7
+    assert rel < 1e-7
