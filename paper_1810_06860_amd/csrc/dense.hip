@@ -18,11 +18,100 @@ namespace {
 
 constexpr int GT = 32;   // gram tile
 
+__device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
+                               double* __restrict__ Rinv, int64_t ldr, double* R,
+                               double* X, int64_t nrows, int* __restrict__ shifted,
+                               int* __restrict__ flag) {
+  __shared__ double trace;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    double t = 0.0;
+    for (int i = 0; i < b; ++i) t += G[(int64_t)i * ldg + i];
+    trace = t;
+  }
+  __syncthreads();
+  const double u = 1.1102230246251565e-16;
+  double shift = 0.0;
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    for (int t = tid; t < b * b; t += blockDim.x) {
+      const int i = t / b, j = t % b;
+      double v = (i <= j) ? G[(int64_t)i * ldg + j] : 0.0;
+      if (i == j) v += shift;
+      R[t] = v;
+    }
+    __syncthreads();
+    bool failed = false;
+    for (int j = 0; j < b; ++j) {
+      // a pivot below 1e-13 of its original diagonal means kappa(H) of
+      // order 1e6 or worse: Cholesky QR would lose all orthogonality
+      const double d = R[j * b + j];
+      const double gjj = G[(int64_t)j * ldg + j] + shift;
+      if (!(d > 1e-13 * gjj) || !(d > 1e-300)) {
+        failed = true;                               // the same for every thread
+        break;
+      }
+      const double rd = 1.0 / d;
+      const int rem = b - j - 1;
+      for (int t = tid; t < rem * rem; t += blockDim.x) {
+        const int i = j + 1 + t / rem, c = j + 1 + t % rem;
+        if (c >= i) R[i * b + c] -= R[j * b + i] * R[j * b + c] * rd;
+      }
+      __syncthreads();
+    }
+    if (!failed) break;
+    // shifted Cholesky QR: s = 11 (N b + b (b + 1)) u ||X||^2, ||X||^2 <= tr G
+    shift = (shift == 0.0)
+                ? 11.0 * ((double)nrows * b + (double)b * (b + 1)) * u *
+                      fmax(trace, 1e-300)
+                : shift * 100.0;
+    if (tid == 0 && shifted) atomicAdd(shifted, 1);
+    if (tid == 0 && flag) *flag = 1;
+    __syncthreads();
+  }
+  // scale: R_jj = sqrt(d_j), R_jc = (R_jj R_jc) / R_jj
+  for (int t = tid; t < b * b; t += blockDim.x) {
+    const int i = t / b, c = t % b;
+    if (c > i) R[t] = R[t] / sqrt(R[i * b + i]);
+  }
+  __syncthreads();
+  for (int i = tid; i < b; i += blockDim.x) R[i * b + i] = sqrt(R[i * b + i]);
+  __syncthreads();
+  // column c of R^{-1} by back substitution (thread per column), in LDS
+  for (int c = tid; c < b; c += blockDim.x) {
+    for (int i = b - 1; i > c; --i) X[i * b + c] = 0.0;
+    X[c * b + c] = 1.0 / R[c * b + c];
+    for (int i = c - 1; i >= 0; --i) {
+      double acc = 0.0;
+      for (int t = i + 1; t <= c; ++t) acc += R[i * b + t] * X[t * b + c];
+      X[i * b + c] = -acc / R[i * b + i];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < b * b; t += blockDim.x)
+    Rinv[(int64_t)(t / b) * ldr + t % b] = X[t];
+}
+
+// Fused completion (mode 1: sum the partials into C; mode 2: also Cholesky +
+// R^{-1} of C, p = q): every participating workgroup counts itself on
+// `counter` after its partial is written; the last one does the completion
+// and resets the counter (no waiting on other workgroups).
+struct GramTail {
+  int mode = 0;
+  int* counter = nullptr;
+  int expected = 0, nsplit = 0;
+  double* C = nullptr;
+  int64_t ldc = 0;
+  double* Rinv = nullptr;
+  int64_t ldr = 0, nrows = 0;
+  int* shifted = nullptr;
+  int* flag = nullptr;
+};
+
 template <class IT, class AT>
 __global__ __launch_bounds__(256) void gram_kernel(
     int64_t N, int p, int q, const IT* __restrict__ A, int64_t lda,
     const IT* __restrict__ B, int64_t ldb, AT* __restrict__ part,
-    int64_t rows_per_split, int sym, const int* __restrict__ gate) {
+    int64_t rows_per_split, int sym, const int* __restrict__ gate, GramTail tail) {
   if (gate && *gate == 0) return;
   const int ti = blockIdx.x, tj = blockIdx.y, sp = blockIdx.z;
   if (sym && tj < ti) return;
@@ -59,6 +148,32 @@ __global__ __launch_bounds__(256) void gram_kernel(
   if (i0 < p && j0 + 1 < q) out[(int64_t)i0 * q + j0 + 1] = acc01;
   if (i0 + 1 < p && j0 < q) out[(int64_t)(i0 + 1) * q + j0] = acc10;
   if (i0 + 1 < p && j0 + 1 < q) out[(int64_t)(i0 + 1) * q + j0 + 1] = acc11;
+  if (tail.mode == 0) return;
+  __shared__ int is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = atomicAdd(tail.counter, 1) == tail.expected - 1;
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  const int64_t tot = (int64_t)p * q;
+  for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) {
+    const int i = (int)(t / q), j = (int)(t % q);
+    int si = i, sj = j;
+    if (sym && (i / GT) > (j / GT)) { si = j; sj = i; }   // mirrored tile
+    double acc = 0.0;
+    for (int sp2 = 0; sp2 < tail.nsplit; ++sp2)
+      acc += (double)part[(int64_t)sp2 * tot + (int64_t)si * q + sj];
+    tail.C[(int64_t)i * tail.ldc + j] = acc;
+  }
+  __threadfence();
+  __syncthreads();
+  if (tail.mode == 2) {
+    extern __shared__ double lds[];
+    chol_inv_block(p, tail.C, tail.ldc, tail.Rinv, tail.ldr, lds, lds + (size_t)p * p,
+                   tail.nrows, tail.shifted, tail.flag);
+  }
+  if (threadIdx.x == 0) *tail.counter = 0;
 }
 
 // Sum of the split partials.  `lanes` consecutive threads (a power of two
@@ -165,73 +280,7 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(
   const bool in_lds = b <= kCholLdsMax;
   double* R = in_lds ? lds : work;                   // b x b, row-major
   double* X = in_lds ? lds + (size_t)b * b : work + (size_t)b * b;   // R^{-1}
-  __shared__ double trace;
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    double t = 0.0;
-    for (int i = 0; i < b; ++i) t += G[(int64_t)i * ldg + i];
-    trace = t;
-  }
-  __syncthreads();
-  const double u = 1.1102230246251565e-16;
-  double shift = 0.0;
-  for (int attempt = 0; attempt < 6; ++attempt) {
-    for (int t = tid; t < b * b; t += blockDim.x) {
-      const int i = t / b, j = t % b;
-      double v = (i <= j) ? G[(int64_t)i * ldg + j] : 0.0;
-      if (i == j) v += shift;
-      R[t] = v;
-    }
-    __syncthreads();
-    bool failed = false;
-    for (int j = 0; j < b; ++j) {
-      // a pivot below 1e-13 of its original diagonal means kappa(H) of
-      // order 1e6 or worse: Cholesky QR would lose all orthogonality
-      const double d = R[j * b + j];
-      const double gjj = G[(int64_t)j * ldg + j] + shift;
-      if (!(d > 1e-13 * gjj) || !(d > 1e-300)) {
-        failed = true;                               // the same for every thread
-        break;
-      }
-      const double rd = 1.0 / d;
-      const int rem = b - j - 1;
-      for (int t = tid; t < rem * rem; t += blockDim.x) {
-        const int i = j + 1 + t / rem, c = j + 1 + t % rem;
-        if (c >= i) R[i * b + c] -= R[j * b + i] * R[j * b + c] * rd;
-      }
-      __syncthreads();
-    }
-    if (!failed) break;
-    // shifted Cholesky QR: s = 11 (N b + b (b + 1)) u ||X||^2, ||X||^2 <= tr G
-    shift = (shift == 0.0)
-                ? 11.0 * ((double)nrows * b + (double)b * (b + 1)) * u *
-                      fmax(trace, 1e-300)
-                : shift * 100.0;
-    if (tid == 0 && shifted) atomicAdd(shifted, 1);
-    if (tid == 0 && flag) *flag = 1;
-    __syncthreads();
-  }
-  // scale: R_jj = sqrt(d_j), R_jc = (R_jj R_jc) / R_jj
-  for (int t = tid; t < b * b; t += blockDim.x) {
-    const int i = t / b, c = t % b;
-    if (c > i) R[t] = R[t] / sqrt(R[i * b + i]);
-  }
-  __syncthreads();
-  for (int i = tid; i < b; i += blockDim.x) R[i * b + i] = sqrt(R[i * b + i]);
-  __syncthreads();
-  // column c of R^{-1} by back substitution (thread per column), in LDS
-  for (int c = tid; c < b; c += blockDim.x) {
-    for (int i = b - 1; i > c; --i) X[i * b + c] = 0.0;
-    X[c * b + c] = 1.0 / R[c * b + c];
-    for (int i = c - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int t = i + 1; t <= c; ++t) acc += R[i * b + t] * X[t * b + c];
-      X[i * b + c] = -acc / R[i * b + i];
-    }
-  }
-  __syncthreads();
-  for (int t = tid; t < b * b; t += blockDim.x)
-    Rinv[(int64_t)(t / b) * ldr + t % b] = X[t];
+  chol_inv_block(b, G, ldg, Rinv, ldr, R, X, nrows, shifted, flag);
 }
 
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
@@ -306,7 +355,7 @@ void launch_gram(int64_t N, int p, int q, const IT* A, int64_t lda, const IT* B,
   splits = std::max<int64_t>(1, ceil_div(std::max<int64_t>(N, 1), rps));
   dim3 grid((unsigned)ceil_div(p, GT), (unsigned)ceil_div(q, GT), (unsigned)splits);
   hipLaunchKernelGGL((gram_kernel<IT, AT>), grid, dim3(256), 0, st, N, p, q, A,
-                     lda, B, ldb, part, rps, sym, gate);
+                     lda, B, ldb, part, rps, sym, gate, GramTail());
   MC_CHECK_LAUNCH();
   const int64_t tot = (int64_t)p * q;
   int lanes = 1;   // threads per output: about 16 splits each, at most 64
@@ -325,6 +374,66 @@ template void launch_gram<float, float>(int64_t, int, int, const float*,
                                         int64_t, const float*, int64_t, double*,
                                         int64_t, int, float*, int64_t,
                                         hipStream_t, const int*);
+
+// Gram (or cross-Gram) with its completion in the same launch: C = A^T B
+// (mode 1) or, with A = B, also Rinv = R^{-1} of C = R^T R (mode 2).
+template <class IT, class AT>
+void launch_gram_fused(int64_t N, int p, int q, const IT* A, int64_t lda, const IT* B,
+                       int64_t ldb, double* C, int64_t ldc, int sym, AT* part,
+                       int64_t part_cap, int* counter, double* Rinv, int64_t ldr,
+                       int64_t nrows, int* shifted, int* flag, hipStream_t st,
+                       const int* gate) {
+  if (p <= 0 || q <= 0) return;
+  const bool chol = Rinv != nullptr;
+  MC_REQUIRE(!chol || (p == q && p <= kCholLdsMax), kEINVAL, "fused Cholesky size");
+  // at most 64 row splits: one workgroup sums the partials
+  int64_t splits = std::min<int64_t>(64, gram_splits(N, p, q, sym));
+  while (splits > 1 && splits * p * q > part_cap) --splits;
+  MC_REQUIRE(splits * p * q <= part_cap, kEINVAL, "gram partial buffer too small");
+  const int64_t rps = round_up(ceil_div(std::max<int64_t>(N, 1), splits), GT);
+  splits = std::max<int64_t>(1, ceil_div(std::max<int64_t>(N, 1), rps));
+  const int64_t tp = ceil_div(p, GT), tq = ceil_div(q, GT);
+  int64_t tiles = 0;
+  for (int64_t a = 0; a < tp; ++a)
+    for (int64_t c = 0; c < tq; ++c)
+      if (!sym || c >= a) ++tiles;
+  GramTail t;
+  t.mode = chol ? 2 : 1;
+  t.counter = counter;
+  t.expected = (int)(tiles * splits);
+  t.nsplit = (int)splits;
+  t.C = C;
+  t.ldc = ldc;
+  t.Rinv = Rinv;
+  t.ldr = ldr;
+  t.nrows = nrows;
+  t.shifted = shifted;
+  t.flag = flag;
+  static const bool attr = [] {
+    for (const void* f : {(const void*)gram_kernel<double, double>,
+                          (const void*)gram_kernel<float, float>})
+      if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              2 * kCholLdsMax * kCholLdsMax * (int)sizeof(double)) !=
+          hipSuccess)
+        (void)hipGetLastError();
+    return true;
+  }();
+  (void)attr;
+  const size_t lds = chol ? 2 * (size_t)p * p * sizeof(double) : 0;
+  dim3 grid((unsigned)tp, (unsigned)tq, (unsigned)splits);
+  hipLaunchKernelGGL((gram_kernel<IT, AT>), grid, dim3(256), lds, st, N, p, q, A, lda, B,
+                     ldb, part, rps, sym, gate, t);
+  MC_CHECK_LAUNCH();
+}
+template void launch_gram_fused<double, double>(int64_t, int, int, const double*, int64_t,
+                                                const double*, int64_t, double*, int64_t,
+                                                int, double*, int64_t, int*, double*,
+                                                int64_t, int64_t, int*, int*, hipStream_t,
+                                                const int*);
+template void launch_gram_fused<float, float>(int64_t, int, int, const float*, int64_t,
+                                              const float*, int64_t, double*, int64_t, int,
+                                              float*, int64_t, int*, double*, int64_t,
+                                              int64_t, int*, int*, hipStream_t, const int*);
 
 template <class XT, class OT>
 void launch_panel_gemm(int64_t N, int p, int q, const XT* X, int64_t ldx,

@@ -88,6 +88,16 @@ void launch_gram(int64_t N, int p, int q, const IT* A, int64_t lda, const IT* B,
                  int64_t ldb, double* C, int64_t ldc, int sym, AT* part,
                  int64_t part_cap, hipStream_t st, const int* gate = nullptr);
 
+// The same with the completion in one launch: C (mode "cross", Rinv null), or
+// with A = B also Rinv = R^{-1} for C = R^T R (shifted retry as in
+// launch_chol_inv).  `counter` is a device int that is 0 between launches.
+template <class IT, class AT>
+void launch_gram_fused(int64_t N, int p, int q, const IT* A, int64_t lda, const IT* B,
+                       int64_t ldb, double* C, int64_t ldc, int sym, AT* part,
+                       int64_t part_cap, int* counter, double* Rinv, int64_t ldr,
+                       int64_t nrows, int* shifted, int* flag, hipStream_t st,
+                       const int* gate = nullptr);
+
 // C = beta C0 + alpha X W diag(colscale)   (colscale may be null)
 template <class XT, class OT>
 void launch_panel_gemm(int64_t N, int p, int q, const XT* X, int64_t ldx,

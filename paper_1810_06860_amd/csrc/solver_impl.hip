@@ -39,6 +39,10 @@ void swap_buf(DevBuf<T>& a, DevBuf<T>& b) {
 }
 
 // algorithmic bytes of one SpMM: values + indices + pointers + panel in + out
+// Gram products over at most this many rows finish (and factor) in the same
+// launch; taller panels keep many row splits and a separate reduction
+constexpr int64_t kFuseRows = 8192;
+
 double spmm_bytes(int64_t nnz, int64_t rows, int64_t cols, int b, int sv, int sx) {
   return (double)nnz * (sv + 4) + 4.0 * (rows + 1) + (double)cols * b * sx +
          (double)rows * b * sx;
@@ -56,6 +60,8 @@ class SolverT final : public Solver {
       : Solver(m, n, nnz, prm, st) {
     shift_count_.reserve(1, st_);
     blk_flag_.reserve(1, st_);
+    fuse_ctr_.reserve(1, st_);
+    MC_HIP(hipMemsetAsync(fuse_ctr_.p, 0, sizeof(int), st_));   // 0 between launches
     ctr_.reserve(2, st_);
     MC_HIP(hipHostMalloc((void**)&hctr_, 2 * sizeof(uint32_t)));
     MC_HIP(hipMemsetAsync(shift_count_.p, 0, sizeof(int), st_));
@@ -139,7 +145,7 @@ class SolverT final : public Solver {
   DevBuf<AT> gram_part_, spmm_part_;
   DevBuf<double> G_, Cg_, Rinv_, chol_work_, S_, Sinv_, D_, Wk_, sig_, sdd_part_,
       scal_, ritz_part_, ritz_out_, obs_;
-  DevBuf<int> shift_count_, blk_flag_;
+  DevBuf<int> shift_count_, blk_flag_, fuse_ctr_;
   DevBuf<uint32_t> ctr_;          // (step, attempt) of the Gaussian stream
   uint32_t* hctr_ = nullptr;      // pinned staging for ctr_
   std::map<GraphKey, hipGraphExec_t> graphs_;
@@ -310,13 +316,19 @@ void SolverT<P, VT, AT>::spmm_yt_rr(const P* X, int64_t ldx, P* out, int64_t ldo
 template <class P, class VT, class AT>
 void SolverT<P, VT, AT>::cholqr_pass(const P* Hin, int64_t ldin, P* out, int64_t ldo,
                                      int b, const int* gate) {
-  prof.begin(kProfGram, (double)sizeof(P) * m_ * b, 1.0 * m_ * b * (b + 1), ls());
-  launch_gram<P, AT>(m_, b, b, Hin, ldin, Hin, ldin, G_.p, b, 1, gram_part_.p,
-                     gram_cap_, ls(), gate);
-  prof.end(ls());
-  prof.begin(kProfChol, 16.0 * b * b, b * (double)b * b, ls());
-  launch_chol_inv(b, G_.p, b, Rinv_.p, b, chol_work_.p, m_, shift_count_.p, ls(),
-                  blk_flag_.p, gate);
+  // Gram, its completion and the Cholesky inverse in one launch
+  prof.begin(kProfGram, (double)sizeof(P) * m_ * b,
+             1.0 * m_ * b * (b + 1) + (double)b * b * b, ls());
+  if (b <= kCholLdsMax && m_ <= kFuseRows) {
+    launch_gram_fused<P, AT>(m_, b, b, Hin, ldin, Hin, ldin, G_.p, b, 1, gram_part_.p,
+                             gram_cap_, fuse_ctr_.p, Rinv_.p, b, m_, shift_count_.p,
+                             blk_flag_.p, ls(), gate);
+  } else {
+    launch_gram<P, AT>(m_, b, b, Hin, ldin, Hin, ldin, G_.p, b, 1, gram_part_.p,
+                       gram_cap_, ls(), gate);
+    launch_chol_inv(b, G_.p, b, Rinv_.p, b, chol_work_.p, m_, shift_count_.p, ls(),
+                    blk_flag_.p, gate);
+  }
   prof.end(ls());
   prof.begin(kProfGemm, 2.0 * sizeof(P) * m_ * b, 2.0 * m_ * b * b, ls());
   launch_panel_gemm<P, P>(m_, b, b, Hin, ldin, Rinv_.p, b, 1.0, nullptr, 0.0,
@@ -329,8 +341,13 @@ template <class P, class VT, class AT>
 void SolverT<P, VT, AT>::project(const P* Hin, int64_t ldin, P* Hout, int jb, int b,
                                  int Lw, const int* gate) {
   prof.begin(kProfGram, (double)sizeof(P) * m_ * (jb + b), 2.0 * m_ * jb * b, ls());
-  launch_gram<P, AT>(m_, jb, b, Qw_.p, Lw, Hin, ldin, Cg_.p, b, 0, gram_part_.p,
-                     gram_cap_, ls(), gate);
+  if ((int64_t)jb * b <= 128 * 128 && m_ <= kFuseRows)
+    launch_gram_fused<P, AT>(m_, jb, b, Qw_.p, Lw, Hin, ldin, Cg_.p, b, 0, gram_part_.p,
+                             gram_cap_, fuse_ctr_.p, nullptr, 0, 0, nullptr, nullptr,
+                             ls(), gate);
+  else
+    launch_gram<P, AT>(m_, jb, b, Qw_.p, Lw, Hin, ldin, Cg_.p, b, 0, gram_part_.p,
+                       gram_cap_, ls(), gate);
   prof.end(ls());
   prof.begin(kProfGemm, (double)sizeof(P) * m_ * (jb + 2 * b), 2.0 * m_ * jb * b, ls());
   launch_panel_gemm<P, P>(m_, jb, b, Qw_.p, Lw, Cg_.p, b, -1.0, nullptr, 1.0, Hin,
