@@ -29,7 +29,40 @@ HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6          # MI355X FP64 (vector and matrix)
 FP32_PEAK_TFLOPS = 157.3
 
-HBM_FAMILIES = ("spmm_fwd", "spmm_bwd", "sddmm")
+# families whose algorithmic intensity is below the FP64 ridge (78.6 TFLOP/s
+# / 8 TB/s): the sparse products, the fused SDDMM, and the Gram / panel
+# products of the tall-skinny blocks (2 N b^2 flops on 8 N b bytes, b <= 40)
+HBM_FAMILIES = ("spmm_fwd", "spmm_bwd", "sddmm", "gram", "panel_gemm")
+
+
+def source_sha():
+    """Digest of the kernel sources (the committed HBM counters are valid
+    only for the kernels they were taken on)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1810_06860_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) +
+                    glob.glob(os.path.join(csrc, "*.hpp"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, family, precision):
+    """HBM bytes per launch of `family` from the committed PMC runs
+    (FETCH_SIZE + WRITE_SIZE, calibrated), or None."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
+            tj = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if tj.get("source_sha256") != source_sha():
+        return None
+    ent = tj.get(workload)
+    if not ent or ent.get("precision") != precision:
+        return None
+    return ent.get("families", {}).get(family)
 
 
 def log(msg):
@@ -61,7 +94,7 @@ def parse():
     return ap.parse_args()
 
 
-def roofline(prof, prec):
+def roofline(prof, prec, workload):
     fams = {k: v for k, v in prof.items() if v["launches"] > 0 and v["ms"] > 0}
     if not fams:
         return None, None
@@ -78,7 +111,7 @@ def roofline(prof, prec):
         roof = dict(bound="alu", achieved=round(achieved, 4), peak=peak,
                     unit="TFLOP/s")
     roof["frac"] = round(roof["achieved"] / roof["peak"], 5)
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(workload, dom, prec)
     roof["kernel"] = dom
     roof["launches"] = v["launches"]
     roof["avg_launch_us"] = round(per_launch_ms * 1e3, 3)
@@ -227,7 +260,7 @@ def main():
     value = done / dt
 
     log(f"profiled pass: {pdone} steps")
-    dom, roof = roofline(prof, a.precision)
+    dom, roof = roofline(prof, a.precision, a.workload)
     U, sig, V = solver.factors()
     res_last = infos[-1]["res"]
     acc = dict(res_last=res_last, rank=infos[-1]["r"], steps_total=a.warmup + done,
