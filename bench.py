@@ -182,9 +182,12 @@ def serving_leg(a):
                            max_active=a.serve_slots, stream_pool=streams,
                            on_done=lambda s, n: log(f"serving: {n}/{len(reqs)} done "
                                                     f"(req {s.id}, {s.steps} steps, "
-                                                    f"{s.latency:.2f} s)"))
+                                                    f"{s.latency:.2f} s{', ' + s.error if s.error else ''})"))
     torch.cuda.synchronize()
     out = serving.summarize(served)
+    errs = [f"req {s.id}: {s.error}" for s in served if s.error]
+    if errs:
+        out["errors"] = errs
     out.update(precision="fp32 kernels, fp64 eig", budget_gib=a.serve_budget_gib,
                slots=a.serve_slots, streams=a.serve_streams,
                nnz_total=int(sum(p.nnz for p in problems)),

@@ -54,7 +54,8 @@ void* dev_alloc(size_t bytes, hipStream_t stream) {
   const hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess || !p) {
     (void)hipGetLastError();
-    throw Error(kENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    throw Error(kENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed (" +
+                             hipGetErrorString(e) + ")");
   }
   return p;
 }

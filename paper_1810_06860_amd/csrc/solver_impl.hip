@@ -107,8 +107,9 @@ class SolverT final : public Solver {
   hipStream_t ls() const { return capturing_ ? cap_ : st_; }
   // capture needs an eigensolve without host round trips
   bool graphs_ok(int w, int k) const {
-    return prm_.use_graphs && !prof.on && EigSolver::device_only(w, k);
+    return prm_.use_graphs && !prof.on && !graphs_broken_ && EigSolver::device_only(w, k);
   }
+  bool graphs_broken_ = false;
   template <class F> void run_graph(const GraphKey& key, F&& body);
   void clear_graphs() {
     for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
@@ -455,23 +456,31 @@ void SolverT<P, VT, AT>::run_graph(const GraphKey& key, F&& body) {
     if (!cap_) MC_HIP(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
     if (graphs_.size() >= 64) clear_graphs();
     hipGraph_t g = nullptr;
-    MC_HIP(hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal));
+    // relaxed: solves driven from other host threads may allocate meanwhile
+    // (nothing inside the captured body allocates)
+    MC_HIP(hipStreamBeginCapture(cap_, hipStreamCaptureModeRelaxed));
     capturing_ = true;
+    bool ok = true;
     try {
       body();
-    } catch (...) {
-      capturing_ = false;
-      hipGraph_t junk = nullptr;
-      (void)hipStreamEndCapture(cap_, &junk);
-      if (junk) (void)hipGraphDestroy(junk);
-      throw;
+    } catch (const Error&) {
+      ok = false;
     }
     capturing_ = false;
-    MC_HIP(hipStreamEndCapture(cap_, &g));
+    const hipError_t ee = hipStreamEndCapture(cap_, &g);
     hipGraphExec_t ge = nullptr;
-    const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    MC_HIP(e);
+    if (ok && ee == hipSuccess && g) ok = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (!ok || ee != hipSuccess || !ge) {
+      // the runtime gave up the capture (it can, when other host threads use
+      // the device meanwhile): run this call kernel by kernel, and keep this
+      // solve on direct launches from now on; results are the same
+      (void)hipGetLastError();
+      if (ge) (void)hipGraphExecDestroy(ge);
+      graphs_broken_ = true;
+      body();
+      return;
+    }
     it = graphs_.emplace(key, ge).first;
   }
   MC_HIP(hipGraphLaunch(it->second, st_));

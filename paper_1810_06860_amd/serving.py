@@ -52,6 +52,7 @@ class Served:
     res: float
     footprint: int
     factors: tuple = None
+    error: str = ""
 
     @property
     def latency(self):
@@ -71,14 +72,17 @@ def _default_factory(stream_pool):
                 counter[0] += 1
             st = C.c_void_p(s.cuda_stream)
         p = req.problem
-        return SVT(p.m, p.n, p.rows, p.cols, p.vals, req.params, stream=st)
+        # direct launches: graph capture from one host thread is not reliable
+        # while other threads use the device (the runtime may drop it)
+        prm = dict(req.params, use_graphs=0)
+        return SVT(p.m, p.n, p.rows, p.cols, p.vals, prm, stream=st)
     return make
 
 
 def _run_to_end(solver, i_max):
     """Step one solve until it converges or reaches i_max."""
     from .svt import MCError
-    steps, last, status = 0, {}, MC_OK
+    steps, last, status, err = 0, {}, MC_OK, ""
     try:
         while steps < i_max:
             last = solver.step()
@@ -86,8 +90,8 @@ def _run_to_end(solver, i_max):
             if last.get("converged"):
                 break
     except MCError as e:
-        status = e.status
-    return steps, last, status
+        status, err = e.status, str(e)
+    return steps, last, status, err
 
 
 def serve(requests, budget_bytes, max_active=16, solver_factory=None,
@@ -118,7 +122,7 @@ def serve(requests, budget_bytes, max_active=16, solver_factory=None,
             if device is not None:
                 device()
             solver = solver_factory(req)
-            steps, last, status = _run_to_end(solver, req.params.get("i_max", 200))
+            steps, last, status, err = _run_to_end(solver, req.params.get("i_max", 200))
             facs = solver.factors() if keep_factors and status == MC_OK else None
             solver.close()
             rec = Served(id=req.id, t_arrival=req.t_arrival, t_admit=t_admit,
@@ -126,7 +130,7 @@ def serve(requests, budget_bytes, max_active=16, solver_factory=None,
                          converged=bool(last.get("converged", 0)),
                          rank=int(last.get("r", 0)),
                          res=float(last.get("res", float("nan"))), footprint=fp,
-                         factors=facs)
+                         factors=facs, error=err)
         except Exception as e:                       # reported after the loop
             errors.append(e)
             rec = None
