@@ -35,63 +35,33 @@ FP32_PEAK_TFLOPS = 157.3
 HBM_FAMILIES = ("spmm_fwd", "spmm_bwd", "sddmm", "gram", "panel_gemm")
 
 
-def source_sha():
-    """Digest of the kernel sources (the committed HBM counters are valid
-    only for the kernels they were taken on)."""
-    import glob
+def source_sha(files):
+    """Digest of kernel source files: committed HBM counters are valid only
+    for the kernels they were taken on."""
     import hashlib
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1810_06860_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.hip")) +
-                    glob.glob(os.path.join(csrc, "*.hpp"))):
-        with open(f, "rb") as fh:
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1810_06860_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
 def measured_traffic(workload, family, precision):
     """HBM bytes per launch of `family` from the committed PMC runs
-    (FETCH_SIZE + WRITE_SIZE, calibrated), or None."""
+    (FETCH_SIZE + WRITE_SIZE, calibrated), or None when absent or when the
+    family's kernel source changed since."""
     try:
         with open(os.path.join(ROOT, "profiles", "traffic.json")) as fh:
             tj = json.load(fh)
-    except (OSError, ValueError):
+        ent = tj[workload]
+        if ent.get("precision") != precision:
+            return None
+        fam = ent["families"][family]
+        if fam["sha256"] != source_sha(fam["sources"]):
+            return None
+        return fam["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
         return None
-    if tj.get("source_sha256") != source_sha():
-        return None
-    ent = tj.get(workload)
-    if not ent or ent.get("precision") != precision:
-        return None
-    return ent.get("families", {}).get(family)
-
-
-def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def parse():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=290)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="image1024")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--cpu-seconds", type=float, default=30.0)
-    ap.add_argument("--prof-steps", type=int, default=60,
-                    help="steps of the event-profiled pass (per-kernel times)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--eager", action="store_true",
-                    help="launch kernel by kernel in the timed region too "
-                         "(no HIP graphs), e.g. under a counter profiler")
-    ap.add_argument("--serve", type=int, default=32,
-                    help="requests of the serving trace to run (0: skip)")
-    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
-    ap.add_argument("--serve-slots", type=int, default=16)
-    ap.add_argument("--serve-streams", type=int, default=4)
-    ap.add_argument("--copy-calib-mib", type=int, default=0,
-                    help="also run a plain device copy of this size (for "
-                         "calibrating HBM counters under a profiler)")
-    return ap.parse_args()
 
 
 def roofline(prof, prec, workload):
