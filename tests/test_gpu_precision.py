@@ -55,3 +55,22 @@ def test_bf16_operator_halves_value_traffic():
         p = s.get_profile()
         per[prec] = p["spmm_fwd"]["bytes"] / max(p["spmm_fwd"]["launches"], 1)
     assert per["fp32"] < per["fp64"] and per["bf16"] < per["fp32"]
+
+
+def test_bf16_and_fp32_on_scaled_ratings_against_fp64():
+    # power-law sampled ratings at 1/10 scale: reduced-precision forms against
+    # the FP64 GPU form after the same number of steps
+    from paper_1810_06860_amd import SVT
+    prob, prm = synth.make_problem("ratings70k_s10")
+    X = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        s = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, dict(prm, precision=prec))
+        for _ in range(40):
+            info = s.step()
+        U, sig, V = s.factors()
+        X[prec] = (U * sig) @ V.T
+        print(f"{prec}: rank {info['r']} res {info['res']:.5f}")
+    for prec, tol in (("fp32", 1e-5), ("bf16", 1e-3)):
+        rel = np.linalg.norm(X[prec] - X["fp64"]) / np.linalg.norm(X["fp64"])
+        print(f"{prec} vs fp64: {rel:.2e}")
+        assert rel < tol

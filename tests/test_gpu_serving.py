@@ -53,3 +53,25 @@ def test_served_results_equal_alone_and_close_to_fp64():
         assert rel < 1e-3
     summ = serving.summarize(served)
     print(summ)
+
+
+def test_step_many_equals_single_steps():
+    # several handles advanced together by mc_svt_step_many (host worker
+    # threads, direct launches) against the same problems stepped one by one
+    from paper_1810_06860_amd import SVT, step_many
+    probs = [synth.planted(260 + 40 * j, 220 + 30 * j, 4 + j, 0.35, seed_data=70 + j,
+                           seed_phi=170 + j) for j in range(4)]
+    prm = dict(eps=1e-6, i_max=40, use_graphs=0)
+    many = [SVT(p.m, p.n, p.rows, p.cols, p.vals, prm) for p in probs]
+    one = [SVT(p.m, p.n, p.rows, p.cols, p.vals, prm) for p in probs]
+    for _ in range(25):
+        infos, status = step_many(many)
+        for j, s in enumerate(one):
+            if status[j] == 0:
+                assert s.step() == infos[j]
+            else:
+                assert status[j] == 7          # MC_EDONE: converged earlier
+    for a, b in zip(many, one):
+        Ua, sa, Va = a.factors()
+        Ub, sb, Vb = b.factors()
+        assert np.array_equal(sa, sb) and np.array_equal(Ua, Ub) and np.array_equal(Va, Vb)
