@@ -64,6 +64,35 @@ def measured_traffic(workload, family, precision):
         return None
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=290)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="image1024")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--cpu-seconds", type=float, default=30.0)
+    ap.add_argument("--prof-steps", type=int, default=60,
+                    help="steps of the event-profiled pass (per-kernel times)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch kernel by kernel in the timed region too "
+                         "(no HIP graphs), e.g. under a counter profiler")
+    ap.add_argument("--serve", type=int, default=32,
+                    help="requests of the serving trace to run (0: skip)")
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for "
+                         "calibrating HBM counters under a profiler)")
+    return ap.parse_args()
+
+
 def roofline(prof, prec, workload):
     fams = {k: v for k, v in prof.items() if v["launches"] > 0 and v["ms"] > 0}
     if not fams:

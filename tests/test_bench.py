@@ -1,0 +1,55 @@
+"""bench.py contract checks that need no GPU."""
+
+import importlib.util
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_arguments_and_defaults():
+    b = _bench()
+    old = sys.argv
+    try:
+        sys.argv = ["bench.py"]
+        a = b.parse()
+    finally:
+        sys.argv = old
+    assert (a.gpus, a.workload, a.precision) == (1, "image1024", "fp64")
+    assert a.steps > 0 and a.warmup >= 0
+
+
+def test_roofline_picks_the_dominant_family():
+    b = _bench()
+    prof = {"spmm_fwd": dict(launches=10, ms=1.0, bytes=8e9, flops=1e9),
+            "eigensolve": dict(launches=2, ms=3.0, bytes=0.0, flops=6e9),
+            "rng": dict(launches=0, ms=0.0, bytes=0.0, flops=0.0)}
+    dom, roof = b.roofline(prof, "fp64", "no-such-workload")
+    assert dom == "eigensolve" and roof["bound"] == "alu" and roof["traffic"] is None
+    assert abs(roof["achieved"] - 6e9 / 2 / 1.5e-3 / 1e12) < 1e-3
+    prof["spmm_fwd"]["ms"] = 10.0
+    dom, roof = b.roofline(prof, "fp64", "no-such-workload")
+    assert dom == "spmm_fwd" and roof["bound"] == "hbm" and roof["unit"] == "GB/s"
+    assert abs(roof["frac"] - roof["achieved"] / 8000.0) < 1e-4
+
+
+def test_measured_traffic_is_tied_to_sources():
+    b = _bench()
+    v = b.measured_traffic("image1024", "gram", "fp64")
+    assert v is None or v > 0
+    assert b.measured_traffic("image1024", "gram", "bf16") is None
