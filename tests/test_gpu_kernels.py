@@ -203,3 +203,26 @@ def test_sddmm_brute_force(K, r):
     np.testing.assert_allclose(x, want_x, rtol=1e-13, atol=1e-13)
     np.testing.assert_allclose(ynew, y + delta * (mv - want_x), rtol=1e-13, atol=1e-13)
     assert ss == pytest.approx(np.sum((mv - want_x) ** 2), rel=1e-12)
+
+
+@pytest.mark.parametrize("transpose", [False, True])
+def test_spmm_empty_rows_and_columns(K, transpose):
+    # rows 0..99 and columns 0..49 hold no entries; a single-entry row and a
+    # single-entry column; outputs of empty rows must be exactly zero
+    m, n = 400, 300
+    rows, cols = _coo(m - 100, n - 50, 9000, 21)
+    rows = rows + 100
+    cols = cols + 50
+    rows = np.concatenate([rows, [5]])
+    cols = np.concatenate([cols, [7]])
+    rng = np.random.default_rng(4)
+    vals = rng.standard_normal(rows.size)
+    A = scipy.sparse.csr_matrix((vals, (rows, cols)), shape=(m, n))
+    for b in (3, 37):
+        X = rng.standard_normal(((m if transpose else n), b))
+        got = K.spmm(m, n, rows, cols, vals, X, transpose=transpose)
+        want = (A.T @ X) if transpose else (A @ X)
+        scale = (abs(A.T) if transpose else abs(A)) @ np.abs(X) + 1e-300
+        assert np.max(np.abs(got - want) / scale) < 1e-14
+        empty = np.flatnonzero(np.asarray(abs(A.T if transpose else A).sum(axis=1)).ravel() == 0)
+        assert empty.size > 0 and np.all(got[empty] == 0.0)

@@ -139,3 +139,57 @@ def test_svt_steps_match_oracle_ratings_scaled(name, steps):
           f"max res rel diff {worst:.1e}, X rel diff {rel:.1e}")
     assert worst < 1e-7
     assert rel < 1e-7
+
+
+@pytest.mark.parametrize("recycle,ritz_tol", [(2, 1e-4), (2, 0.0), (1, 0.0)])
+def test_recycling_strategies_match_oracle(recycle, ritz_tol):
+    # strategy 2 (reuse U) with the guard, and both strategies with the
+    # paper's rule taken literally (no guard): step-by-step against the oracle
+    prob = synth.planted(400, 330, 6, 0.3, seed_data=41, seed_phi=141)
+    prm = dict(eps=1e-6, i_max=45, recycle=recycle, i_reuse=12, q_reuse=4,
+               ritz_tol=ritz_tol, p_init=3, adaptive_p=1)
+    orc = FastSVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    from paper_1810_06860_amd import SVT
+    g = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    recycled = 0
+    for i in range(35):
+        oi = orc.step()
+        gi = g.step()
+        assert (gi["r"], gi["k"], gi["p"], gi["fresh"], gi["recycled"], gi["rejected"]) == \
+            (oi.r, oi.k, oi.p, oi.fresh, oi.recycled, oi.rejected), i
+        assert gi["res"] == pytest.approx(oi.res, rel=1e-8)
+        recycled += gi["recycled"] - gi["rejected"]
+        if oi.converged:
+            break
+    U, sig, V = g.factors()
+    Xg = (U * sig) @ V.T
+    Xo = (orc.U * orc.sig) @ orc.V.T
+    assert np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo) < 1e-8
+    if ritz_tol == 0.0:
+        assert recycled > 0          # the literal rule does recycle here
+
+
+def test_empty_rows_and_columns_and_lifecycle():
+    # a problem with empty rows and columns through whole steps, then the
+    # status codes at convergence and at i_max
+    from paper_1810_06860_amd import MCError, SVT
+    base = synth.planted(300, 260, 5, 0.5, seed_data=52, seed_phi=152)
+    keep = (base.rows >= 20) & (base.cols >= 30)
+    rows, cols, vals = base.rows[keep], base.cols[keep], base.vals[keep]
+    prm = dict(eps=1e-4, i_max=120)
+    orc = FastSVT(base.m, base.n, rows, cols, vals, prm)
+    g = SVT(base.m, base.n, rows, cols, vals, prm)
+    for _ in range(20):
+        oi, gi = orc.step(), g.step()
+        assert (gi["r"], gi["k"]) == (oi.r, oi.k)
+        assert gi["res"] == pytest.approx(oi.res, rel=1e-8)
+    U, sig, V = g.factors()
+    assert np.all(np.abs(U[:20]) < 1e-12 * np.abs(U).max())      # empty rows
+    out = g.solve()
+    assert out["status"] == 0 and out["converged"] == 1
+    with pytest.raises(MCError) as e:
+        g.step()
+    assert e.value.status == 7                                   # MC_EDONE
+    h = SVT(base.m, base.n, rows, cols, vals, dict(prm, i_max=3))
+    out = h.solve()
+    assert out["status"] == 8 and out["iters"] == 3              # MC_ENOTCONV
