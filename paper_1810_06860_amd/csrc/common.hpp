@@ -65,6 +65,13 @@ struct DevBuf {
   // Ensure capacity for `count` elements (contents are NOT preserved).
   T* reserve(size_t count, hipStream_t s) {
     if (count <= n && p) return p;
+    {
+      // buffers grow only outside stream capture (callers size them first)
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (s && hipStreamIsCapturing(s, &cs) == hipSuccess &&
+          cs != hipStreamCaptureStatusNone)
+        throw Error(kEDEVICE, "device buffer growth inside a stream capture");
+    }
     release();
     stream = s;
     size_t want = count ? count : 1;

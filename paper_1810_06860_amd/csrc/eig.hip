@@ -491,8 +491,11 @@ void EigSolver::reserve(int L, hipStream_t st) {
   // tridiagonal path: reflector rows (allocated here, outside any stream
   // capture)
   hh.reserve((size_t)L * L, st);
-  if (L <= tri_big_max())
-    big.reserve(TriBigWork::doubles(L, std::min(L, tri_big_kmax())), st);
+  {
+    // the multi-launch path serves every width up to tri_big_max()
+    const int Lb = std::min(L, tri_big_max());
+    big.reserve(TriBigWork::doubles(Lb, std::min(Lb, tri_big_kmax())), st);
+  }
   if (!hflags) MC_HIP(hipHostMalloc((void**)&hflags, sizeof(int) * 64));
 }
 

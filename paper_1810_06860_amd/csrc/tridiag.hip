@@ -673,6 +673,16 @@ __global__ __launch_bounds__(256) void big_matvec_kernel(
   }
 }
 
+// Ag (L x L, ld L) = G (ld ldg): a kernel, so that the sequence can be
+// captured as a graph
+__global__ __launch_bounds__(256) void copy_square_kernel(int L, const double* __restrict__ G,
+                                                          int64_t ldg, double* __restrict__ Ag) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= (int64_t)L * L) return;
+  const int64_t r = t / L, c = t % L;
+  Ag[t] = G[r * ldg + c];
+}
+
 // A22 -= v w^T + w v^T, w = p - (beta/2)(p^T v) v, on 64 x 64 tiles
 __global__ __launch_bounds__(256) void big_update_kernel(
     int L, int j, double* __restrict__ Ag, const double* __restrict__ Pg,
@@ -816,8 +826,8 @@ __global__ void ns_matrix_kernel(int k, double* __restrict__ C) {
   C[t] = (a == b ? 1.5 : 0.0) - 0.5 * C[t];
 }
 
-// Rayleigh quotients on T and W = H_0 ... H_{L-3} Z: 16 lanes per vector,
-// vector entries vlane + 16 q in registers
+// Rayleigh quotients on T and W = H_0 ... H_{L-3} Z: one wavefront per
+// vector, entries lane + 64 q in registers (q < R)
 template <int R>
 __global__ __launch_bounds__(512) void big_back_kernel(
     int L, int k, const double* __restrict__ Zg, const double* __restrict__ hh,
@@ -825,49 +835,51 @@ __global__ __launch_bounds__(512) void big_back_kernel(
     const double* __restrict__ dg, const double* __restrict__ eg,
     double* __restrict__ S, double* __restrict__ D, double* __restrict__ W,
     int64_t ldw) {
-  const int tid = threadIdx.x, vlane = tid % kVecLanes;
-  const int col = blockIdx.x * (512 / kVecLanes) + tid / kVecLanes;
-  const bool act = col < k;
-  const int cc = act ? col : 0;
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.x * 8 + (threadIdx.x >> 6);
+  if (col >= k) return;                        // whole wavefronts
   double z[R];
   double rq = 0.0;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int i = vlane + kVecLanes * q;
-    const bool in = act && i < L;
+    const int i = lane + 64 * q;
+    const bool in = i < L;
     const int ic = min(i, L - 1);
-    const double zi = in ? Zg[(int64_t)ic * k + cc] : 0.0;
-    const double zp = (in && i + 1 < L) ? Zg[(int64_t)(ic + 1) * k + cc] : 0.0;
+    const double zi = in ? Zg[(int64_t)ic * k + col] : 0.0;
+    const double zp = (in && i + 1 < L) ? Zg[(int64_t)(ic + 1) * k + col] : 0.0;
     z[q] = zi;
     rq += zi * (dg[ic] * zi + 2.0 * eg[ic] * zp);
   }
-  rq = group_sum(rq, kVecLanes);
-  if (act && vlane == 0) {
+  rq = wsum(rq);
+  if (lane == 0) {
     D[col] = rq;
     S[col] = sqrt(fmax(rq, 0.0));
   }
   for (int j = L - 3; j >= 0; --j) {
     const double beta = hbg[j];
     const double rv = hrg[j];
-    double v[R];
+    const double* __restrict__ hr = hh + (int64_t)j * L;
     double dot = 0.0;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int i = vlane + kVecLanes * q;
-      const double h = hh[(int64_t)j * L + min(i, L - 1)];
-      v[q] = i == j + 1 ? 1.0 : (i > j + 1 && i < L ? h * rv : 0.0);
-      dot += v[q] * z[q];
+      const int i = lane + 64 * q;
+      const double h = hr[min(i, L - 1)];
+      const double v = i == j + 1 ? 1.0 : (i > j + 1 && i < L ? h * rv : 0.0);
+      dot += v * z[q];
     }
-    dot = group_sum(dot, kVecLanes) * beta;
-#pragma unroll
-    for (int q = 0; q < R; ++q) z[q] -= dot * v[q];
-  }
-  if (act) {
+    dot = wsum(dot) * beta;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int i = vlane + kVecLanes * q;
-      if (i < L) W[(int64_t)i * ldw + col] = z[q];
+      const int i = lane + 64 * q;
+      const double h = hr[min(i, L - 1)];
+      const double v = i == j + 1 ? 1.0 : (i > j + 1 && i < L ? h * rv : 0.0);
+      z[q] -= dot * v;
     }
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = lane + 64 * q;
+    if (i < L) W[(int64_t)i * ldw + col] = z[q];
   }
 }
 
@@ -899,7 +911,7 @@ void tri_set_lds_attributes(size_t lim) {
       (void)hipGetLastError();
 }
 
-int tri_big_max() { return kVecLanes * 40; }
+int tri_big_max() { return kVecLanes * 64; }
 int tri_big_kmax() { return 140; }       // chol_rinv_kernel keeps k x k in LDS
 
 // trailing block solved in LDS by the tail kernel
@@ -941,8 +953,9 @@ void launch_tri_big(int L, const double* G, int64_t ldg, int k, double* S, doubl
   double* Ri = C + (size_t)k * k;
   double* gpart = Ri + (size_t)k * k;
   const int64_t gcap = gram_splits(L, k, k, 1) * (int64_t)k * k;
-  MC_HIP(hipMemcpy2DAsync(Ag, L * sizeof(double), G, ldg * sizeof(double),
-                          L * sizeof(double), L, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(copy_square_kernel, dim3((unsigned)(((int64_t)L * L + 255) / 256)),
+                     dim3(256), 0, st, L, G, ldg, Ag);
+  MC_CHECK_LAUNCH();
   const int Ls = tail_block(L, lds_bytes);
   const int j0 = L - Ls;
   for (int j = 0; j < j0; ++j) {
@@ -975,12 +988,12 @@ void launch_tri_big(int L, const double* G, int64_t ldg, int k, double* S, doubl
   MC_CHECK_LAUNCH();
   launch_panel_gemm<double, double>(L, k, k, Z2, k, C, k, 1.0, nullptr, 0.0, nullptr, 0, Zg,
                                     k, st);
-  const dim3 grid((unsigned)((k + 512 / kVecLanes - 1) / (512 / kVecLanes)));
-  if (L <= kVecLanes * 24)
-    hipLaunchKernelGGL(big_back_kernel<24>, grid, dim3(512), 0, st, L, k, Zg, hh, hbg,
-                       hrg, dg, eg, S, D, W, ldw);
+  const dim3 grid((unsigned)((k + 7) / 8));
+  if (L <= 512)
+    hipLaunchKernelGGL(big_back_kernel<8>, grid, dim3(512), 0, st, L, k, Zg, hh, hbg, hrg,
+                       dg, eg, S, D, W, ldw);
   else
-    hipLaunchKernelGGL(big_back_kernel<40>, grid, dim3(512), 0, st, L, k, Zg, hh, hbg,
+    hipLaunchKernelGGL(big_back_kernel<16>, grid, dim3(512), 0, st, L, k, Zg, hh, hbg,
                        hrg, dg, eg, S, D, W, ldw);
   MC_CHECK_LAUNCH();
 }

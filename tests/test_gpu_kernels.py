@@ -151,7 +151,7 @@ def test_syev_matches_eigh(K, L, k):
     assert sweeps < 30
 
 
-@pytest.mark.parametrize("L,k", [(200, 50), (480, 100), (600, 140)])
+@pytest.mark.parametrize("L,k", [(200, 50), (480, 100), (600, 140), (900, 90)])
 def test_syev_large_multi_launch_path(K, L, k):
     # beyond one workgroup's LDS: reduction over many workgroups, then LDS
     rng = np.random.default_rng(L + 7)

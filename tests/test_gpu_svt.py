@@ -193,3 +193,22 @@ def test_empty_rows_and_columns_and_lifecycle():
     h = SVT(base.m, base.n, rows, cols, vals, dict(prm, i_max=3))
     out = h.solve()
     assert out["status"] == 8 and out["iters"] == 3              # MC_ENOTCONV
+
+
+def test_large_krylov_width_graph_matches_eager():
+    # k near 45 and p = 3 put L = (p + 1)(k + 10) past one workgroup's LDS:
+    # the multi-launch eigensolver, captured as a graph and launched directly
+    from paper_1810_06860_amd import SVT
+    prob = synth.planted(700, 650, 40, 0.45, seed_data=61, seed_phi=161)
+    prm = dict(eps=1e-8, i_max=12, p_init=3, adaptive_p=0)
+    a = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, dict(prm, use_graphs=1))
+    b = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, dict(prm, use_graphs=0))
+    widest = 0
+    for _ in range(12):
+        ia, ib = a.step(), b.step()
+        assert ia == ib
+        widest = max(widest, 4 * (ia["k"] + 10))
+    assert widest > 160
+    Ua, sa, Va = a.factors()
+    Ub, sb, Vb = b.factors()
+    assert np.array_equal(sa, sb) and np.array_equal(Ua, Ub) and np.array_equal(Va, Vb)
