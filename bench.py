@@ -87,6 +87,8 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-graphs", type=int, default=1,
+                    help="1: served solves replay captured graphs")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for "
                          "calibrating HBM counters under a profiler)")
@@ -179,6 +181,7 @@ def serving_leg(a):
     torch.cuda.synchronize()
     served = serving.serve(reqs, budget_bytes=int(a.serve_budget_gib * (1 << 30)),
                            max_active=a.serve_slots, stream_pool=streams,
+                           graphs=bool(a.serve_graphs),
                            on_done=lambda s, n: log(f"serving: {n}/{len(reqs)} done "
                                                     f"(req {s.id}, {s.steps} steps, "
                                                     f"{s.latency:.2f} s{', ' + s.error if s.error else ''})"))
@@ -188,6 +191,7 @@ def serving_leg(a):
     if errs:
         out["errors"] = errs
     out.update(precision="fp32 kernels, fp64 eig", budget_gib=a.serve_budget_gib,
+               graphs=bool(a.serve_graphs),
                slots=a.serve_slots, streams=a.serve_streams,
                nnz_total=int(sum(p.nnz for p in problems)),
                arrivals="Poisson, mean gap 50 ms", generation_s=round(gen_s, 1))

@@ -166,10 +166,9 @@ mc_status mc_svt_step(mc_svt_t h, mc_svt_step_info* info);
  * mc_svt_step would return; status[j] (may be NULL) the per-handle status,
  * MC_EDONE for a handle that had already converged.  Returns MC_OK if every
  * handle succeeded or was already converged, else the first error.
- * Calls of mc_svt_step_many must not overlap (one caller thread).  Handles
- * stepped concurrently (here or from several host threads) should be created
- * with use_graphs = 0: a graph capture on one thread can be dropped by the
- * runtime while other threads use the device. */
+ * Calls of mc_svt_step_many must not overlap (one caller thread).  If the
+ * runtime drops a handle's graph capture, that handle continues with direct
+ * launches (same results). */
 mc_status mc_svt_step_many(mc_svt_t* hs, int32_t count,
                            mc_svt_step_info* info, mc_status* status);
 

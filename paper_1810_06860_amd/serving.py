@@ -59,7 +59,7 @@ class Served:
         return self.t_done - self.t_arrival
 
 
-def _default_factory(stream_pool):
+def _default_factory(stream_pool, graphs):
     from .svt import SVT
     counter = [0]
     lock = threading.Lock()
@@ -72,9 +72,7 @@ def _default_factory(stream_pool):
                 counter[0] += 1
             st = C.c_void_p(s.cuda_stream)
         p = req.problem
-        # direct launches: graph capture from one host thread is not reliable
-        # while other threads use the device (the runtime may drop it)
-        prm = dict(req.params, use_graphs=0)
+        prm = dict(req.params, use_graphs=int(bool(graphs)))
         return SVT(p.m, p.n, p.rows, p.cols, p.vals, prm, stream=st)
     return make
 
@@ -96,14 +94,16 @@ def _run_to_end(solver, i_max):
 
 def serve(requests, budget_bytes, max_active=16, solver_factory=None,
           footprint_fn=None, clock=time.perf_counter, keep_factors=False,
-          stream_pool=None, on_done=None, device=None):
+          stream_pool=None, on_done=None, device=None, graphs=False):
     """Run the request loop until every request is served.
 
     Returns a list of `Served` records in completion order; `on_done(record,
-    count)` is called as each request completes.
+    count)` is called as each request completes.  With `graphs`, each solve
+    replays captured graphs of its SVD calls (a capture the runtime drops
+    falls back to direct launches for that solve).
     """
     if solver_factory is None:
-        solver_factory = _default_factory(stream_pool)
+        solver_factory = _default_factory(stream_pool, graphs)
     if footprint_fn is None:
         from .svt import footprint
 
