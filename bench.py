@@ -76,8 +76,12 @@ def parse():
     ap.add_argument("--workload", default="image1024")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
-    ap.add_argument("--prof-steps", type=int, default=60,
-                    help="steps of the event-profiled pass (per-kernel times)")
+    ap.add_argument("--prof-steps", type=int, default=0,
+                    help="steps of the event-profiled pass (per-kernel times); "
+                         "0: the same steps as the timed region")
+    ap.add_argument("--ritz-tol", type=float, default=None,
+                    help="override the workload's Ritz guard (0: the paper's "
+                         "recycling rule alone)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="launch kernel by kernel in the timed region too "
@@ -133,6 +137,20 @@ def family_table(prof, total_s):
             ent["TFLOPs"] = round(v["flops"] / (ms * 1e-3) / 1e12, 4)
         out[k] = ent
     return out
+
+
+def factored_rel_diff(f1, f2):
+    """||U1 S1 V1^T - U2 S2 V2^T||_F / ||U2 S2 V2^T||_F without forming the
+    matrices (they can be 140,000 x 27,000)."""
+    import numpy as np
+    U1, s1, V1 = f1
+    U2, s2, V2 = f2
+    A = np.hstack([U1 * s1, -(U2 * s2)])
+    B = np.hstack([V1, V2])
+    num = np.sum((A.T @ A) * (B.T @ B))
+    A2 = U2 * s2
+    den = np.sum((A2.T @ A2) * (V2.T @ V2))
+    return np.sqrt(max(num, 0.0) / den) if den > 0 else 0.0
 
 
 def cpu_baseline(prob, prm, budget_s, max_steps):
@@ -222,6 +240,8 @@ def main():
     prm = dict(prm)
     prm["precision"] = a.precision
     prm["i_max"] = max(prm["i_max"], a.warmup + a.steps)
+    if a.ritz_tol is not None:
+        prm["ritz_tol"] = a.ritz_tol
     if a.eager:
         prm["use_graphs"] = 0
     solver = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
@@ -250,7 +270,7 @@ def main():
     torch.cuda.synchronize()
     tp0 = time.perf_counter()
     pdone = 0
-    for _ in range(min(a.prof_steps, a.steps)):
+    for _ in range(min(a.prof_steps, a.steps) if a.prof_steps > 0 else a.steps):
         pinfo = prof_solver.step()
         pdone += 1
         if pinfo["converged"]:
@@ -274,11 +294,40 @@ def main():
                fresh=sum(i["fresh"] for i in infos),
                recycled=sum(i["recycled"] for i in infos),
                rejected=sum(i["rejected"] for i in infos))
+    if a.precision != "fp64":
+        # the plain FP64 form on the same GPU, same steps: speed and distance
+        ref = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals,
+                  dict(prm, precision="fp64"))
+        for _ in range(a.warmup):
+            ref.step()
+        torch.cuda.synchronize()
+        r0 = time.perf_counter()
+        for _ in range(done):
+            rinfo = ref.step()
+        torch.cuda.synchronize()
+        r1 = time.perf_counter()
+        U64, s64, V64 = ref.factors()
+        ref.close()
+        acc["fp64_steps_per_s"] = round(done / (r1 - r0), 4)
+        acc["fp64_res_last"] = rinfo["res"]
+        acc["rel_err_vs_fp64"] = float(factored_rel_diff((U, sig, V), (U64, s64, V64)))
+        log(f"fp64 form: {acc['fp64_steps_per_s']} steps/s, X rel diff "
+            f"{acc['rel_err_vs_fp64']:.3e}")
     truth = prob.truth_dense()
     if truth is not None:
         X = (U * sig) @ V.T
         acc["rel_err_vs_truth"] = float(np.linalg.norm(X - truth) /
                                         np.linalg.norm(truth))
+    else:
+        # large shapes: on 2^20 cells drawn uniformly (seeded), on and off Phi
+        g = np.random.default_rng(7)
+        ri = g.integers(0, prob.m, 1 << 20)
+        ci = g.integers(0, prob.n, 1 << 20)
+        t = prob.truth_at(ri, ci)
+        if t is not None:
+            x = np.einsum("ij,ij->i", U[ri] * sig, V[ci])
+            acc["rel_err_vs_truth_sampled"] = float(np.linalg.norm(x - t) /
+                                                    np.linalg.norm(t))
     cpu = None
     if not a.no_cpu_baseline:
         orc, cpu = cpu_baseline(prob, prm, a.cpu_seconds, a.warmup + done)
@@ -322,7 +371,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": a.workload, "m": prob.m, "n": prob.n,
                    "nnz": prob.nnz, "precision": a.precision,
-                   "recycle": prm["recycle"], "p_init": prm["p_init"],
+                   "recycle": prm["recycle"], "ritz_tol": prm["ritz_tol"],
+                   "p_init": prm["p_init"],
                    "adaptive_p": prm["adaptive_p"], "tau": prm["tau"],
                    "delta": prm["delta"], "eps": prm["eps"]},
         "roofline": roof,

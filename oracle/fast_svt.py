@@ -26,7 +26,11 @@ Readings of points the listing leaves open:
   that would need more columns than that basis holds runs rSVD-BKI instead.
 * Guarded recycling (ritz_tol > 0) is an addition, not in the paper: a
   recycled result whose Ritz residual max_j ||Y v_j - s_j u_j|| / s_j
-  exceeds ritz_tol is discarded and rSVD-BKI runs instead.
+  exceeds ritz_tol is discarded and rSVD-BKI runs instead.  A rejection in
+  step i also suspends recycling in steps i+1 .. i+q_reuse (every call of
+  those steps is rSVD-BKI), so an operator whose recycled results keep
+  failing the guard does not pay for a discarded call in every step.  With
+  ritz_tol = 0 nothing is rejected and the paper's rule applies unchanged.
 * Block width b = min(k + s, min(m, n)) and the power parameter is clamped so
   that (p + 1) b <= min(m, n) (eigSVD of B^T needs n >= (p + 1) b, Alg. 3).
 * The rank search stops at the cap min(m, n, k_max).
@@ -97,6 +101,7 @@ class FastSVT:
         self.q = 0
         self.p = self.prm.p_init
         self.streak = 0
+        self.rej_i = 0          # last step with a rejected recycled call
         self.err_hist = []
         self.saved = None
         self.kcap = min(self.m, self.n)
@@ -150,9 +155,10 @@ class FastSVT:
         self.p, self.streak = adapt_p(self.p, self.streak, self.err_hist, prm)
         attempt = fresh = recycled = rejected = 0
         while True:
+            suspended = 0 < self.rej_i < self.i <= self.rej_i + prm.q_reuse
             use_fresh = (prm.recycle == 0 or self.i < prm.i_reuse
                          or self.q == prm.q_reuse or self.saved is None
-                         or k > self.saved.shape[1])
+                         or k > self.saved.shape[1] or suspended)
             if not use_fresh:
                 U, S, V = self._recycled(Y, k)
                 self.q += 1
@@ -160,6 +166,7 @@ class FastSVT:
                 if prm.ritz_tol > 0 and self._ritz(Y, U, S, V) > prm.ritz_tol:
                     use_fresh = True
                     rejected += 1
+                    self.rej_i = self.i
             if use_fresh:
                 U, S, V = self._fresh(Y, k, attempt)
                 attempt += 1

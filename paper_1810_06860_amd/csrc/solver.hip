@@ -5,7 +5,8 @@
 //   repeat
 //     fresh rSVD-BKI (Alg. 5) when i < i_reuse, q == q_reuse or there is no
 //     usable basis; otherwise recycle the last call's Q (strategy 1) or U
-//     (strategy 2) (Sec. IV.B), optionally checked by the Ritz residual
+//     (strategy 2) (Sec. IV.B), optionally checked by the Ritz residual (a
+//     rejected recycle in step i also makes steps i+1 .. i+q_reuse fresh)
 //   until the k-th singular value <= tau (k += l otherwise)
 //   r = #{S_j > tau}; fused SDDMM: residual on Phi and Y += delta P_Phi(M - X)
 // The device work of these calls lives in solver_impl.hip.
@@ -126,8 +127,10 @@ double Solver::sddmm(int r) {
 // Alg. 6 allows it (Sec. IV.B), fresh otherwise.
 void Solver::launch_svd(bool force_fresh) {
   const int k = k_cur_;
+  const bool suspended = rej_i_ > 0 && i_ > rej_i_ && i_ <= rej_i_ + prm_.q_reuse;
   const bool fresh = force_fresh || prm_.recycle == 0 || i_ < prm_.i_reuse ||
-                     q_ == prm_.q_reuse || basis_cols_ == 0 || k > basis_cols_;
+                     q_ == prm_.q_reuse || basis_cols_ == 0 || k > basis_cols_ ||
+                     suspended;
   if (fresh) {
     fresh_launch(k, p_, (uint32_t)i_, attempt_++);
     ++cur_.fresh;
@@ -182,6 +185,7 @@ bool Solver::step_poll(bool block) {
         const double ratio = recycled_finish(k_cur_);
         if (prm_.ritz_tol > 0 && ratio > prm_.ritz_tol) {    // guard: redo fresh
           ++cur_.rejected;
+          rej_i_ = i_;
           launch_svd(true);
           return false;
         }

@@ -37,17 +37,29 @@ class Problem:
     V: Optional[np.ndarray] = None
     dense: Optional[np.ndarray] = None  # full ground truth, when small
     meta: dict = field(default_factory=dict)
+    offset: float = 0.0         # truth = offset + scale * U V^T (before any
+    scale: float = 1.0          # rounding or clipping of the observed values)
 
     @property
     def nnz(self):
         return int(self.vals.size)
 
-    def truth_dense(self):
+    def truth_dense(self, max_cells=1 << 25):
+        """The full ground truth, or None when unknown or above max_cells."""
         if self.dense is not None:
             return self.dense
-        if self.U is not None:
-            return self.U @ self.V.T
+        if self.U is not None and self.m * self.n <= max_cells:
+            return self.offset + self.scale * (self.U @ self.V.T)
         return None
+
+    def truth_at(self, rows, cols):
+        """Ground truth at the given cells, or None when unknown."""
+        if self.dense is not None:
+            return self.dense[rows, cols]
+        if self.U is None:
+            return None
+        return self.offset + self.scale * np.einsum(
+            "ij,ij->i", self.U[rows], self.V[cols])
 
 
 def planted(m, n, rank, ratio, seed_data, seed_phi, name="planted"):
@@ -151,6 +163,7 @@ def ratings(m, n, nnz, rank, s=1.1, seed_data=3, name="ratings"):
     raw = np.einsum("ij,ij->i", U[rows_out], V[cols_out]) / np.sqrt(rank)
     vals = np.clip(np.rint(3.5 + raw), 1.0, 5.0)
     return Problem(m, n, rows_out, cols_out, vals, name=name, U=U, V=V,
+                   offset=3.5, scale=1.0 / np.sqrt(rank),
                    meta=dict(rank=rank, s=s, seed_data=seed_data,
                              integer_values=True))
 

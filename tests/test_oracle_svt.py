@@ -147,6 +147,38 @@ def test_guarded_recycling_matches_plain(strategy):
     assert rel < 1e-3
 
 
+@pytest.mark.parametrize("strategy", [1, 2])
+def test_rejected_recycles_leave_no_trace(strategy):
+    # A guard that rejects every recycled result must reproduce the solve
+    # without recycling exactly: a discarded call changes no state, and the
+    # rSVD-BKI calls draw the same test matrices.  After a rejection in step
+    # i, steps i+1 .. i+q_reuse make no recycled call; step i+q_reuse+1 tries
+    # again.
+    p = _small_planted(m=120, n=100, rank=4, ratio=0.35, seed=11)
+    base = dict(tau=500.0, delta=1.2 / 0.35, eps=1e-3, i_max=80)
+    plain = FastSVT(p.m, p.n, p.rows, p.cols, p.vals, base)
+    q_reuse = 3
+    rej = FastSVT(p.m, p.n, p.rows, p.cols, p.vals,
+                  dict(base, recycle=strategy, i_reuse=20, q_reuse=q_reuse,
+                       ritz_tol=1e-300))
+    last_rej = None
+    for _ in range(80):
+        a, b = plain.step(), rej.step()
+        assert (a.res, a.r, a.k, a.p, a.fresh) == (b.res, b.r, b.k, b.p, b.fresh)
+        assert np.array_equal(a.S, b.S)
+        assert b.recycled == b.rejected
+        if last_rej is not None and b.i <= last_rej + q_reuse:
+            assert b.recycled == 0, b.i
+        if last_rej is not None and b.i == last_rej + q_reuse + 1:
+            assert b.recycled > 0, b.i
+        if b.rejected:
+            last_rej = b.i
+        if a.converged:
+            break
+    assert rej.rejected_total >= 3
+    assert np.array_equal(plain.U, rej.U) and np.array_equal(plain.V, rej.V)
+
+
 def test_rank_cap():
     p = _small_planted(m=80, n=60, rank=6, ratio=0.5, seed=5)
     prm = dict(tau=300.0, delta=2.4, eps=1e-5, i_max=40, k_max=3)
