@@ -4,12 +4,17 @@
 //   N dimension is split over workgroups; each writes its partial tile and a
 //   second kernel sums the partials in a fixed order (deterministic).  Used
 //   for the Gram B B^T of eigSVD (Alg. 3 step 1) and for the Gram / cross-Gram
-//   products of the block orthonormalisation of the Krylov blocks.
+//   products of the block orthonormalisation of the Krylov blocks.  The
+//   products run on the matrix cores (16x16x4 FP64 or FP32 MFMA); the fused
+//   form for short blocks (completion and Cholesky in the last workgroup)
+//   uses vector FMAs on 32 x 32 tiles.
 // * panel GEMM:  C = beta C0 + alpha X W diag(colscale), X tall (N x p),
 //   W small (p x q).  Used for H - Q (Q^T H), H R^-1, U = Q W and
 //   V = B^T W S^-1 (Alg. 3 step 4, Alg. 5 step 10).
 // * Cholesky + triangular inverse of a small SPD matrix in one workgroup,
 //   with a diagonal shift when a pivot breaks down (shifted Cholesky QR).
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace mcsvt {
@@ -176,6 +181,162 @@ __global__ __launch_bounds__(256) void gram_kernel(
   if (threadIdx.x == 0) *tail.counter = 0;
 }
 
+// Matrix-core Gram: the same partial products as gram_kernel, computed with
+// the 16x16x4 FP64 / FP32 MFMA instructions.  A workgroup owns a 128 x 128
+// output block and a range of rows, so each row of A and B is read by as few
+// workgroups as possible; each of its four wavefronts owns a 64 x 64 quarter
+// (4 x 4 instruction tiles accumulated in registers).  Instruction tiles that
+// lie wholly outside p x q are skipped.  For a symmetric product only blocks
+// on and above the diagonal run, and on a diagonal block the quarter below
+// the diagonal is skipped: the reduction reads it mirrored (granularity 64).
+// Rows pass through LDS 16 at a time, loaded one stage ahead into registers.
+constexpr int MB = 128;  // output block of gram_mfma_kernel
+constexpr int MQ = 64;   // quarter of a wavefront; mirror granularity
+constexpr int MK = 16;   // rows per LDS stage
+
+template <class T> struct Mfma16;
+template <> struct Mfma16<double> {
+  typedef double V __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ V op(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of the 16 x 16 result held in element v of a lane (column lane % 16)
+  static __device__ __forceinline__ int row(int lane, int v) { return lane / 16 + 4 * v; }
+};
+template <> struct Mfma16<float> {
+  typedef float V __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ V op(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane / 16) + v; }
+};
+
+// The row loop of gram_mfma_kernel for one block kind: SAME (diagonal block
+// of a symmetric product: B is A), NI x NJ instruction tiles of the
+// wavefront's quarter (0: loads only).  Everything that varies inside the
+// loop is a template parameter, so the loop body has no branches; only the
+// last, partial stage uses row-guarded loads.
+template <class T, bool SAME, int NI, int NJ>
+__device__ __forceinline__ void gram_mfma_rows(
+    int64_t n0, int64_t n1, int p, int q, const T* __restrict__ A, int64_t lda,
+    const T* __restrict__ B, int64_t ldb, T* __restrict__ out, int a0, int b0,
+    int wr, int wc, T (*As)[MB + 1], T (*Bs)[MB + 1]) {
+  using M = Mfma16<T>;
+  using V = typename M::V;
+  constexpr int LPT = MK * MB / 256;          // elements per thread and stage
+  const int lane = threadIdx.x & 63;
+  const int lc = threadIdx.x & (MB - 1), lr = threadIdx.x / MB;
+  const bool acol = a0 + lc < p, bcol = b0 + lc < q;
+  // thread's column of A (B); rows lr, lr + 2, ..., lr + 14 of a stage
+  const T* Ac = A + (acol ? a0 + lc : 0) + lr * lda;
+  const T* Bc = B + (bcol ? b0 + lc : 0) + lr * ldb;
+  T ra[LPT], rb[LPT];
+  auto fetch = [&](int64_t nb) {
+    if (nb + MK <= n1) {
+#pragma unroll
+      for (int i = 0; i < LPT; ++i) {
+        ra[i] = Ac[(nb + 2 * i) * lda];
+        if (!SAME) rb[i] = Bc[(nb + 2 * i) * ldb];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < LPT; ++i) {
+        const bool rin = nb + lr + 2 * i < n1;
+        ra[i] = rin ? Ac[(nb + 2 * i) * lda] : T(0);
+        if (!SAME) rb[i] = rin ? Bc[(nb + 2 * i) * ldb] : T(0);
+      }
+    }
+  };
+  V acc[NI > 0 ? NI : 1][NJ > 0 ? NJ : 1];
+#pragma unroll
+  for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
+#pragma unroll
+    for (int j = 0; j < (NJ > 0 ? NJ : 1); ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
+  fetch(n0);
+  for (int64_t nb = n0; nb < n1; nb += MK) {
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+      As[lr + 2 * i][lc] = acol ? ra[i] : T(0);
+      if (!SAME) Bs[lr + 2 * i][lc] = bcol ? rb[i] : T(0);
+    }
+    __syncthreads();
+    if (nb + MK < n1) fetch(nb + MK);         // in flight during the products
+    if (NI > 0 && NJ > 0) {
+      T(*Bt)[MB + 1] = SAME ? As : Bs;
+#pragma unroll
+      for (int kk = 0; kk < MK; kk += 4) {
+        const int kr = kk + lane / 16, cc = lane % 16;
+        T x[NI > 0 ? NI : 1], y[NJ > 0 ? NJ : 1];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) x[i] = As[kr][wr * MQ + i * 16 + cc];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) y[j] = Bt[kr][wc * MQ + j * 16 + cc];
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) acc[i][j] = M::op(x[i], y[j], acc[i][j]);
+      }
+    }
+    __syncthreads();
+  }
+  if (NI == 0 || NJ == 0) return;
+  const int ra0 = a0 + wr * MQ, cb0 = b0 + wc * MQ;
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = ra0 + i * 16 + M::row(lane, v);
+        const int c = cb0 + j * 16 + lane % 16;
+        if (r < p && c < q) out[(int64_t)r * q + c] = acc[i][j][v];
+      }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void gram_mfma_kernel(
+    int64_t N, int p, int q, const T* __restrict__ A, int64_t lda,
+    const T* __restrict__ B, int64_t ldb, T* __restrict__ part,
+    int64_t rows_per_split, int sym, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  const int bi = blockIdx.x, bj = blockIdx.y, sp = blockIdx.z;
+  if (sym && bj < bi) return;
+  __shared__ T As[MK][MB + 1];
+  __shared__ T Bs[MK][MB + 1];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wr = w >> 1, wc = w & 1;
+  const int a0 = bi * MB, b0 = bj * MB;
+  const int64_t n0 = (int64_t)sp * rows_per_split;
+  const int64_t n1 = min(N, n0 + rows_per_split);
+  if (n0 >= n1) return;
+  const bool same = sym && bi == bj;
+  // instruction tiles of this wavefront's quarter that touch p x q, rounded
+  // up to 2 or 4 (0: the quarter is outside, or mirrored)
+  auto tiles = [](int rem) { return rem <= 0 ? 0 : (rem <= 32 ? 2 : 4); };
+  int ni = tiles(p - a0 - wr * MQ), nj = tiles(q - b0 - wc * MQ);
+  if (same && wr > wc) ni = 0;
+  if (ni == 0 || nj == 0) ni = nj = 0;
+  T* out = part + (int64_t)sp * p * q;
+#define MC_GRAM_ROWS(S, I, J)                                                      \
+  gram_mfma_rows<T, S, I, J>(n0, n1, p, q, A, lda, B, ldb, out, a0, b0, wr, wc, As, \
+                             Bs)
+#define MC_GRAM_KIND(S)                            \
+  if (ni == 0) MC_GRAM_ROWS(S, 0, 0);              \
+  else if (ni == 4 && nj == 4) MC_GRAM_ROWS(S, 4, 4); \
+  else if (ni == 4) MC_GRAM_ROWS(S, 4, 2);         \
+  else if (nj == 4) MC_GRAM_ROWS(S, 2, 4);         \
+  else MC_GRAM_ROWS(S, 2, 2);
+  if (same) {
+    MC_GRAM_KIND(true)
+  } else {
+    MC_GRAM_KIND(false)
+  }
+#undef MC_GRAM_KIND
+#undef MC_GRAM_ROWS
+}
+
 // Sum of the split partials.  `lanes` consecutive threads (a power of two
 // dividing 64, so they sit in one wavefront) share an output: lane j adds the
 // splits j, j + lanes, ... in order, then the lanes are combined by a fixed
@@ -183,7 +344,7 @@ __global__ __launch_bounds__(256) void gram_kernel(
 template <class AT>
 __global__ __launch_bounds__(256) void gram_reduce_kernel(
     int p, int q, int nsplit, int lanes, const AT* __restrict__ part,
-    double* __restrict__ C, int64_t ldc, int sym, const int* __restrict__ gate) {
+    double* __restrict__ C, int64_t ldc, int sym, int tile, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
   const int per_block = 256 / lanes;
   const int lane = threadIdx.x % lanes;
@@ -196,7 +357,7 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(
     j = (int)(t % q);
     si = i;
     sj = j;
-    if (sym && (i / GT) > (j / GT)) { si = j; sj = i; }   // mirrored tile
+    if (sym && (i / tile) > (j / tile)) { si = j; sj = i; }   // mirrored tile
   }
   double acc = 0.0;
   if (live)
@@ -334,7 +495,10 @@ __global__ void ritz_reduce_kernel(int nblk, int k, const double* __restrict__ p
 
 }  // namespace
 
-int64_t gram_splits(int64_t N, int p, int q, int sym) {
+namespace {
+
+// Row splits of the fused Gram (gram_kernel, 32 x 32 tiles).
+int64_t fused_splits(int64_t N, int p, int q, int sym) {
   const int64_t tiles = ceil_div(p, GT) * ceil_div(q, GT);
   const int64_t eff = sym ? (tiles + ceil_div(p, GT)) / 2 : tiles;
   // aim at ~2048 workgroups, chunks of at least 64 rows
@@ -343,26 +507,45 @@ int64_t gram_splits(int64_t N, int p, int q, int sym) {
   return splits;
 }
 
+// Row splits of the matrix-core Gram: about 1024 workgroups, at least four
+// LDS stages each, and partials of at most half the elements read.
+int64_t gram_mfma_splits(int64_t N, int p, int q, int sym) {
+  const int64_t blocks = ceil_div(p, MB) * ceil_div(q, MB);
+  const int64_t eff = sym ? (blocks + ceil_div(p, MB)) / 2 : blocks;
+  int64_t splits = std::max<int64_t>(1, 1024 / std::max<int64_t>(eff, 1));
+  splits = std::min<int64_t>(splits, std::max<int64_t>(1, ceil_div(N, 4 * MK)));
+  splits = std::min<int64_t>(
+      splits, std::max<int64_t>(1, N * (int64_t)(p + q) / (2 * (int64_t)p * q)));
+  return splits;
+}
+
+}  // namespace
+
+int64_t gram_splits(int64_t N, int p, int q, int sym) {
+  return std::max(fused_splits(N, p, q, sym), gram_mfma_splits(N, p, q, sym));
+}
+
 template <class IT, class AT>
 void launch_gram(int64_t N, int p, int q, const IT* A, int64_t lda, const IT* B,
                  int64_t ldb, double* C, int64_t ldc, int sym, AT* part,
                  int64_t part_cap, hipStream_t st, const int* gate) {
   if (p <= 0 || q <= 0) return;
-  int64_t splits = gram_splits(N, p, q, sym);
+  int64_t splits = gram_mfma_splits(N, p, q, sym);
   while (splits > 1 && splits * p * q > part_cap) --splits;
   MC_REQUIRE(splits * p * q <= part_cap, kEINVAL, "gram partial buffer too small");
-  const int64_t rps = round_up(ceil_div(std::max<int64_t>(N, 1), splits), GT);
+  const int64_t rps = round_up(ceil_div(std::max<int64_t>(N, 1), splits), MK);
   splits = std::max<int64_t>(1, ceil_div(std::max<int64_t>(N, 1), rps));
-  dim3 grid((unsigned)ceil_div(p, GT), (unsigned)ceil_div(q, GT), (unsigned)splits);
-  hipLaunchKernelGGL((gram_kernel<IT, AT>), grid, dim3(256), 0, st, N, p, q, A,
-                     lda, B, ldb, part, rps, sym, gate, GramTail());
+  dim3 grid((unsigned)ceil_div(p, MB), (unsigned)ceil_div(q, MB), (unsigned)splits);
+  static_assert(std::is_same<IT, AT>::value, "the matrix-core Gram accumulates in its input type");
+  hipLaunchKernelGGL((gram_mfma_kernel<AT>), grid, dim3(256), 0, st, N, p, q, A,
+                     lda, B, ldb, part, rps, sym, gate);
   MC_CHECK_LAUNCH();
   const int64_t tot = (int64_t)p * q;
   int lanes = 1;   // threads per output: about 16 splits each, at most 64
   while (lanes < 64 && lanes * 16 < splits) lanes <<= 1;
   const int64_t per_block = 256 / lanes;
   hipLaunchKernelGGL((gram_reduce_kernel<AT>), dim3((unsigned)ceil_div(tot, per_block)),
-                     dim3(256), 0, st, p, q, (int)splits, lanes, part, C, ldc, sym,
+                     dim3(256), 0, st, p, q, (int)splits, lanes, part, C, ldc, sym, MQ,
                      gate);
   MC_CHECK_LAUNCH();
 }
@@ -387,7 +570,7 @@ void launch_gram_fused(int64_t N, int p, int q, const IT* A, int64_t lda, const 
   const bool chol = Rinv != nullptr;
   MC_REQUIRE(!chol || (p == q && p <= kCholLdsMax), kEINVAL, "fused Cholesky size");
   // at most 64 row splits: one workgroup sums the partials
-  int64_t splits = std::min<int64_t>(64, gram_splits(N, p, q, sym));
+  int64_t splits = std::min<int64_t>(64, fused_splits(N, p, q, sym));
   while (splits > 1 && splits * p * q > part_cap) --splits;
   MC_REQUIRE(splits * p * q <= part_cap, kEINVAL, "gram partial buffer too small");
   const int64_t rps = round_up(ceil_div(std::max<int64_t>(N, 1), splits), GT);

@@ -81,6 +81,9 @@ void launch_scale(int64_t n, const double* a, double alpha, double* out,
                   hipStream_t st);
 
 // C (p x q, FP64) = A^T B with A (N x p), B (N x q); sym: A == B, p == q.
+// gram_splits: the most row splits a launch_gram or launch_gram_fused call of
+// that shape uses (its partial buffer holds gram_splits * p * q elements; a
+// smaller buffer means fewer splits).
 int64_t gram_splits(int64_t N, int p, int q, int sym);
 // gate: optional device flag; when it reads 0 the kernels do nothing.
 template <class IT, class AT>

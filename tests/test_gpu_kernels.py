@@ -108,7 +108,9 @@ def test_spmm_fp32_error_bound(K):
 
 @pytest.mark.parametrize("N,p,q,sym", [(1000, 21, 21, 1), (5000, 84, 84, 1),
                                        (777, 63, 21, 0), (33, 5, 7, 0),
-                                       (20000, 330, 330, 1)])
+                                       (20000, 330, 330, 1), (1, 3, 3, 1),
+                                       (16, 64, 64, 1), (4099, 129, 17, 0),
+                                       (70001, 81, 81, 1), (3001, 200, 65, 0)])
 def test_gram_fp64(K, N, p, q, sym):
     rng = np.random.default_rng(N + p)
     A = rng.standard_normal((N, p))
@@ -117,6 +119,23 @@ def test_gram_fp64(K, N, p, q, sym):
     want = A.T @ (A if sym else B)
     scale = np.abs(A).T @ np.abs(A if sym else B)
     assert np.max(np.abs(got - want) / scale) < 1e-14
+    if sym:
+        assert np.array_equal(got, got.T)
+
+
+@pytest.mark.parametrize("N,p,q,sym", [(1000, 21, 21, 1), (4099, 129, 17, 0),
+                                       (70001, 81, 81, 1), (10700, 400, 400, 1)])
+def test_gram_fp32(K, N, p, q, sym):
+    # FP32 products accumulated in FP32 within a row split, splits summed in
+    # FP64: error within N u32 of sum |a_i||b_j| (a loose form of the
+    # recursive-summation bound)
+    rng = np.random.default_rng(N + p + 1)
+    A = rng.standard_normal((N, p)).astype(np.float32).astype(np.float64)
+    B = None if sym else rng.standard_normal((N, q)).astype(np.float32).astype(np.float64)
+    got = K.gram(A, B, precision="fp32")
+    want = A.T @ (A if sym else B)
+    scale = np.abs(A).T @ np.abs(A if sym else B)
+    assert np.max(np.abs(got - want) / scale) < N * 2.0 ** -24
     if sym:
         assert np.array_equal(got, got.T)
 
