@@ -29,6 +29,7 @@ __device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
                                int* __restrict__ flag) {
   __shared__ double trace;
   const int tid = threadIdx.x;
+  const int tx = tid & 31, ty = tid >> 5, ny = (int)(blockDim.x >> 5);
   if (tid == 0) {
     double t = 0.0;
     for (int i = 0; i < b; ++i) t += G[(int64_t)i * ldg + i];
@@ -38,12 +39,12 @@ __device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
   const double u = 1.1102230246251565e-16;
   double shift = 0.0;
   for (int attempt = 0; attempt < 6; ++attempt) {
-    for (int t = tid; t < b * b; t += blockDim.x) {
-      const int i = t / b, j = t % b;
-      double v = (i <= j) ? G[(int64_t)i * ldg + j] : 0.0;
-      if (i == j) v += shift;
-      R[t] = v;
-    }
+    for (int i = ty; i < b; i += ny)
+      for (int c = tx; c < b; c += 32) {
+        double v = (i <= c) ? G[(int64_t)i * ldg + c] : 0.0;
+        if (i == c) v += shift;
+        R[i * b + c] = v;
+      }
     __syncthreads();
     bool failed = false;
     for (int j = 0; j < b; ++j) {
@@ -56,10 +57,11 @@ __device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
         break;
       }
       const double rd = 1.0 / d;
-      const int rem = b - j - 1;
-      for (int t = tid; t < rem * rem; t += blockDim.x) {
-        const int i = j + 1 + t / rem, c = j + 1 + t % rem;
-        if (c >= i) R[i * b + c] -= R[j * b + i] * R[j * b + c] * rd;
+      // rows i > j over thread rows, columns c >= i over the 32 lanes of a
+      // thread row (no index division in the loop)
+      for (int i = j + 1 + ty; i < b; i += ny) {
+        const double f = R[j * b + i];
+        for (int c = i + tx; c < b; c += 32) R[i * b + c] -= f * R[j * b + c] * rd;
       }
       __syncthreads();
     }
@@ -73,27 +75,38 @@ __device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
     if (tid == 0 && flag) *flag = 1;
     __syncthreads();
   }
-  // scale: R_jj = sqrt(d_j), R_jc = (R_jj R_jc) / R_jj
-  for (int t = tid; t < b * b; t += blockDim.x) {
-    const int i = t / b, c = t % b;
-    if (c > i) R[t] = R[t] / sqrt(R[i * b + i]);
+  // scale: R_jj = sqrt(d_j), R_jc = (R_jj R_jc) / R_jj; the square roots
+  // go through X (free until the inverse)
+  for (int i = tid; i < b; i += blockDim.x) X[i] = sqrt(R[i * b + i]);
+  __syncthreads();
+  for (int i = ty; i < b; i += ny) {
+    const double si = X[i];
+    for (int c = i + 1 + tx; c < b; c += 32) R[i * b + c] = R[i * b + c] / si;
   }
   __syncthreads();
-  for (int i = tid; i < b; i += blockDim.x) R[i * b + i] = sqrt(R[i * b + i]);
+  for (int i = tid; i < b; i += blockDim.x) R[i * b + i] = X[i];
   __syncthreads();
-  // column c of R^{-1} by back substitution (thread per column), in LDS
+  // column c of R^{-1} by back substitution (thread per column), in LDS; the
+  // dot products run on four partial sums
   for (int c = tid; c < b; c += blockDim.x) {
     for (int i = b - 1; i > c; --i) X[i * b + c] = 0.0;
     X[c * b + c] = 1.0 / R[c * b + c];
     for (int i = c - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int t = i + 1; t <= c; ++t) acc += R[i * b + t] * X[t * b + c];
-      X[i * b + c] = -acc / R[i * b + i];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int t = i + 1;
+      for (; t + 3 <= c; t += 4) {
+        a0 += R[i * b + t] * X[t * b + c];
+        a1 += R[i * b + t + 1] * X[(t + 1) * b + c];
+        a2 += R[i * b + t + 2] * X[(t + 2) * b + c];
+        a3 += R[i * b + t + 3] * X[(t + 3) * b + c];
+      }
+      for (; t <= c; ++t) a0 += R[i * b + t] * X[t * b + c];
+      X[i * b + c] = -((a0 + a1) + (a2 + a3)) / R[i * b + i];
     }
   }
   __syncthreads();
-  for (int t = tid; t < b * b; t += blockDim.x)
-    Rinv[(int64_t)(t / b) * ldr + t % b] = X[t];
+  for (int i = ty; i < b; i += ny)
+    for (int c = tx; c < b; c += 32) Rinv[(int64_t)i * ldr + c] = X[i * b + c];
 }
 
 // Fused completion (mode 1: sum the partials into C; mode 2: also Cholesky +
