@@ -255,8 +255,7 @@ size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& p
   // copy of G, reflectors, vectors and small factors (k <= 140)
   const int64_t Lb = std::min<int64_t>(L, 1024), kb = std::min<int64_t>(Lb, 140);
   bytes += (size_t)8 * (L * L);
-  bytes += (size_t)8 * (2 * Lb * Lb + 6 * Lb + 2 * Lb * kb + 3 * kb * kb +
-                        ((Lb + 63) / 64) * kb * kb + 64);
+  bytes += (size_t)8 * TriBigWork::doubles((int)Lb, (int)kb);
   bytes += (size_t)8 * (mx * L / 4 + ceil_div(nnz, 256) + nnz);
   return bytes;
 }

@@ -606,70 +606,122 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
 
 // ---- matrices too large for one workgroup's LDS -----------------------------
 // The first j0 = L - Ls Householder steps run on a copy of G in global memory,
-// each as two launches over many workgroups; a one-workgroup kernel then
-// finishes the trailing Ls x Ls block in LDS and finds the eigenvalues.
-// Eigenvectors: one workgroup per vector for the inverse iteration, Cholesky
-// QR and a Newton-Schulz step with the Gram and panel kernels, and a
-// back-transformation kernel with each vector in registers.
+// one launch per step; a one-workgroup kernel then finishes the trailing
+// Ls x Ls block in LDS and finds the eigenvalues.  Eigenvectors: one
+// workgroup per vector for the inverse iteration, Cholesky QR and a
+// Newton-Schulz step with the Gram and panel kernels, and a back-
+// transformation kernel with each vector in registers.
 
-constexpr int kBigRows = 64;       // rows of the trailing block per workgroup
+constexpr int kBigRows = 4;        // trailing rows per workgroup (one per wavefront)
 
-// p = beta A22 v for 64 rows per workgroup (4 wavefronts split the sum), and
-// the workgroup's share of p^T v.  Every workgroup derives the reflector of
-// step j from row j itself; workgroup 0 records it.
-__global__ __launch_bounds__(256) void big_matvec_kernel(
-    int L, int j, const double* __restrict__ Ag, double* __restrict__ hh,
+// Launch j (0 <= j < j0) of the tridiagonalisation.  It first applies the
+// rank-2 update of step j-1, A22 -= v w^T + w v^T with w = p - (beta/2)(p^T v) v,
+// which the previous launch left pending (it needs p complete), to this
+// workgroup's rows, restricted to rows and columns > j.  Every workgroup
+// rebuilds the updated row j from the stored row and the vectors of step
+// j-1, takes the reflector of step j from it, and forms p = beta A22 v for
+// its own rows (whole rows, so p needs no reduction across workgroups) and
+// its share of p^T v.  Workgroup 0 records the reflector.  Launch j = j0
+// applies the last pending update to rows and columns >= j0 and stops.
+// p and the p^T v partials alternate between two buffers by step parity.
+__global__ __launch_bounds__(256) void big_step_kernel(
+    int L, int j, int j0, double* __restrict__ Ag, double* __restrict__ hh,
     double* __restrict__ dg, double* __restrict__ eg, double* __restrict__ hbg,
-    double* __restrict__ hrg, double* __restrict__ Pg, double* __restrict__ part) {
+    double* __restrict__ hrg, double* __restrict__ Pbuf, double* __restrict__ pbuf) {
+  extern __shared__ double sv[];
+  double* vp = sv;            // v of step j-1 on [j, L)
+  double* wp = vp + L;        // w of step j-1 on [j, L)
+  double* vj = wp + L;        // v of step j on [j + 1, L)
   __shared__ double red[4];
-  __shared__ double sacc[4][64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int o = j + 1, n = L - o;
-  const double* __restrict__ hrow = Ag + (int64_t)j * L + o;
-  double sq = 0.0;
-  for (int c = 1 + tid; c < n; c += 256) sq += hrow[c] * hrow[c];
-  sq = wsum(sq);
-  if (lane == 0) red[wave] = sq;
-  __syncthreads();
-  const double sig2 = (red[0] + red[1]) + (red[2] + red[3]);
-  const double alpha = hrow[0];
-  double beta = 0.0, rv = 0.0, mu = alpha;
-  if (sig2 > 0.0) {
-    mu = sqrt(alpha * alpha + sig2);
-    const double v0 = alpha <= 0.0 ? alpha - mu : -sig2 / (alpha + mu);
-    beta = 2.0 * v0 * v0 / (sig2 + v0 * v0);
-    rv = 1.0 / v0;
-  }
-  if (blockIdx.x == 0) {
-    if (tid == 0) {
-      dg[j] = Ag[(int64_t)j * L + j];
-      eg[j] = mu;
-      hbg[j] = beta;
-      hrg[j] = rv;
+  const bool last = j == j0;
+  const int o = last ? j : j + 1;             // first row / column this launch touches
+  const int npart_stride = (L + kBigRows - 1) / kBigRows;
+  const bool upd = j >= 1;
+  if (upd) {
+    // step j-1: its trailing block starts at j
+    const int jp = j - 1;
+    const double bp = hbg[jp], rvp = hrg[jp];
+    const double* __restrict__ Pp = Pbuf + (size_t)(jp & 1) * L;
+    const double* __restrict__ pp = pbuf + (size_t)(jp & 1) * npart_stride;
+    const int nparts = (L - j + kBigRows - 1) / kBigRows;
+    double pvt = 0.0;
+    for (int w = 0; w < nparts; ++w) pvt += pp[w];
+    const double K = 0.5 * bp * pvt;
+    for (int c = j + tid; c < L; c += 256) {
+      const double v = c == j ? 1.0 : hh[(int64_t)jp * L + c] * rvp;
+      vp[c] = v;
+      wp[c] = Pp[c - j] - K * v;
     }
-    for (int t = tid; t < n; t += 256) hh[(int64_t)j * L + o + t] = hrow[t];
+    __syncthreads();
   }
-  const int r = blockIdx.x * kBigRows + lane;       // trailing row
-  double acc = 0.0;
-  if (r < n) {
-    const int i = o + r;
-#pragma unroll 4
-    for (int c = wave; c < n; c += 4) {
-      const double h = hrow[c];
-      acc += Ag[(int64_t)(o + c) * L + i] * (c == 0 ? 1.0 : h * rv);
+  if (!last) {
+    // row j after step j-1 (columns > j), the reflector of step j from it
+    const int n = L - o;
+    double sq = 0.0;
+    for (int c = o + tid; c < L; c += 256) {
+      double x = Ag[(int64_t)j * L + c];
+      if (upd) x -= vp[j] * wp[c] + wp[j] * vp[c];
+      vj[c] = x;
+      if (c > o) sq += x * x;
     }
-  }
-  sacc[wave][lane] = acc;
-  __syncthreads();
-  if (wave == 0) {
-    double pv = 0.0;
+    sq = wsum(sq);
+    if (lane == 0) red[wave] = sq;
+    __syncthreads();
+    const double sig2 = (red[0] + red[1]) + (red[2] + red[3]);
+    const double alpha = vj[o];
+    double beta = 0.0, rv = 0.0, mu = alpha;
+    if (sig2 > 0.0) {
+      mu = sqrt(alpha * alpha + sig2);
+      const double v0 = alpha <= 0.0 ? alpha - mu : -sig2 / (alpha + mu);
+      beta = 2.0 * v0 * v0 / (sig2 + v0 * v0);
+      rv = 1.0 / v0;
+    }
+    if (blockIdx.x == 0) {
+      if (tid == 0) {
+        double djj = Ag[(int64_t)j * L + j];
+        if (upd) djj -= vp[j] * wp[j] + wp[j] * vp[j];
+        dg[j] = djj;
+        eg[j] = mu;
+        hbg[j] = beta;
+        hrg[j] = rv;
+      }
+      for (int t = tid; t < n; t += 256) hh[(int64_t)j * L + o + t] = vj[o + t];
+    }
+    __syncthreads();                            // vj[o] read above by every thread
+    for (int c = o + tid; c < L; c += 256) vj[c] = c == o ? 1.0 : vj[c] * rv;
+    __syncthreads();
+    // this workgroup's rows: update by step j-1, then p = beta A22 v
+    const int r = blockIdx.x * kBigRows + wave;  // trailing row
+    double pr = 0.0;
     if (r < n) {
-      const double p = beta * ((sacc[0][lane] + sacc[1][lane]) + (sacc[2][lane] + sacc[3][lane]));
-      Pg[r] = p;
-      pv = p * (r == 0 ? 1.0 : hrow[r] * rv);
+      const int a = o + r;
+      double* __restrict__ row = Ag + (int64_t)a * L;
+      double acc = 0.0;
+      for (int c = o + lane; c < L; c += 64) {
+        double x = row[c];
+        if (upd) {
+          x -= vp[a] * wp[c] + wp[a] * vp[c];
+          row[c] = x;
+        }
+        acc += x * vj[c];
+      }
+      acc = wsum(acc);
+      pr = beta * acc;
+      if (lane == 0) Pbuf[(size_t)(j & 1) * L + r] = pr;
     }
-    pv = wsum(pv);
-    if (lane == 0) part[blockIdx.x] = pv;
+    if (lane == 0) red[wave] = r < n ? pr * vj[o + r] : 0.0;
+    __syncthreads();
+    if (tid == 0)
+      pbuf[(size_t)(j & 1) * npart_stride + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  } else if (upd) {
+    // the pending update of step j0 - 1 on rows and columns >= j0
+    const int r = blockIdx.x * kBigRows + wave;
+    if (o + r < L) {
+      const int a = o + r;
+      double* __restrict__ row = Ag + (int64_t)a * L;
+      for (int c = o + lane; c < L; c += 64) row[c] -= vp[a] * wp[c] + wp[a] * vp[c];
+    }
   }
 }
 
@@ -681,34 +733,6 @@ __global__ __launch_bounds__(256) void copy_square_kernel(int L, const double* _
   if (t >= (int64_t)L * L) return;
   const int64_t r = t / L, c = t % L;
   Ag[t] = G[r * ldg + c];
-}
-
-// A22 -= v w^T + w v^T, w = p - (beta/2)(p^T v) v, on 64 x 64 tiles
-__global__ __launch_bounds__(256) void big_update_kernel(
-    int L, int j, double* __restrict__ Ag, const double* __restrict__ Pg,
-    const double* __restrict__ part, int nparts, const double* __restrict__ hbg,
-    const double* __restrict__ hrg) {
-  const double beta = hbg[j];
-  if (beta == 0.0) return;
-  const double rv = hrg[j];
-  double pvt = 0.0;
-  for (int w = 0; w < nparts; ++w) pvt += part[w];
-  const double K = 0.5 * beta * pvt;
-  const int o = j + 1, n = L - o;
-  const double* __restrict__ hrow = Ag + (int64_t)j * L + o;
-  const int b = blockIdx.x * 64 + (threadIdx.x & 63);
-  if (b >= n) return;
-  const double vb = b == 0 ? 1.0 : hrow[b] * rv;
-  const double wb = Pg[b] - K * vb;
-  const int a0 = blockIdx.y * 64 + (threadIdx.x >> 6);
-  const int a1 = min(n, (int)(blockIdx.y + 1) * 64);
-#pragma unroll 4
-  for (int a = a0; a < a1; a += 4) {
-    const double va = a == 0 ? 1.0 : hrow[a] * rv;
-    const double wa = Pg[a] - K * va;
-    double* x = Ag + (int64_t)(o + a) * L + o + b;
-    *x -= va * wb + wa * vb;
-  }
 }
 
 // The trailing block (rows and columns j0 ..) in LDS: the remaining steps and
@@ -926,7 +950,7 @@ static int tail_block(int L, size_t lds_bytes) {
 size_t TriBigWork::doubles(int L, int k) {
   const size_t nparts = (size_t)(L + kBigRows - 1) / kBigRows;
   const size_t splits = (size_t)gram_splits(L, k, k, 1);
-  return 2 * (size_t)L * L + 5 * (size_t)L + nparts + k + 8 + 2 * (size_t)L * k +
+  return 2 * (size_t)L * L + 6 * (size_t)L + 2 * nparts + k + 8 + 2 * (size_t)L * k +
          3 * (size_t)k * k + splits * k * k;
 }
 
@@ -943,9 +967,9 @@ void launch_tri_big(int L, const double* G, int64_t ldg, int k, double* S, doubl
   double* eg = dg + L;
   double* hbg = eg + L;
   double* hrg = hbg + L;
-  double* Pg = hrg + L;
-  double* part = Pg + L;
-  double* lam = part + nparts;
+  double* Pg = hrg + L;                      // p of two consecutive steps
+  double* part = Pg + 2 * (size_t)L;         // their p^T v partials
+  double* lam = part + 2 * (size_t)nparts;
   double* tn = lam + k;
   double* Zg = tn + 8;
   double* Z2 = Zg + (size_t)L * k;
@@ -958,14 +982,13 @@ void launch_tri_big(int L, const double* G, int64_t ldg, int k, double* S, doubl
   MC_CHECK_LAUNCH();
   const int Ls = tail_block(L, lds_bytes);
   const int j0 = L - Ls;
-  for (int j = 0; j < j0; ++j) {
-    const int n = L - j - 1;
-    const int nb = (n + kBigRows - 1) / kBigRows;
-    hipLaunchKernelGGL(big_matvec_kernel, dim3(nb), dim3(256), 0, st, L, j, Ag, hh, dg,
-                       eg, hbg, hrg, Pg, part);
-    MC_CHECK_LAUNCH();
-    hipLaunchKernelGGL(big_update_kernel, dim3(nb, nb), dim3(256), 0, st, L, j, Ag, Pg,
-                       part, nb, hbg, hrg);
+  const size_t step_lds = 3 * sizeof(double) * (size_t)L;
+  for (int j = 0; j <= j0; ++j) {
+    if (j == j0 && j0 == 0) break;             // nothing pending
+    const int o = j == j0 ? j : j + 1;
+    const int nb = (L - o + kBigRows - 1) / kBigRows;
+    hipLaunchKernelGGL(big_step_kernel, dim3((unsigned)nb), dim3(256), step_lds, st, L, j,
+                       j0, Ag, hh, dg, eg, hbg, hrg, Pg, part);
     MC_CHECK_LAUNCH();
   }
   const size_t tail_bytes = sizeof(double) * ((size_t)Ls * Ls + 7 * (size_t)L + 6 * kTWaves) +

@@ -170,9 +170,12 @@ def test_syev_matches_eigh(K, L, k):
     assert sweeps < 30
 
 
-@pytest.mark.parametrize("L,k", [(200, 50), (480, 100), (600, 140), (900, 90)])
+@pytest.mark.parametrize("L,k", [(142, 20), (143, 7), (200, 50), (480, 100),
+                                 (600, 140), (900, 90), (1024, 60)])
 def test_syev_large_multi_launch_path(K, L, k):
-    # beyond one workgroup's LDS: reduction over many workgroups, then LDS
+    # beyond one workgroup's LDS: one launch per Householder step over many
+    # workgroups (a single step and its pending update at L = 142, 143), then
+    # the trailing block in LDS
     rng = np.random.default_rng(L + 7)
     A = rng.standard_normal((3 * L, L)) * np.logspace(0, -4, L)
     A[:, 0] *= 50.0
