@@ -50,6 +50,17 @@ mc_status mc_k_gram(int64_t N, int32_t p, int32_t q, const double* A,
                     const double* B, int32_t sym, int32_t precision,
                     void* stream, double* C);
 
+/* Panel product C (N x q) = beta C0 + alpha X W diag(colscale) with X (N x p)
+ * and W (p x q), all row-major host arrays; colscale (q) and C0 may be NULL
+ * (then they are not applied / beta must be 0).  This is the product behind
+ * H R^-1, H - Q (Q^T H), U = Q W and V = B^T W S^-1 (Alg. 3 step 4, Alg. 5
+ * step 10).  precision MC_FP32 rounds X to FP32 first (the solver's FP32
+ * panels); the arithmetic is FP64 either way. */
+mc_status mc_k_panel(int64_t N, int32_t p, int32_t q, const double* X,
+                     const double* W, double alpha, const double* colscale,
+                     double beta, const double* C0, int32_t precision,
+                     void* stream, double* C);
+
 /* Orthonormal basis of range(H) for H (N x b) by two passes of Cholesky QR
  * (with a diagonal shift on breakdown): Q (N x b). */
 mc_status mc_k_cholqr2(int64_t N, int32_t b, const double* H, void* stream,

@@ -380,63 +380,75 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(
   if (live && lane == 0) C[(int64_t)i * ldc + j] = acc;
 }
 
-// C = beta*C0 + alpha * X W diag(colscale)
-constexpr int PR = 64;   // rows per tile
-constexpr int PC = 32;   // cols per tile
-constexpr int PK = 32;   // k chunk
+// C = beta*C0 + alpha * X W diag(colscale), X tall (N x p), W small (p x q),
+// on the FP64 matrix cores.  A workgroup owns 64 rows and up to 128 columns
+// (NT tiles of 16), so X is read once for q <= 128; each wavefront
+// owns 16 rows x NT 16-column instruction tiles.  X (converted to FP64) and
+// W pass through LDS in chunks of 32 along p.
+constexpr int QR = 64;   // rows per workgroup
+constexpr int QK = 32;   // chunk along p
 
-template <class XT, class OT>
-__global__ __launch_bounds__(256) void panel_gemm_kernel(
+template <class XT, class OT, int NT>
+__global__ __launch_bounds__(256) void panel_mfma_kernel(
     int64_t N, int p, int q, const XT* __restrict__ X, int64_t ldx,
     const double* __restrict__ W, int64_t ldw, double alpha,
     const double* __restrict__ colscale, double beta,
     const OT* __restrict__ C0, int64_t ldc0, OT* __restrict__ C, int64_t ldc,
     const int* __restrict__ gate) {
+  using M = Mfma16<double>;
+  using V = M::V;
+  constexpr int QC = 16 * NT;
   if (gate && *gate == 0) return;
-  __shared__ double Xs[PR][PK + 1];
-  __shared__ double Ws[PK][PC + 1];
-  const int64_t r0 = (int64_t)blockIdx.x * PR;
-  const int c0 = blockIdx.y * PC;
-  const int tx = threadIdx.x % 16;   // 2 cols each
-  const int ty = threadIdx.x / 16;   // 4 rows each
-  double acc[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-  for (int k0 = 0; k0 < p; k0 += PK) {
-    for (int t = threadIdx.x; t < PR * PK; t += 256) {
-      const int r = t / PK, c = t % PK;
-      const int64_t row = r0 + r;
-      Xs[r][c] = (row < N && k0 + c < p) ? (double)X[row * ldx + k0 + c] : 0.0;
+  __shared__ double Xs[QR][QK + 1];
+  __shared__ double Ws[QK][QC + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * QR;
+  const int c0 = blockIdx.y * QC;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  V acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[t][v] = 0.0;
+  // loaders: X column xc of rows xr + 8 i; W row wr + 256 / QC * i
+  const int xc = threadIdx.x & (QK - 1), xr = threadIdx.x / QK;
+  for (int k0 = 0; k0 < p; k0 += QK) {
+    const bool kin = k0 + xc < p;
+#pragma unroll
+    for (int i = 0; i < QR / 8; ++i) {
+      const int64_t row = r0 + xr + 8 * i;
+      const bool ok = kin && row < N;
+      const int64_t rc = row < N ? row : N - 1;
+      const double v = (double)X[rc * ldx + (kin ? k0 + xc : 0)];
+      Xs[xr + 8 * i][xc] = ok ? v : 0.0;
     }
-    for (int t = threadIdx.x; t < PK * PC; t += 256) {
-      const int r = t / PC, c = t % PC;
+    for (int t = threadIdx.x; t < QK * QC; t += 256) {
+      const int r = t / QC, c = t % QC;
       Ws[r][c] = (k0 + r < p && c0 + c < q) ? W[(int64_t)(k0 + r) * ldw + c0 + c] : 0.0;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < PK; ++kk) {
-      const double w0 = Ws[kk][tx * 2], w1 = Ws[kk][tx * 2 + 1];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const double xv = Xs[ty * 4 + a][kk];
-        acc[a][0] += xv * w0;
-        acc[a][1] += xv * w1;
-      }
+    for (int kk = 0; kk < QK; kk += 4) {
+      const double a = Xs[w * 16 + lane % 16][kk + lane / 16];
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+        acc[t] = M::op(a, Ws[kk + lane / 16][t * 16 + lane % 16], acc[t]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int64_t row = r0 + ty * 4 + a;
-    if (row >= N) continue;
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int bcol = 0; bcol < 2; ++bcol) {
-      const int col = c0 + tx * 2 + bcol;
-      if (col >= q) continue;
-      double v = alpha * acc[a][bcol];
-      if (colscale) v *= colscale[col];
-      if (beta != 0.0) v += beta * (double)C0[row * ldc0 + col];
-      C[row * ldc + col] = (OT)v;
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = r0 + w * 16 + M::row(lane, v);
+      const int col = c0 + t * 16 + lane % 16;
+      if (row < N && col < q) {
+        double x = alpha * acc[t][v];
+        if (colscale) x *= colscale[col];
+        if (beta != 0.0) x += beta * (double)C0[row * ldc0 + col];
+        C[row * ldc + col] = (OT)x;
+      }
     }
-  }
 }
 
 // One workgroup: G (b x b, SPD) = R^T R, Rinv = R^-1 (upper triangular).
@@ -638,10 +650,23 @@ void launch_panel_gemm(int64_t N, int p, int q, const XT* X, int64_t ldx,
                        int64_t ldc0, OT* C, int64_t ldc, hipStream_t st,
                        const int* gate) {
   if (N <= 0 || q <= 0) return;
-  dim3 grid((unsigned)ceil_div(N, PR), (unsigned)ceil_div(q, PC));
-  hipLaunchKernelGGL((panel_gemm_kernel<XT, OT>), grid, dim3(256), 0, st, N, p,
-                     q, X, ldx, W, ldw, alpha, colscale, beta, C0, ldc0, C, ldc,
-                     gate);
+  // 16-column instruction tiles per workgroup: all of q up to 128
+  const int nt = (int)std::min<int64_t>(8, ceil_div(q, 16));
+  dim3 grid((unsigned)ceil_div(N, QR), (unsigned)ceil_div(q, 16 * nt));
+#define MC_PANEL(NT)                                                                   \
+  hipLaunchKernelGGL((panel_mfma_kernel<XT, OT, NT>), grid, dim3(256), 0, st, N, p, q, X, \
+                     ldx, W, ldw, alpha, colscale, beta, C0, ldc0, C, ldc, gate)
+  switch (nt) {
+    case 1: MC_PANEL(1); break;
+    case 2: MC_PANEL(2); break;
+    case 3: MC_PANEL(3); break;
+    case 4: MC_PANEL(4); break;
+    case 5: MC_PANEL(5); break;
+    case 6: MC_PANEL(6); break;
+    case 7: MC_PANEL(7); break;
+    default: MC_PANEL(8); break;
+  }
+#undef MC_PANEL
   MC_CHECK_LAUNCH();
 }
 template void launch_panel_gemm<double, double>(int64_t, int, int,

@@ -169,6 +169,37 @@ mc_status mc_k_gram(int64_t N, int32_t p, int32_t q, const double* A,
   });
 }
 
+mc_status mc_k_panel(int64_t N, int32_t p, int32_t q, const double* X,
+                     const double* W, double alpha, const double* colscale,
+                     double beta, const double* C0, int32_t precision,
+                     void* stream, double* C) {
+  return kguard([&] {
+    MC_REQUIRE(N >= 1 && p >= 1 && q >= 1 && X && W && C, mcsvt::kEINVAL,
+               "bad arguments");
+    MC_REQUIRE(beta == 0.0 || C0, mcsvt::kEINVAL, "beta != 0 needs C0");
+    hipStream_t st = (hipStream_t)stream;
+    mcsvt::DevBuf<double> dX, dW, ds, dC0, dC;
+    upload(dX, X, N * p, st);
+    upload(dW, W, (int64_t)p * q, st);
+    const double* pS = colscale ? upload(ds, colscale, q, st) : nullptr;
+    const double* pC0 = C0 ? upload(dC0, C0, N * q, st) : nullptr;
+    dC.reserve(N * q, st);
+    if (precision == MC_FP64) {
+      mcsvt::launch_panel_gemm<double, double>(N, p, q, dX.p, p, dW.p, q, alpha, pS, beta,
+                                               pC0, q, dC.p, q, st);
+    } else {
+      mcsvt::DevBuf<float> fX;
+      fX.reserve(N * p, st);
+      mcsvt::launch_cast<double, float>(N * p, dX.p, fX.p, st);
+      mcsvt::launch_panel_gemm<float, double>(N, p, q, fX.p, p, dW.p, q, alpha, pS, beta,
+                                              pC0, q, dC.p, q, st);
+      MC_HIP(hipStreamSynchronize(st));
+    }
+    download(C, dC.p, N * q, st);
+    MC_HIP(hipStreamSynchronize(st));
+  });
+}
+
 mc_status mc_k_cholqr2(int64_t N, int32_t b, const double* H, void* stream,
                        double* Q) {
   return kguard([&] {

@@ -69,6 +69,21 @@ def gram(A, B=None, precision="fp64"):
     return out
 
 
+def panel(X, W, alpha=1.0, colscale=None, beta=0.0, C0=None, precision="fp64"):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    N, p = X.shape
+    q = W.shape[1]
+    s = None if colscale is None else np.ascontiguousarray(colscale, dtype=np.float64)
+    c0 = None if C0 is None else np.ascontiguousarray(C0, dtype=np.float64)
+    out = np.zeros((N, q))
+    check(lib().mc_k_panel(N, p, q, _p(X, C.c_double), _p(W, C.c_double),
+                           float(alpha), None if s is None else _p(s, C.c_double),
+                           float(beta), None if c0 is None else _p(c0, C.c_double),
+                           _prec(precision), current_stream(), _p(out, C.c_double)))
+    return out
+
+
 def cholqr2(H):
     H = np.ascontiguousarray(H, dtype=np.float64)
     Q = np.zeros_like(H)

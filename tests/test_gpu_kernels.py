@@ -140,6 +140,29 @@ def test_gram_fp32(K, N, p, q, sym):
         assert np.array_equal(got, got.T)
 
 
+@pytest.mark.parametrize("N,p,q", [(1, 1, 1), (63, 5, 7), (1000, 21, 21), (4097, 33, 81),
+                                   (70001, 324, 81), (3000, 100, 129), (2000, 81, 300),
+                                   (500, 17, 16), (777, 64, 48)])
+def test_panel_matches_fp64_product(K, N, p, q):
+    # C = beta C0 + alpha X W diag(s): FP64 accumulation, error within the
+    # dot-product bound p u |X| |W|
+    rng = np.random.default_rng(N + p + q)
+    X = rng.standard_normal((N, p))
+    W = rng.standard_normal((p, q))
+    s = rng.uniform(0.5, 2.0, q)
+    C0 = rng.standard_normal((N, q))
+    got = K.panel(X, W, alpha=-0.75, colscale=s, beta=1.5, C0=C0)
+    want = 1.5 * C0 + (-0.75 * (X @ W)) * s
+    scale = 1.5 * np.abs(C0) + 0.75 * (np.abs(X) @ np.abs(W)) * s
+    assert np.max(np.abs(got - want) / scale) < (p + 4) * 2.0 ** -53
+    plain = K.panel(X, W)
+    assert np.max(np.abs(plain - X @ W) / (np.abs(X) @ np.abs(W))) < (p + 2) * 2.0 ** -53
+    # FP32 input rounding: the same product of the rounded X
+    Xf = X.astype(np.float32).astype(np.float64)
+    got32 = K.panel(X, W, precision="fp32")
+    assert np.max(np.abs(got32 - Xf @ W) / (np.abs(Xf) @ np.abs(W))) < (p + 2) * 2.0 ** -53
+
+
 @pytest.mark.parametrize("N,b,kappa", [(2000, 21, 1e2), (5000, 64, 1e5),
                                        (3000, 110, 1e3), (500, 7, 1e9)])
 def test_cholqr2_orthonormal_same_range(K, N, b, kappa):
