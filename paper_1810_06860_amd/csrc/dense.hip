@@ -140,13 +140,28 @@ __global__ __launch_bounds__(256) void gram_kernel(
   const int64_t n0 = (int64_t)sp * rows_per_split;
   const int64_t n1 = min(N, n0 + rows_per_split);
   const int a0 = ti * GT, b0 = tj * GT;
+  // Out-of-range elements load from a clamped in-range address and are
+  // zeroed by a factor 0 (not a select, which the compiler would turn back
+  // into a branch around each load and a wait after it).
+  const int c = threadIdx.x % GT;
+  const AT fa = a0 + c < p ? AT(1) : AT(0), fb = b0 + c < q ? AT(1) : AT(0);
+  const IT* Ac = A + (a0 + c < p ? a0 + c : 0);
+  const IT* Bc = B + (b0 + c < q ? b0 + c : 0);
   for (int64_t nb = n0; nb < n1; nb += GT) {
-    for (int t = threadIdx.x; t < GT * GT; t += 256) {
-      const int r = t / GT, c = t % GT;
-      const int64_t row = nb + r;
+    AT va[GT * GT / 256], vb[GT * GT / 256];
+#pragma unroll
+    for (int i = 0; i < GT * GT / 256; ++i) {
+      const int64_t row = nb + threadIdx.x / GT + (256 / GT) * i;
       const bool rin = row < n1;
-      As[r][c] = (rin && a0 + c < p) ? (AT)A[row * lda + a0 + c] : (AT)0;
-      Bs[r][c] = (rin && b0 + c < q) ? (AT)B[row * ldb + b0 + c] : (AT)0;
+      const int64_t rr = rin ? row : n0;
+      const AT m = rin ? AT(1) : AT(0);
+      va[i] = (AT)Ac[rr * lda] * (m * fa);
+      vb[i] = (AT)Bc[rr * ldb] * (m * fb);
+    }
+#pragma unroll
+    for (int i = 0; i < GT * GT / 256; ++i) {
+      As[threadIdx.x / GT + (256 / GT) * i][c] = va[i];
+      Bs[threadIdx.x / GT + (256 / GT) * i][c] = vb[i];
     }
     __syncthreads();
 #pragma unroll 8

@@ -561,10 +561,9 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
     W[(int64_t)i * ldw + j] = Z[t];
   }
   __syncthreads();
-  // reflector data back into LDS (row j, columns j+1 ..)
-  for (int j = 0; j + 2 < L; ++j)
-    for (int t = tid; t < L - j - 1; t += kTT)
-      A[j * L + j + 1 + t] = hh[(int64_t)j * L + j + 1 + t];
+  // reflector data back into LDS (row j, columns j+1 ..): one copy of the
+  // whole square, whose other entries the back-transformation never reads
+  for (int t = tid; t < L * L; t += kTT) A[t] = hh[t];
   __syncthreads();
 
   // ---- 4. back-transformation -------------------------------------------
