@@ -30,18 +30,25 @@ __device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
   __shared__ double trace;
   const int tid = threadIdx.x;
   const int tx = tid & 31, ty = tid >> 5, ny = (int)(blockDim.x >> 5);
+  // the diagonal of G in LDS (X is free until the inverse): the breakdown
+  // test reads it every column, and global reads there would be serial
+  double* gd = X;
+  for (int i = tid; i < b; i += blockDim.x) gd[i] = G[(int64_t)i * ldg + i];
+  __syncthreads();
   if (tid == 0) {
     double t = 0.0;
-    for (int i = 0; i < b; ++i) t += G[(int64_t)i * ldg + i];
+    for (int i = 0; i < b; ++i) t += gd[i];
     trace = t;
   }
   __syncthreads();
   const double u = 1.1102230246251565e-16;
   double shift = 0.0;
   for (int attempt = 0; attempt < 6; ++attempt) {
+    // G is stored full; the lower triangle is zeroed by a factor so the
+    // loads need no branch
     for (int i = ty; i < b; i += ny)
       for (int c = tx; c < b; c += 32) {
-        double v = (i <= c) ? G[(int64_t)i * ldg + c] : 0.0;
+        double v = G[(int64_t)i * ldg + c] * (i <= c ? 1.0 : 0.0);
         if (i == c) v += shift;
         R[i * b + c] = v;
       }
@@ -51,7 +58,7 @@ __device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
       // a pivot below 1e-13 of its original diagonal means kappa(H) of
       // order 1e6 or worse: Cholesky QR would lose all orthogonality
       const double d = R[j * b + j];
-      const double gjj = G[(int64_t)j * ldg + j] + shift;
+      const double gjj = gd[j] + shift;
       if (!(d > 1e-13 * gjj) || !(d > 1e-300)) {
         failed = true;                               // the same for every thread
         break;
@@ -194,9 +201,18 @@ __global__ __launch_bounds__(256) void gram_kernel(
     const int i = (int)(t / q), j = (int)(t % q);
     int si = i, sj = j;
     if (sym && (i / GT) > (j / GT)) { si = j; sj = i; }   // mirrored tile
+    // splits in groups of eight independent loads, summed in split order
+    const AT* pp = part + (int64_t)si * q + sj;
     double acc = 0.0;
-    for (int sp2 = 0; sp2 < tail.nsplit; ++sp2)
-      acc += (double)part[(int64_t)sp2 * tot + (int64_t)si * q + sj];
+    int sp2 = 0;
+    for (; sp2 + 8 <= tail.nsplit; sp2 += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (double)pp[(int64_t)(sp2 + u) * tot];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; sp2 < tail.nsplit; ++sp2) acc += (double)pp[(int64_t)sp2 * tot];
     tail.C[(int64_t)i * tail.ldc + j] = acc;
   }
   __threadfence();
