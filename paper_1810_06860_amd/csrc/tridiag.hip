@@ -612,6 +612,8 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
 // transformation kernel with each vector in registers.
 
 constexpr int kBigRows = 4;        // trailing rows per workgroup (one per wavefront)
+constexpr int kStepPer = 16;       // row entries per lane: rows of up to 64 * 16 = 1024
+static_assert(64 * kStepPer >= 64 * kVecLanes, "big_step_kernel rows must cover tri_big_max()");
 
 // Launch j (0 <= j < j0) of the tridiagonalisation.  It first applies the
 // rank-2 update of step j-1, A22 -= v w^T + w v^T with w = p - (beta/2)(p^T v) v,
@@ -631,7 +633,7 @@ __global__ __launch_bounds__(256) void big_step_kernel(
   double* vp = sv;            // v of step j-1 on [j, L)
   double* wp = vp + L;        // w of step j-1 on [j, L)
   double* vj = wp + L;        // v of step j on [j + 1, L)
-  __shared__ double red[4];
+  __shared__ double red[4], redp[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool last = j == j0;
   const int o = last ? j : j + 1;             // first row / column this launch touches
@@ -644,8 +646,13 @@ __global__ __launch_bounds__(256) void big_step_kernel(
     const double* __restrict__ Pp = Pbuf + (size_t)(jp & 1) * L;
     const double* __restrict__ pp = pbuf + (size_t)(jp & 1) * npart_stride;
     const int nparts = (L - j + kBigRows - 1) / kBigRows;
-    double pvt = 0.0;
-    for (int w = 0; w < nparts; ++w) pvt += pp[w];
+    // p^T v: the partials summed by the whole workgroup (one load each)
+    double pv = 0.0;
+    for (int w = tid; w < nparts; w += 256) pv += pp[w];
+    pv = wsum(pv);
+    if (lane == 0) redp[wave] = pv;
+    __syncthreads();
+    const double pvt = (redp[0] + redp[1]) + (redp[2] + redp[3]);
     const double K = 0.5 * bp * pvt;
     for (int c = j + tid; c < L; c += 256) {
       const double v = c == j ? 1.0 : hh[(int64_t)jp * L + c] * rvp;
@@ -696,14 +703,23 @@ __global__ __launch_bounds__(256) void big_step_kernel(
     if (r < n) {
       const int a = o + r;
       double* __restrict__ row = Ag + (int64_t)a * L;
+      // the row's entries first (all loads in flight; lanes past the end read
+      // the last entry), then the update and the product
+      double xs[kStepPer];
+#pragma unroll
+      for (int u = 0; u < kStepPer; ++u) xs[u] = row[min(o + lane + 64 * u, L - 1)];
       double acc = 0.0;
-      for (int c = o + lane; c < L; c += 64) {
-        double x = row[c];
-        if (upd) {
-          x -= vp[a] * wp[c] + wp[a] * vp[c];
-          row[c] = x;
+#pragma unroll
+      for (int u = 0; u < kStepPer; ++u) {
+        const int c = o + lane + 64 * u;
+        if (c < L) {
+          double x = xs[u];
+          if (upd) {
+            x -= vp[a] * wp[c] + wp[a] * vp[c];
+            row[c] = x;
+          }
+          acc += x * vj[c];
         }
-        acc += x * vj[c];
       }
       acc = wsum(acc);
       pr = beta * acc;
@@ -719,7 +735,14 @@ __global__ __launch_bounds__(256) void big_step_kernel(
     if (o + r < L) {
       const int a = o + r;
       double* __restrict__ row = Ag + (int64_t)a * L;
-      for (int c = o + lane; c < L; c += 64) row[c] -= vp[a] * wp[c] + wp[a] * vp[c];
+      double xs[kStepPer];
+#pragma unroll
+      for (int u = 0; u < kStepPer; ++u) xs[u] = row[min(o + lane + 64 * u, L - 1)];
+#pragma unroll
+      for (int u = 0; u < kStepPer; ++u) {
+        const int c = o + lane + 64 * u;
+        if (c < L) row[c] = xs[u] - (vp[a] * wp[c] + wp[a] * vp[c]);
+      }
     }
   }
 }
