@@ -23,6 +23,14 @@ namespace {
 
 constexpr int GT = 32;   // gram tile
 
+// 1/x from the hardware estimate and two Newton steps (about 1 ulp), for the
+// serial chains of the factorisation; x is a positive normal number there
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * (2.0 - x * r);
+  return r * (2.0 - x * r);
+}
+
 __device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
                                double* __restrict__ Rinv, int64_t ldr, double* R,
                                double* X, int64_t nrows, int* __restrict__ shifted,
@@ -63,7 +71,7 @@ __device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
         failed = true;                               // the same for every thread
         break;
       }
-      const double rd = 1.0 / d;
+      const double rd = rcp_nr(d);
       // rows i > j over thread rows, columns c >= i over the 32 lanes of a
       // thread row (no index division in the loop)
       for (int i = j + 1 + ty; i < b; i += ny) {
@@ -91,13 +99,18 @@ __device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
     for (int c = i + 1 + tx; c < b; c += 32) R[i * b + c] = R[i * b + c] / si;
   }
   __syncthreads();
-  for (int i = tid; i < b; i += blockDim.x) R[i * b + i] = X[i];
+  __shared__ double invd[kCholLdsMax];
+  for (int i = tid; i < b; i += blockDim.x) {
+    R[i * b + i] = X[i];
+    if (i < kCholLdsMax) invd[i] = rcp_nr(X[i]);
+  }
   __syncthreads();
   // column c of R^{-1} by back substitution (thread per column), in LDS; the
   // dot products run on four partial sums
   for (int c = tid; c < b; c += blockDim.x) {
     for (int i = b - 1; i > c; --i) X[i * b + c] = 0.0;
-    X[c * b + c] = 1.0 / R[c * b + c];
+    const bool fast = b <= kCholLdsMax;              // reciprocals of the diagonal in LDS
+    X[c * b + c] = fast ? invd[c] : 1.0 / R[c * b + c];
     for (int i = c - 1; i >= 0; --i) {
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       int t = i + 1;
@@ -108,7 +121,8 @@ __device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
         a3 += R[i * b + t + 3] * X[(t + 3) * b + c];
       }
       for (; t <= c; ++t) a0 += R[i * b + t] * X[t * b + c];
-      X[i * b + c] = -((a0 + a1) + (a2 + a3)) / R[i * b + i];
+      const double dot = (a0 + a1) + (a2 + a3);
+      X[i * b + c] = fast ? -dot * invd[i] : -dot / R[i * b + i];
     }
   }
   __syncthreads();

@@ -377,9 +377,9 @@ void SolverT<P, VT, AT>::orth_block(int j, int b, int Lw) {
   cholqr_pass(H2_.p, b, H1_.p, b, b, nullptr);
   project(H1_.p, b, H2_.p, jb, b, Lw, nullptr);
   cholqr_pass(H2_.p, b, out, Lw, b, nullptr);
+  // the gated pass writes the block directly (it reads H2, not the block)
   project(out, Lw, H2_.p, jb, b, Lw, gate);
-  cholqr_pass(H2_.p, b, H1_.p, b, b, gate);
-  launch_copy_gated<P>(m_, b, H1_.p, b, out, Lw, gate, ls());
+  cholqr_pass(H2_.p, b, out, Lw, b, gate);
 }
 
 // S (k values) and, with the Ritz guard, the k Ritz ratios: enqueued copies
