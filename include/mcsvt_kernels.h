@@ -66,9 +66,12 @@ mc_status mc_k_panel(int64_t N, int32_t p, int32_t q, const double* X,
 mc_status mc_k_cholqr2(int64_t N, int32_t b, const double* H, void* stream,
                        double* Q);
 
-/* Symmetric eigensolver (block Jacobi, FP64) of G (L x L): the k largest
- * eigenvalues, descending, in evals (k) and their eigenvectors in W (L x k);
- * *sweeps receives the number of Jacobi sweeps. */
+/* Top-k symmetric eigensolver (FP64) of G (L x L), the solver's own dispatch:
+ * one-wavefront Jacobi for L <= 16, Householder tridiagonalisation +
+ * multisection + inverse iteration up to L = 1024 (k <= 140), block Jacobi
+ * beyond.  The k largest eigenvalues, descending, in evals (k) and their
+ * eigenvectors in W (L x k); *sweeps receives the number of block-Jacobi
+ * sweeps (0 on the other paths). */
 mc_status mc_k_syev(int32_t L, const double* G, int32_t k, void* stream,
                     double* evals, double* W, int32_t* sweeps);
 

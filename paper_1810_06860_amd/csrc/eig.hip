@@ -60,6 +60,114 @@ __device__ __forceinline__ int rr_pos(int j, int rr, int n2) {
   return 1 + x;
 }
 
+// Tiny eigenproblems (L <= kTinyL) in one wavefront: cyclic Jacobi with the
+// round-robin ordering of the L indices (a dummy pads odd L), A and the
+// eigenvector matrix V in LDS.  A round computes the rotations of its
+// disjoint pairs, then applies them to the rows of A, then to the columns of
+// A and V (A <- J^T A J, V <- V J).  One wavefront's LDS operations complete
+// in order, so the rounds need wavefront fences, not barriers.  A rotation is
+// applied only when |a_pq| > max(4e-15 sqrt(|a_pp a_qq|), 1e-14 ||G||_F);
+// the solve stops after a sweep without rotations (at most 40 sweeps).
+constexpr int kTinyL = 16;
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(64) void jac_tiny_kernel(
+    int L, const double* __restrict__ G, int64_t ldg, int k, double* __restrict__ S_out,
+    double* __restrict__ D_out, double* __restrict__ W_out, int64_t ldw) {
+  __shared__ double A[kTinyL][kTinyL + 1];
+  __shared__ double V[kTinyL][kTinyL + 1];
+  __shared__ double Cs[kTinyL / 2], Sn[kTinyL / 2];
+  __shared__ int Pp[kTinyL / 2], Qq[kTinyL / 2], idx[kTinyL];
+  const int lane = threadIdx.x;
+  double f2 = 0.0;
+  for (int t = lane; t < L * L; t += 64) {
+    const int i = t / L, j = t % L;
+    const double g = G[(int64_t)i * ldg + j];
+    A[i][j] = g;
+    V[i][j] = i == j ? 1.0 : 0.0;
+    f2 += g * g;
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) f2 += __shfl_xor(f2, o, 64);
+  const double tol_abs = 1e-14 * sqrt(f2);
+  wave_sync();
+  const int n2 = L + (L & 1), np = n2 / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    bool rotated = false;
+    for (int rr = 0; rr < n2 - 1; ++rr) {
+      double c = 1.0, sn = 0.0;
+      if (lane < np) {
+        int p = rr_pos(lane, rr, n2), q = rr_pos(n2 - 1 - lane, rr, n2);
+        if (p > q) { const int x = p; p = q; q = x; }
+        if (q < L) {
+          const double app = A[p][p], aqq = A[q][q], apq = A[p][q];
+          if (fabs(apq) > fmax(4e-15 * sqrt(fabs(app * aqq)), tol_abs)) {
+            const double th = (aqq - app) / (2.0 * apq);
+            const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = t * c;
+          }
+        }
+        Cs[lane] = c;
+        Sn[lane] = sn;
+        Pp[lane] = p;
+        Qq[lane] = q;
+      }
+      const bool any = __any(sn != 0.0);
+      wave_sync();
+      if (!any) continue;                      // uniform
+      rotated = true;
+      for (int t = lane; t < np * L; t += 64) {  // rows p, q of A
+        const int i = t / L, j = t % L;
+        const int p = Pp[i], q = Qq[i];
+        const double ci = Cs[i], si = Sn[i];
+        if (q < L && si != 0.0) {
+          const double ap = A[p][j], aq = A[q][j];
+          A[p][j] = ci * ap - si * aq;
+          A[q][j] = si * ap + ci * aq;
+        }
+      }
+      wave_sync();
+      for (int t = lane; t < np * L; t += 64) {  // columns p, q of A and V
+        const int i = t / L, j = t % L;
+        const int p = Pp[i], q = Qq[i];
+        const double ci = Cs[i], si = Sn[i];
+        if (q < L && si != 0.0) {
+          const double ap = A[j][p], aq = A[j][q];
+          A[j][p] = ci * ap - si * aq;
+          A[j][q] = si * ap + ci * aq;
+          const double vp = V[j][p], vq = V[j][q];
+          V[j][p] = ci * vp - si * vq;
+          V[j][q] = si * vp + ci * vq;
+        }
+      }
+      wave_sync();
+    }
+    if (!rotated) break;
+  }
+  // the k largest: rank by (value descending, index ascending)
+  if (lane < L) {
+    const double dj = A[lane][lane];
+    int rank = 0;
+    for (int i = 0; i < L; ++i) rank += (A[i][i] > dj) || (A[i][i] == dj && i < lane);
+    if (rank < k) {
+      idx[rank] = lane;
+      if (D_out) D_out[rank] = dj;
+      S_out[rank] = sqrt(fmax(dj, 0.0));
+    }
+  }
+  wave_sync();
+  for (int t = lane; t < L * k; t += 64) {
+    const int i = t / k, c = t % k;
+    W_out[(int64_t)i * ldw + c] = V[i][idx[c]];
+  }
+}
+
 __global__ __launch_bounds__(kSingleThreads) void jac_topk_kernel(
     int L, const double* __restrict__ G, int64_t ldg, int k,
     double* __restrict__ S_out, double* __restrict__ D_out,
@@ -557,6 +665,15 @@ bool EigSolver::device_only(int L, int k) {
 
 void EigSolver::solve_topk(int L, const double* G, int64_t ldg, int k, double* S,
                            double* D, double* Wk, int64_t ldw, hipStream_t st) {
+  if (L <= kTinyL) {
+    hipLaunchKernelGGL(jac_tiny_kernel, dim3(1), dim3(64), 0, st, L, G, ldg, k, S, D, Wk,
+                       ldw);
+    MC_CHECK_LAUNCH();
+    this->L = L;
+    this->Lp = L;
+    sweeps = 0;      // known on the device only
+    return;
+  }
   if (tri_fits(L, k, lds_limit())) {
     reserve(L, st);
     this->L = L;

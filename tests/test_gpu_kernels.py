@@ -176,7 +176,8 @@ def test_cholqr2_orthonormal_same_range(K, N, b, kappa):
     assert np.linalg.norm(Q @ (Q.T @ Qr) - Qr) < 1e-8 * max(1.0, kappa * 1e-8)
 
 
-@pytest.mark.parametrize("L,k", [(5, 3), (21, 5), (32, 32), (64, 64), (84, 11),
+@pytest.mark.parametrize("L,k", [(1, 1), (2, 2), (5, 3), (9, 9), (13, 5), (16, 16),
+                                 (17, 8), (21, 5), (32, 32), (64, 64), (84, 11),
                                  (130, 40), (150, 20), (330, 110)])
 def test_syev_matches_eigh(K, L, k):
     rng = np.random.default_rng(L)
@@ -220,6 +221,24 @@ def test_syev_large_clustered(K):
     np.testing.assert_allclose(ev[:7], [9.0] * 4 + [4.0] * 3, rtol=1e-12)
     assert np.linalg.norm(G @ W - W * ev) < 1e-12 * 9.0 * np.sqrt(10)
     assert np.linalg.norm(W.T @ W - np.eye(10)) < 2e-14 * 220
+
+
+def test_syev_tiny_repeated_and_graded(K):
+    # the one-wavefront Jacobi path (L <= 16): repeated eigenvalues, a graded
+    # spectrum over 12 orders of magnitude, and a diagonal input
+    rng = np.random.default_rng(12)
+    Q, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    lam = np.array([5.0, 5.0, 5.0, 2.0, 2.0] + list(np.logspace(0, -12, 7)))
+    G = (Q * lam) @ Q.T
+    G = 0.5 * (G + G.T)
+    ev, W, _ = K.syev(G, 6)
+    np.testing.assert_allclose(ev[:5], [5.0, 5.0, 5.0, 2.0, 2.0], rtol=1e-13)
+    assert np.linalg.norm(G @ W - W * ev) < 1e-13 * 5.0 * np.sqrt(6)
+    assert np.linalg.norm(W.T @ W - np.eye(6)) < 1e-13
+    D = np.diag([3.0, 1.0, 4.0, 1.5, 9.0, 2.6, 5.0])
+    ev2, W2, _ = K.syev(D, 7)
+    np.testing.assert_array_equal(ev2, [9.0, 5.0, 4.0, 3.0, 2.6, 1.5, 1.0])
+    np.testing.assert_array_equal(np.abs(W2), np.eye(7)[:, [4, 6, 2, 0, 5, 3, 1]])
 
 
 def test_syev_degenerate_and_diagonal(K):
