@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define MCSVT_ABI_VERSION 1
+#define MCSVT_ABI_VERSION 2
 
 typedef struct mc_svt* mc_svt_t;
 
@@ -112,6 +112,11 @@ typedef struct {
   double c;         /* the constant of Y^0 actually used */
   double norm2;     /* ||P_Phi(M)||_2 as computed on the device */
   double mnorm;     /* ||P_Phi(M)||_F */
+  int32_t shifts;   /* Cholesky factorisations of the block orthonormalisation
+                       that needed a diagonal shift (shifted Cholesky QR), as of
+                       the last rSVD-BKI call */
+  int32_t redone;   /* rSVD-BKI calls redone with the third orthonormalisation
+                       pass because a factorisation needed a shift */
 } mc_svt_result;
 
 /* Optional allocator hooks (e.g. a framework's caching allocator).  alloc

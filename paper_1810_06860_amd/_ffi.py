@@ -48,7 +48,7 @@ class Result(C.Structure):
                 ("converged", C.c_int32), ("fresh", C.c_int32),
                 ("recycled", C.c_int32), ("rejected", C.c_int32),
                 ("res", C.c_double), ("c", C.c_double), ("norm2", C.c_double),
-                ("mnorm", C.c_double)]
+                ("mnorm", C.c_double), ("shifts", C.c_int32), ("redone", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -125,6 +125,8 @@ void fill_result(const mcsvt::Solver& s, mc_svt_result* o) {
   o->c = s.c();
   o->norm2 = s.norm2();
   o->mnorm = s.mnorm();
+  o->shifts = s.shifts_seen();
+  o->redone = s.redone_total();
 }
 
 // COO rows from either COO row ids or a CSR row pointer (host).

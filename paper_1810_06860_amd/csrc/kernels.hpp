@@ -121,7 +121,10 @@ template <class T>
 void launch_copy_gated(int64_t rows, int cols, const T* src, int64_t lds_, T* dst,
                        int64_t ldd, const int* gate, hipStream_t st);
 
-void launch_recip(int k, const double* S, double* out, hipStream_t st);
+// out = 1 / S (0 where S <= 0); with `count`, also count_out[0] = *count (so
+// one copy to the host can carry both)
+void launch_recip(int k, const double* S, double* out, hipStream_t st,
+                  const int* count = nullptr, double* count_out = nullptr);
 // out[j] = ||R_j - S_j U_j|| / S_j  (Ritz residual ratios, k columns)
 int ritz_blocks(int64_t m);
 template <class T>

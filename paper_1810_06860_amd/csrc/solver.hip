@@ -110,10 +110,16 @@ void Solver::mark() {
 void Solver::wait() { MC_HIP(hipEventSynchronize(done_ev_)); }
 
 void Solver::fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt) {
-  fresh_launch(k, p, step_id, attempt);
+  fresh_launch(k, p, step_id, attempt, false);
   mark();
   wait();
-  fresh_finish(k);
+  if (!fresh_finish(k)) {
+    ++redone_total_;
+    fresh_launch(k, p, step_id, attempt, true);
+    mark();
+    wait();
+    fresh_finish(k);
+  }
 }
 
 double Solver::sddmm(int r) {
@@ -132,7 +138,8 @@ void Solver::launch_svd(bool force_fresh) {
                      q_ == prm_.q_reuse || basis_cols_ == 0 || k > basis_cols_ ||
                      suspended;
   if (fresh) {
-    fresh_launch(k, p_, (uint32_t)i_, attempt_++);
+    last_attempt_ = attempt_++;
+    fresh_launch(k, p_, (uint32_t)i_, last_attempt_, false);
     ++cur_.fresh;
   } else {
     recycled_launch(k);
@@ -189,8 +196,13 @@ bool Solver::step_poll(bool block) {
           launch_svd(true);
           return false;
         }
-      } else {
-        fresh_finish(k_cur_);
+      } else if (!fresh_finish(k_cur_)) {
+        // a shifted Cholesky factorisation in the unguarded call: redo it
+        // guarded (same attempt, same test matrix)
+        ++redone_total_;
+        fresh_launch(k_cur_, p_, (uint32_t)i_, last_attempt_, true);
+        mark();
+        return false;
       }
       if (lastS_[k_cur_ - 1] > prm_.tau && k_cur_ < kcap_) {  // rank search
         k_cur_ = std::min(k_cur_ + prm_.l, kcap_);

@@ -97,6 +97,8 @@ class Solver {
   int fresh_total() const { return fresh_total_; }
   int recycled_total() const { return recycled_total_; }
   int rejected_total() const { return rejected_total_; }
+  int shifts_seen() const { return shifts_seen_; }
+  int redone_total() const { return redone_total_; }
   const std::vector<double>& last_sigma() const { return lastS_; }
   hipStream_t stream() const { return st_; }
 
@@ -106,9 +108,15 @@ class Solver {
  protected:
   // One rSVD-BKI call: enqueues the device work and the copy of its k
   // singular values to the host, sets k_last_, the recycling basis, q_ = 0.
-  virtual void fresh_launch(int k, int p, uint32_t step_id, uint32_t attempt) = 0;
-  // after the enqueued work finished: lastS_ (k, descending)
-  virtual void fresh_finish(int k) = 0;
+  // Unguarded, the orthonormalisation runs two passes per block; guarded, it
+  // adds the third pass that a shifted Cholesky factorisation needs (gated on
+  // the device by a flag).
+  virtual void fresh_launch(int k, int p, uint32_t step_id, uint32_t attempt,
+                            bool guarded) = 0;
+  // after the enqueued work finished: lastS_ (k, descending).  False when an
+  // unguarded call needed a shifted factorisation: the call must be redone
+  // guarded (same test matrix), which gives the result of the guarded form.
+  virtual bool fresh_finish(int k) = 0;
   // One recycled SVD from the saved basis (enqueue), then lastS_ and the
   // worst Ritz ratio when the guard is on (else 0).
   virtual void recycled_launch(int k) = 0;
@@ -129,7 +137,7 @@ class Solver {
   StepInfo cur_;
   int k_cur_ = 0;
   bool cur_recycled_ = false;
-  uint32_t attempt_ = 0;
+  uint32_t attempt_ = 0, last_attempt_ = 0;
   hipEvent_t done_ev_ = nullptr;
   void launch_svd(bool force_fresh);
 
@@ -150,6 +158,8 @@ class Solver {
   bool converged_ = false;
   double c_ = 0.0, norm2_ = 0.0, mnorm_ = 0.0;
   int fresh_total_ = 0, recycled_total_ = 0, rejected_total_ = 0;
+  int shifts_seen_ = 0;         // shift count read back with the last fresh call
+  int redone_total_ = 0;        // fresh calls redone guarded
 };
 
 // FP64, FP32 or BF16-value solver according to prm.precision

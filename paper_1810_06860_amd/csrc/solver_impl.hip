@@ -89,8 +89,9 @@ class SolverT final : public Solver {
   }
 
  protected:
-  void fresh_launch(int k, int p, uint32_t step_id, uint32_t attempt) override;
-  void fresh_finish(int k) override;
+  void fresh_launch(int k, int p, uint32_t step_id, uint32_t attempt,
+                    bool guarded) override;
+  bool fresh_finish(int k) override;
   void recycled_launch(int k) override;
   double recycled_finish(int k) override;
   void sddmm_launch(int r) override;
@@ -100,9 +101,9 @@ class SolverT final : public Solver {
   using GraphKey = std::array<int64_t, 8>;
   void ensure(int bmax, int Lmax, int kmax);
   void eig_body(const P* basis, int64_t ldb, int w, int k);
-  void fresh_body(int k, int b, int p_eff, int Lw);
+  void fresh_body(int k, int b, int p_eff, int Lw, bool guarded);
   void ritz_body(int k);
-  void read_launch(int k, bool ritz);
+  void read_launch(int k, bool ritz, bool count = false);
   double read_finish(int k, bool ritz);
   hipStream_t ls() const { return capturing_ ? cap_ : st_; }
   // capture needs an eigensolve without host round trips
@@ -115,7 +116,7 @@ class SolverT final : public Solver {
     for (auto& kv : graphs_) (void)hipGraphExecDestroy(kv.second);
     graphs_.clear();
   }
-  void orth_block(int j, int b, int Lw);
+  void orth_block(int j, int b, int Lw, bool guarded);
   void cholqr_pass(const P* Hin, int64_t ldin, P* out, int64_t ldo, int b,
                    const int* gate);
   void project(const P* Hin, int64_t ldin, P* Hout, int jb, int b, int Lw,
@@ -156,6 +157,7 @@ class SolverT final : public Solver {
   int64_t gram_cap_ = 0;
   EigSolver eig_;
   double* hbuf_ = nullptr;       // pinned host scratch
+  bool last_guarded_ = true;     // the last fresh call ran the gated third pass
   size_t hbuf_n_ = 0;
 };
 
@@ -195,7 +197,7 @@ void SolverT<P, VT, AT>::ensure(int bmax, int Lmax, int kmax) {
   spmm_part_.reserve(std::max<int64_t>(1, slots) * wide, st_);
   U_.reserve(m_ * k, st_);
   V_.reserve(n_ * k, st_);
-  S_.reserve(k, st_);
+  S_.reserve(k + 1, st_);         // + the shift count behind the values
   Sinv_.reserve(k, st_);
   D_.reserve(Lc, st_);
   Wk_.reserve(Lc * k, st_);
@@ -361,15 +363,17 @@ void SolverT<P, VT, AT>::project(const P* Hin, int64_t ldin, P* Hout, int jb, in
 // passes, and a third one only when a Cholesky factorisation needed a shift
 // (the device flag gates it; no host round trip).
 template <class P, class VT, class AT>
-void SolverT<P, VT, AT>::orth_block(int j, int b, int Lw) {
+void SolverT<P, VT, AT>::orth_block(int j, int b, int Lw, bool guarded) {
   P* out = Qw_.p + (int64_t)j * b;
   const int* gate = blk_flag_.p;
-  launch_set_int(blk_flag_.p, 0, ls());
+  if (guarded) launch_set_int(blk_flag_.p, 0, ls());
   if (j == 0) {
     cholqr_pass(H1_.p, b, H2_.p, b, b, nullptr);
     cholqr_pass(H2_.p, b, out, Lw, b, nullptr);
-    cholqr_pass(out, Lw, H1_.p, b, b, gate);
-    launch_copy_gated<P>(m_, b, H1_.p, b, out, Lw, gate, ls());
+    if (guarded) {
+      cholqr_pass(out, Lw, H1_.p, b, b, gate);
+      launch_copy_gated<P>(m_, b, H1_.p, b, out, Lw, gate, ls());
+    }
     return;
   }
   const int jb = j * b;
@@ -378,15 +382,19 @@ void SolverT<P, VT, AT>::orth_block(int j, int b, int Lw) {
   project(H1_.p, b, H2_.p, jb, b, Lw, nullptr);
   cholqr_pass(H2_.p, b, out, Lw, b, nullptr);
   // the gated pass writes the block directly (it reads H2, not the block)
-  project(out, Lw, H2_.p, jb, b, Lw, gate);
-  cholqr_pass(H2_.p, b, out, Lw, b, gate);
+  if (guarded) {
+    project(out, Lw, H2_.p, jb, b, Lw, gate);
+    cholqr_pass(H2_.p, b, out, Lw, b, gate);
+  }
 }
 
 // S (k values) and, with the Ritz guard, the k Ritz ratios: enqueued copies
 // to pinned host memory, read once the stream has reached them
 template <class P, class VT, class AT>
-void SolverT<P, VT, AT>::read_launch(int k, bool ritz) {
-  MC_HIP(hipMemcpyAsync(hbuf_, S_.p, k * sizeof(double), hipMemcpyDeviceToHost, st_));
+void SolverT<P, VT, AT>::read_launch(int k, bool ritz, bool count) {
+  // with `count`, the shift count that the eigSVD step stored behind S
+  MC_HIP(hipMemcpyAsync(hbuf_, S_.p, (k + (count ? 1 : 0)) * sizeof(double),
+                        hipMemcpyDeviceToHost, st_));
   if (ritz)
     MC_HIP(hipMemcpyAsync(hbuf_ + k, ritz_out_.p, k * sizeof(double),
                           hipMemcpyDeviceToHost, st_));
@@ -420,7 +428,7 @@ void SolverT<P, VT, AT>::eig_body(const P* basis, int64_t ldb, int w, int k) {
              2.0 * (m_ + n_) * w * k, ls());
   launch_panel_gemm<P, P>(m_, w, k, basis, ldb, Wk_.p, k, 1.0, nullptr, 0.0, nullptr,
                           0, U_.p, k, ls());                 // U = Q W
-  launch_recip(k, S_.p, Sinv_.p, ls());
+  launch_recip(k, S_.p, Sinv_.p, ls(), shift_count_.p, S_.p + k);
   launch_panel_gemm<P, P>(n_, w, k, Bt_.p, w, Wk_.p, k, 1.0, Sinv_.p, 0.0, nullptr, 0,
                           V_.p, k, ls());                    // V = B^T W S^-1
   prof.end(ls());
@@ -434,16 +442,16 @@ void SolverT<P, VT, AT>::ritz_body(int k) {
 }
 
 template <class P, class VT, class AT>
-void SolverT<P, VT, AT>::fresh_body(int k, int b, int p_eff, int Lw) {
+void SolverT<P, VT, AT>::fresh_body(int k, int b, int p_eff, int Lw, bool guarded) {
   prof.begin(kProfRng, (double)sizeof(P) * n_ * b, 0.0, ls());
   launch_gaussian_ctr<P>(omega_.p, n_, b, b, prm_.seed, ctr_.p, ls());
   prof.end(ls());
   spmm_y(omega_.p, b, H1_.p, b, b);                          // H_0 = Y Omega
-  orth_block(0, b, Lw);
+  orth_block(0, b, Lw, guarded);
   for (int j = 1; j <= p_eff; ++j) {
     spmm_yt(Qw_.p + (int64_t)(j - 1) * b, Lw, Z_.p, b, b);   // Y^T Q_{j-1}
     spmm_y(Z_.p, b, H1_.p, b, b);                            // H_j
-    orth_block(j, b, Lw);
+    orth_block(j, b, Lw, guarded);
   }
   eig_body(Qw_.p, Lw, Lw, k);
 }
@@ -487,7 +495,8 @@ void SolverT<P, VT, AT>::run_graph(const GraphKey& key, F&& body) {
 }
 
 template <class P, class VT, class AT>
-void SolverT<P, VT, AT>::fresh_launch(int k, int p, uint32_t step_id, uint32_t attempt) {
+void SolverT<P, VT, AT>::fresh_launch(int k, int p, uint32_t step_id, uint32_t attempt,
+                                      bool guarded) {
   int b, p_eff;
   widths(k, p, b, p_eff);
   const int Lw = (p_eff + 1) * b;
@@ -497,13 +506,15 @@ void SolverT<P, VT, AT>::fresh_launch(int k, int p, uint32_t step_id, uint32_t a
   hctr_[1] = attempt;
   MC_HIP(hipMemcpyAsync(ctr_.p, hctr_, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, st_));
   if (graphs_ok(Lw, k)) {
-    const GraphKey key{1, k, b, p_eff, Lw, (int64_t)gen_, (int64_t)(intptr_t)Qw_.p, 0};
-    run_graph(key, [&] { fresh_body(k, b, p_eff, Lw); });
+    const GraphKey key{1, k, b, p_eff, Lw, (int64_t)gen_, (int64_t)(intptr_t)Qw_.p,
+                       guarded ? 1 : 0};
+    run_graph(key, [&] { fresh_body(k, b, p_eff, Lw, guarded); });
   } else {
-    fresh_body(k, b, p_eff, Lw);
+    fresh_body(k, b, p_eff, Lw, guarded);
   }
+  last_guarded_ = guarded;
   k_last_ = k;
-  read_launch(k, false);
+  read_launch(k, false, true);
   if (prm_.recycle == 1) {
     swap_buf(Qw_, basis_);
     basis_ld_ = Lw;
@@ -519,8 +530,12 @@ void SolverT<P, VT, AT>::fresh_launch(int k, int p, uint32_t step_id, uint32_t a
 }
 
 template <class P, class VT, class AT>
-void SolverT<P, VT, AT>::fresh_finish(int k) {
+bool SolverT<P, VT, AT>::fresh_finish(int k) {
   read_finish(k, false);
+  const int sc = (int)hbuf_[k];
+  const bool redo = !last_guarded_ && sc != shifts_seen_;
+  shifts_seen_ = sc;
+  return !redo;
 }
 
 // Recycled SVD from the saved basis (Sec. IV.B); the finish returns the

@@ -49,7 +49,7 @@ def test_binding_covers_every_symbol():
 
 def test_default_params_and_version(lib):
     from paper_1810_06860_amd import default_params
-    assert lib.mc_abi_version() == 1
+    assert lib.mc_abi_version() == 2
     p = default_params()
     assert p["l"] == 5 and p["s"] == 10 and p["p_init"] == 3
     assert p["q_reuse"] == 10 and p["eps"] == 1e-4 and p["recycle"] == 0

@@ -170,6 +170,39 @@ def test_recycling_strategies_match_oracle(recycle, ritz_tol):
         assert recycled > 0          # the literal rule does recycle here
 
 
+def test_ill_conditioned_blocks_redo_guarded():
+    # A fully observed rank-6 matrix plus 1e-6 noise: every Krylov block
+    # (width k + 10) is numerically rank deficient, so its Cholesky QR needs a
+    # diagonal shift and the fresh call is redone with the third
+    # orthonormalisation pass.  The oracle's rSVD-BKI refuses such spaces
+    # (its eigSVD guard), so the reference here is exact SVT (dense SVD
+    # shrinkage): with the gap between the kept and the dropped singular
+    # values, the fast steps agree with it to rounding.
+    from paper_1810_06860_amd import SVT
+    rng = np.random.default_rng(77)
+    m, n = 120, 90
+    U, _ = np.linalg.qr(rng.standard_normal((m, 6)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, 6)))
+    sv = np.array([1000.0, 800.0, 600.0, 400.0, 300.0, 50.0])
+    M = (U * sv) @ V.T + 1e-6 * rng.standard_normal((m, n))
+    rows = np.repeat(np.arange(m, dtype=np.int64), n)
+    cols = np.tile(np.arange(n, dtype=np.int64), m)
+    vals = M.ravel()
+    prm = dict(tau=500.0, delta=1.2, eps=1e-12, i_max=12, l=5, s=10, p_init=2,
+               adaptive_p=0, recycle=0, seed=5)
+    g = SVT(m, n, rows, cols, vals, prm)
+    for _ in range(12):
+        g.step()
+    res = g.result()
+    print("shifts", res["shifts"], "redone", res["redone"], "rank", res["rank"])
+    assert res["shifts"] > 0 and res["redone"] > 0
+    ex = svt_exact(m, n, rows, cols, vals, dict(prm, c=res["c"]))
+    Ug, sg, Vg = g.factors()
+    Xg = (Ug * sg) @ Vg.T
+    assert res["rank"] == ex.rank
+    assert np.linalg.norm(Xg - ex.dense()) / np.linalg.norm(ex.dense()) < 1e-9
+
+
 def test_empty_rows_and_columns_and_lifecycle():
     # a problem with empty rows and columns through whole steps, then the
     # status codes at convergence and at i_max
