@@ -12,6 +12,7 @@
 // The device work of these calls lives in solver_impl.hip.
 #include "solver.hpp"
 
+#include <chrono>
 #include <cmath>
 #include <cstring>
 
@@ -107,7 +108,19 @@ void Solver::mark() {
   MC_HIP(hipEventRecord(done_ev_, st_));
 }
 
-void Solver::wait() { MC_HIP(hipEventSynchronize(done_ev_)); }
+// Short waits (a step's read-backs, tens to hundreds of microseconds) poll
+// the event; a blocked wait can add the wake-up latency of the host thread
+// to every step.  Waits longer than 0.5 ms block.
+void Solver::wait() {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t e = hipEventQuery(done_ev_);
+    if (e == hipSuccess) return;
+    if (e != hipErrorNotReady) MC_HIP(e);
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(500)) break;
+  }
+  MC_HIP(hipEventSynchronize(done_ev_));
+}
 
 void Solver::fresh_svd(int k, int p, uint32_t step_id, uint32_t attempt) {
   fresh_launch(k, p, step_id, attempt, false);
