@@ -228,19 +228,62 @@ mc_status mc_svt_destroy(mc_svt_t h);
 const char* mc_svt_last_error(mc_svt_t h);
 
 /*
- * mc_rsvd_bki -- standalone truncated SVD of a sparse matrix by rSVD-BKI
- * (Alg. 5) with the same kernels: Omega = Gaussian(seed, step, attempt)
- * (n x (k+s)), p Krylov iterations, top-k triplets.
- *   A           (m x n) in COO (rows, cols, vals; nnz entries)
- *   k, s, p     rank, oversampling, power parameter ((p+1)(k+s) <= min(m,n))
- *   U (m x k), S (k, descending), V (n x k): host outputs, row-major.
- * Errors as for mc_svt_init, plus MC_EINVAL for k, s, p out of range.
+ * Standalone truncated SVD of a sparse matrix A (m x n), with the kernels of
+ * the solver: the randomized SVDs of Sec. III.
+ *
+ *   MC_RSVD_PI   rSVD-PI (Alg. 4): H = A Omega, then p power iterations
+ *                H <- A (A^T H), the block re-normalised after each one
+ *                (Cholesky QR instead of the pivoted LU: only the range
+ *                matters, Lemma 3), and eigSVD of B^T = A^T Q (Alg. 3) on the
+ *                last block alone.  Needs k + s <= min(m, n).
+ *   MC_RSVD_BKI  rSVD-BKI (Alg. 5): the p + 1 blocks H_0..H_p stacked and
+ *                orthonormalised together before eigSVD.  Needs
+ *                (p + 1)(k + s) <= min(m, n).
+ *
+ * Omega is the n x (k + s) Gaussian test matrix drawn from (seed, step,
+ * attempt) by the library's counter-based generator, so a call is
+ * reproducible and a caller holding the same generator can rebuild it.
+ * Outputs are the top k triplets, singular values descending:
+ *   U (m x k) and V (n x k), host, row-major; S (k) host.
+ * Errors as for mc_svt_init (A is checked the same way), plus MC_EINVAL for
+ * k < 1, s < 0, p < 0, an unknown method, or a basis wider than min(m, n).
  */
+typedef enum { MC_RSVD_PI = 4, MC_RSVD_BKI = 5 } mc_rsvd_method;
+
+typedef struct mc_rsvd* mc_rsvd_t;
+
+/* One call: copies A (COO: rows int64, cols int32, vals; nnz entries) to the
+ * device, runs one truncated SVD, returns U, S, V and frees everything. */
 mc_status mc_rsvd_bki(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
                       const int32_t* cols, const double* vals, int32_t k,
                       int32_t s, int32_t p, uint64_t seed, uint32_t step,
                       uint32_t attempt, int32_t precision, void* stream,
                       double* U, double* S, double* V);
+mc_status mc_rsvd_pi(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
+                     const int32_t* cols, const double* vals, int32_t k,
+                     int32_t s, int32_t p, uint64_t seed, uint32_t step,
+                     uint32_t attempt, int32_t precision, void* stream,
+                     double* U, double* S, double* V);
+
+/* A resident on the device for repeated calls (the oversampling s, the
+ * precision and the generator seed are fixed here).  The handle owns the
+ * device copy of A until mc_rsvd_destroy; its work is queued on `stream`. */
+mc_status mc_rsvd_init(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
+                       const int32_t* cols, const double* vals, int32_t s,
+                       int32_t precision, uint64_t seed, void* stream,
+                       mc_rsvd_t* out);
+/* One truncated SVD by `method` (mc_rsvd_method) with test matrix
+ * (seed, step, attempt).  S (k values) is required; U and V may be NULL, and
+ * are then not copied back.  Returns after S (and U, V) are on the host. */
+mc_status mc_rsvd_run(mc_rsvd_t h, int32_t method, int32_t k, int32_t p,
+                      uint32_t step, uint32_t attempt, double* U, double* S,
+                      double* V);
+/* Per-family kernel times of mc_rsvd_run calls, as mc_svt_profile and
+ * mc_svt_get_profile (calls run kernel by kernel while timing is on). */
+mc_status mc_rsvd_profile(mc_rsvd_t h, int32_t on);
+mc_status mc_rsvd_get_profile(mc_rsvd_t h, mc_prof_entry* out, int32_t cap);
+mc_status mc_rsvd_destroy(mc_rsvd_t h);
+const char* mc_rsvd_last_error(mc_rsvd_t h);   /* per thread when h is NULL */
 
 #ifdef __cplusplus
 }

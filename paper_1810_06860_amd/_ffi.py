@@ -95,6 +95,21 @@ _SIGNATURES = {
                               C.c_int32, C.c_int32, C.c_uint64, C.c_uint32,
                               C.c_uint32, C.c_int32, C.c_void_p,
                               _P(C.c_double), _P(C.c_double), _P(C.c_double)]),
+    "mc_rsvd_pi": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _P(C.c_int64),
+                             _P(C.c_int32), _P(C.c_double), C.c_int32,
+                             C.c_int32, C.c_int32, C.c_uint64, C.c_uint32,
+                             C.c_uint32, C.c_int32, C.c_void_p,
+                             _P(C.c_double), _P(C.c_double), _P(C.c_double)]),
+    "mc_rsvd_init": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _P(C.c_int64),
+                               _P(C.c_int32), _P(C.c_double), C.c_int32, C.c_int32,
+                               C.c_uint64, C.c_void_p, _P(C.c_void_p)]),
+    "mc_rsvd_run": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                              C.c_uint32, C.c_uint32, _P(C.c_double),
+                              _P(C.c_double), _P(C.c_double)]),
+    "mc_rsvd_profile": (C.c_int, [C.c_void_p, C.c_int32]),
+    "mc_rsvd_get_profile": (C.c_int, [C.c_void_p, _P(ProfEntry), C.c_int32]),
+    "mc_rsvd_destroy": (C.c_int, [C.c_void_p]),
+    "mc_rsvd_last_error": (C.c_char_p, [C.c_void_p]),
     # include/mcsvt_kernels.h
     "mc_k_gaussian": (C.c_int, [C.c_int64, C.c_int64, C.c_uint64, C.c_uint32,
                                 C.c_uint32, C.c_void_p, _P(C.c_double)]),

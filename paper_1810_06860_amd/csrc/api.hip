@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <functional>
 #include <thread>
+#include <utility>
 #include <vector>
 #include <cstring>
 #include <memory>
@@ -15,6 +16,11 @@
 #include "solver.hpp"
 
 struct mc_svt {
+  std::unique_ptr<mcsvt::Solver> solver;
+  std::string err;
+};
+
+struct mc_rsvd {
   std::unique_ptr<mcsvt::Solver> solver;
   std::string err;
 };
@@ -83,8 +89,10 @@ void mcsvt_set_thread_error(const char* msg) { mcsvt::t_err = msg ? msg : ""; }
 
 namespace {
 
-template <class F>
-mc_status guarded(mc_svt_t h, F&& f) {
+// runs f; a failure's message goes to the handle (H has a std::string err),
+// or to the calling thread when h is NULL
+template <class H, class F>
+mc_status guarded_on(H* h, F&& f) {
   try {
     f();
     return MC_OK;
@@ -97,6 +105,29 @@ mc_status guarded(mc_svt_t h, F&& f) {
   } catch (const std::exception& e) {
     (h ? h->err : mcsvt::t_err) = e.what();
     return MC_EDEVICE;
+  }
+}
+
+template <class F>
+mc_status guarded(mc_svt_t h, F&& f) {
+  return guarded_on(h, std::forward<F>(f));
+}
+
+void set_profile(mcsvt::Solver& s, int32_t on) {
+  auto& p = s.prof;
+  p.collect();
+  if (on) p.reset();
+  p.on = on != 0;
+}
+
+void get_profile(mcsvt::Solver& s, mc_prof_entry* out) {
+  auto& p = s.prof;
+  p.collect();
+  for (int f = 0; f < MC_PROF_FAMILIES; ++f) {
+    out[f].launches = p.count[f];
+    out[f].ms = p.ms[f];
+    out[f].bytes = p.bytes[f];
+    out[f].flops = p.flops[f];
   }
 }
 
@@ -432,12 +463,7 @@ mc_status mc_svt_profile(mc_svt_t h, int32_t on) {
     mcsvt::t_err = "NULL handle";
     return MC_EINVAL;
   }
-  return guarded(h, [&] {
-    auto& p = h->solver->prof;
-    p.collect();
-    if (on) p.reset();
-    p.on = on != 0;
-  });
+  return guarded(h, [&] { set_profile(*h->solver, on); });
 }
 
 mc_status mc_svt_get_profile(mc_svt_t h, mc_prof_entry* out, int32_t cap) {
@@ -445,16 +471,7 @@ mc_status mc_svt_get_profile(mc_svt_t h, mc_prof_entry* out, int32_t cap) {
     mcsvt::t_err = "bad arguments";
     return MC_EINVAL;
   }
-  return guarded(h, [&] {
-    auto& p = h->solver->prof;
-    p.collect();
-    for (int f = 0; f < MC_PROF_FAMILIES; ++f) {
-      out[f].launches = p.count[f];
-      out[f].ms = p.ms[f];
-      out[f].bytes = p.bytes[f];
-      out[f].flops = p.flops[f];
-    }
-  });
+  return guarded(h, [&] { get_profile(*h->solver, out); });
 }
 
 mc_status mc_svt_destroy(mc_svt_t h) {
@@ -469,35 +486,148 @@ const char* mc_svt_last_error(mc_svt_t h) {
   return mcsvt::t_err.c_str();
 }
 
+namespace {
+
+// a solver holding A = (rows, cols, vals) unscaled, for truncated SVDs
+std::unique_ptr<mcsvt::Solver> make_rsvd_solver(int64_t m, int64_t n, int64_t nnz,
+                                                const int64_t* rows, const int32_t* cols,
+                                                const double* vals, int32_t s,
+                                                int32_t precision, uint64_t seed,
+                                                hipStream_t stream) {
+  MC_REQUIRE(rows && cols && vals, mcsvt::kEINVAL, "NULL argument");
+  check_sizes(m, n, nnz);
+  MC_REQUIRE(s >= 0, mcsvt::kEINVAL, "need s >= 0");
+  MC_REQUIRE(precision >= MC_FP64 && precision <= MC_BF16_EIG64, mcsvt::kEINVAL,
+             "unknown precision");
+  for (int64_t e = 0; e < nnz; ++e)
+    MC_REQUIRE(std::isfinite(vals[e]), mcsvt::kEINVAL, "non-finite value");
+  mc_svt_params prm;
+  mc_svt_default_params(&prm);
+  prm.s = s;
+  prm.seed = seed;
+  prm.precision = (mc_precision)precision;
+  auto holder = mcsvt::make_solver(m, n, nnz, prm, stream);
+  const int st = holder->init(rows, cols, vals, false);
+  if (st == mcsvt::kERANGE) throw mcsvt::Error(st, "index out of range");
+  if (st == mcsvt::kEDUP) throw mcsvt::Error(st, "duplicate cell");
+  if (st != mcsvt::kOK) throw mcsvt::Error(st, "invalid input");
+  return holder;
+}
+
+void check_rsvd_shape(int64_t m, int64_t n, int32_t method, int32_t k, int32_t s,
+                      int32_t p) {
+  MC_REQUIRE(method == MC_RSVD_PI || method == MC_RSVD_BKI, mcsvt::kEINVAL,
+             "unknown method (MC_RSVD_PI or MC_RSVD_BKI)");
+  MC_REQUIRE(k >= 1 && s >= 0 && p >= 0, mcsvt::kEINVAL, "need k >= 1, s >= 0, p >= 0");
+  const int64_t mn = std::min(m, n);
+  if (method == MC_RSVD_BKI)
+    MC_REQUIRE((int64_t)(p + 1) * (k + s) <= mn, mcsvt::kEINVAL,
+               "(p+1)(k+s) must not exceed min(m, n)");
+  else
+    MC_REQUIRE((int64_t)k + s <= mn, mcsvt::kEINVAL, "k+s must not exceed min(m, n)");
+}
+
+void run_rsvd(mcsvt::Solver& solver, int32_t method, int32_t k, int32_t p,
+              uint32_t step, uint32_t attempt, double* U, double* S, double* V) {
+  if (method == MC_RSVD_PI)
+    solver.rsvd_pi(k, p, step, attempt);
+  else
+    solver.rsvd(k, p, step, attempt);
+  solver.get_rsvd(U, S, V);
+}
+
+mc_status one_shot(int32_t method, int64_t m, int64_t n, int64_t nnz,
+                   const int64_t* rows, const int32_t* cols, const double* vals,
+                   int32_t k, int32_t s, int32_t p, uint64_t seed, uint32_t step,
+                   uint32_t attempt, int32_t precision, void* stream, double* U,
+                   double* S, double* V) {
+  return guarded(nullptr, [&] {
+    MC_REQUIRE(U && S && V, mcsvt::kEINVAL, "NULL argument");
+    check_sizes(m, n, nnz);
+    check_rsvd_shape(m, n, method, k, s, p);
+    auto solver = make_rsvd_solver(m, n, nnz, rows, cols, vals, s, precision, seed,
+                                   (hipStream_t)stream);
+    run_rsvd(*solver, method, k, p, step, attempt, U, S, V);
+  });
+}
+
+}  // namespace
+
 mc_status mc_rsvd_bki(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
                       const int32_t* cols, const double* vals, int32_t k,
                       int32_t s, int32_t p, uint64_t seed, uint32_t step,
                       uint32_t attempt, int32_t precision, void* stream,
                       double* U, double* S, double* V) {
+  return one_shot(MC_RSVD_BKI, m, n, nnz, rows, cols, vals, k, s, p, seed, step,
+                  attempt, precision, stream, U, S, V);
+}
+
+mc_status mc_rsvd_pi(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
+                     const int32_t* cols, const double* vals, int32_t k,
+                     int32_t s, int32_t p, uint64_t seed, uint32_t step,
+                     uint32_t attempt, int32_t precision, void* stream,
+                     double* U, double* S, double* V) {
+  return one_shot(MC_RSVD_PI, m, n, nnz, rows, cols, vals, k, s, p, seed, step,
+                  attempt, precision, stream, U, S, V);
+}
+
+mc_status mc_rsvd_init(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
+                       const int32_t* cols, const double* vals, int32_t s,
+                       int32_t precision, uint64_t seed, void* stream,
+                       mc_rsvd_t* out) {
+  if (!out) {
+    mcsvt::t_err = "NULL handle pointer";
+    return MC_EINVAL;
+  }
+  *out = nullptr;
   return guarded(nullptr, [&] {
-    MC_REQUIRE(rows && cols && vals && U && S && V, mcsvt::kEINVAL, "NULL argument");
-    check_sizes(m, n, nnz);
-    const int64_t mn = std::min(m, n);
-    MC_REQUIRE(k >= 1 && s >= 0 && p >= 0, mcsvt::kEINVAL, "need k >= 1, s >= 0, p >= 0");
-    MC_REQUIRE((int64_t)(p + 1) * (k + s) <= mn, mcsvt::kEINVAL,
-               "(p+1)(k+s) must not exceed min(m, n)");
-    for (int64_t e = 0; e < nnz; ++e)
-      MC_REQUIRE(std::isfinite(vals[e]), mcsvt::kEINVAL, "non-finite value");
-    mc_svt_params prm;
-    mc_svt_default_params(&prm);
-    prm.s = s;
-    prm.seed = seed;
-    prm.precision = precision;
-    prm.p_init = prm.p_min = prm.p_max = p;
-    auto holder = mcsvt::make_solver(m, n, nnz, prm, (hipStream_t)stream);
-    mcsvt::Solver& solver = *holder;
-    const int st = solver.init(rows, cols, vals, false);
-    if (st == mcsvt::kERANGE) throw mcsvt::Error(st, "index out of range");
-    if (st == mcsvt::kEDUP) throw mcsvt::Error(st, "duplicate cell");
-    if (st != mcsvt::kOK) throw mcsvt::Error(st, "invalid input");
-    solver.rsvd(k, p, step, attempt);
-    solver.get_rsvd(U, S, V);
+    auto solver = make_rsvd_solver(m, n, nnz, rows, cols, vals, s, precision, seed,
+                                   (hipStream_t)stream);
+    auto h = std::make_unique<mc_rsvd>();
+    h->solver = std::move(solver);
+    *out = h.release();
   });
+}
+
+mc_status mc_rsvd_run(mc_rsvd_t h, int32_t method, int32_t k, int32_t p, uint32_t step,
+                      uint32_t attempt, double* U, double* S, double* V) {
+  if (!h || !h->solver || !S) {
+    mcsvt::t_err = "NULL handle or S";
+    return MC_EINVAL;
+  }
+  return guarded_on(h, [&] {
+    mcsvt::Solver& solver = *h->solver;
+    check_rsvd_shape(solver.m(), solver.n(), method, k, solver.params().s, p);
+    run_rsvd(solver, method, k, p, step, attempt, U, S, V);
+  });
+}
+
+mc_status mc_rsvd_profile(mc_rsvd_t h, int32_t on) {
+  if (!h || !h->solver) {
+    mcsvt::t_err = "NULL handle";
+    return MC_EINVAL;
+  }
+  return guarded_on(h, [&] { set_profile(*h->solver, on); });
+}
+
+mc_status mc_rsvd_get_profile(mc_rsvd_t h, mc_prof_entry* out, int32_t cap) {
+  if (!h || !h->solver || !out || cap < MC_PROF_FAMILIES) {
+    mcsvt::t_err = "bad arguments";
+    return MC_EINVAL;
+  }
+  return guarded_on(h, [&] { get_profile(*h->solver, out); });
+}
+
+mc_status mc_rsvd_destroy(mc_rsvd_t h) {
+  if (!h) return MC_OK;
+  mc_status st = guarded(nullptr, [&] { h->solver.reset(); });
+  delete h;
+  return st;
+}
+
+const char* mc_rsvd_last_error(mc_rsvd_t h) {
+  if (h) return h->err.c_str();
+  return mcsvt::t_err.c_str();
 }
 
 }  // extern "C"

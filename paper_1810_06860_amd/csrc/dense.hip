@@ -15,6 +15,7 @@
 //   with a diagonal shift when a pivot breaks down (shifted Cholesky QR).
 #include <type_traits>
 
+#include "chol_regs.hpp"
 #include "kernels.hpp"
 
 namespace mcsvt {
@@ -22,25 +23,29 @@ namespace mcsvt {
 namespace {
 
 constexpr int GT = 32;   // gram tile
+constexpr int GramTailThreads = 256;   // workgroup size of the fused Gram
 
-// 1/x from the hardware estimate and two Newton steps (about 1 ulp), for the
-// serial chains of the factorisation; x is a positive normal number there
-__device__ __forceinline__ double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = r * (2.0 - x * r);
-  return r * (2.0 - x * r);
-}
-
-__device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
-                               double* __restrict__ Rinv, int64_t ldr, double* R,
-                               double* X, int64_t nrows, int* __restrict__ shifted,
-                               int* __restrict__ flag) {
+// G (b x b, SPD; its upper triangle is read) = R^T R and Rinv = R^{-1}
+// (upper triangular, zeros below), in one workgroup.  Gaussian elimination
+// without pivoting on [G | I], in place in A (b x b): after step j the rows
+// i > j hold the Schur complement on and above the diagonal and, below it,
+// the row operations applied so far to I (L^{-1}, unit diagonal implied), so
+// no separate triangular inversion follows.  With G = L D L^T, R = D^{1/2} L^T
+// and R^{-1} = L^{-T} D^{-1/2}: Rinv[a][c] = Linv[c][a] / sqrt(d_c), a <= c.
+// One barrier per column.  A pivot that is not positive or falls below 1e-13
+// of its original diagonal retries with G + shift I (shifted Cholesky QR).
+// aux holds 2 b doubles.  NC = ceil(b / 32) column strides of a lane (0: any b).
+template <int NC>
+__device__ __forceinline__ void chol_inv_block_nc(int b, const double* __restrict__ G, int64_t ldg,
+                                  double* __restrict__ Rinv, int64_t ldr, double* A,
+                                  double* aux, int64_t nrows, int* __restrict__ shifted,
+                                  int* __restrict__ flag) {
   __shared__ double trace;
   const int tid = threadIdx.x;
   const int tx = tid & 31, ty = tid >> 5, ny = (int)(blockDim.x >> 5);
-  // the diagonal of G in LDS (X is free until the inverse): the breakdown
-  // test reads it every column, and global reads there would be serial
-  double* gd = X;
+  // the diagonal of G in LDS: the breakdown test reads it every column
+  double* gd = aux;
+  double* sc = aux + b;
   for (int i = tid; i < b; i += blockDim.x) gd[i] = G[(int64_t)i * ldg + i];
   __syncthreads();
   if (tid == 0) {
@@ -51,32 +56,64 @@ __device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
   __syncthreads();
   const double u = 1.1102230246251565e-16;
   double shift = 0.0;
+  // a lane's columns, clamped into the row so every load is in range
+  // (NC = 0: any b, plain loops)
+  int cc[NC > 0 ? NC : 1];
+#pragma unroll
+  for (int m = 0; m < NC; ++m) cc[m] = min(tx + 32 * m, b - 1);
   for (int attempt = 0; attempt < 6; ++attempt) {
-    // G is stored full; the lower triangle is zeroed by a factor so the
-    // loads need no branch
+    // the upper triangle of G (lower one zeroed by a factor: no branch
+    // around the load)
     for (int i = ty; i < b; i += ny)
       for (int c = tx; c < b; c += 32) {
         double v = G[(int64_t)i * ldg + c] * (i <= c ? 1.0 : 0.0);
         if (i == c) v += shift;
-        R[i * b + c] = v;
+        A[i * b + c] = v;
       }
     __syncthreads();
     bool failed = false;
     for (int j = 0; j < b; ++j) {
       // a pivot below 1e-13 of its original diagonal means kappa(H) of
       // order 1e6 or worse: Cholesky QR would lose all orthogonality
-      const double d = R[j * b + j];
+      const double d = A[j * b + j];
       const double gjj = gd[j] + shift;
       if (!(d > 1e-13 * gjj) || !(d > 1e-300)) {
         failed = true;                               // the same for every thread
         break;
       }
       const double rd = rcp_nr(d);
-      // rows i > j over thread rows, columns c >= i over the 32 lanes of a
-      // thread row (no index division in the loop)
-      for (int i = j + 1 + ty; i < b; i += ny) {
-        const double f = R[j * b + i];
-        for (int c = i + tx; c < b; c += 32) R[i * b + c] -= f * R[j * b + c] * rd;
+      // row j is only read in this step: its Schur part (c >= j) and its
+      // L^{-1} part (c < j)
+      if constexpr (NC > 0) {
+        double rj[NC];
+#pragma unroll
+        for (int m = 0; m < NC; ++m) rj[m] = A[j * b + cc[m]];
+        for (int i = j + 1 + ty; i < b; i += ny) {
+          const double l = A[j * b + i] * rd;        // multiplier of row i
+          double v[NC];
+#pragma unroll
+          for (int m = 0; m < NC; ++m) v[m] = A[i * b + cc[m]];
+#pragma unroll
+          for (int m = 0; m < NC; ++m) {
+            const int c = tx + 32 * m;
+            if (c < b) {
+              if (c >= i || c < j)
+                A[i * b + c] = v[m] - l * rj[m];
+              else if (c == j)
+                A[i * b + c] = -l;                   // L^{-1}[j][j] = 1
+            }
+          }
+        }
+      } else {
+        for (int i = j + 1 + ty; i < b; i += ny) {
+          const double l = A[j * b + i] * rd;
+          for (int c = tx; c < b; c += 32) {
+            if (c >= i || c < j)
+              A[i * b + c] -= l * A[j * b + c];
+            else if (c == j)
+              A[i * b + c] = -l;
+          }
+        }
       }
       __syncthreads();
     }
@@ -90,44 +127,29 @@ __device__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
     if (tid == 0 && flag) *flag = 1;
     __syncthreads();
   }
-  // scale: R_jj = sqrt(d_j), R_jc = (R_jj R_jc) / R_jj; the square roots
-  // go through X (free until the inverse)
-  for (int i = tid; i < b; i += blockDim.x) X[i] = sqrt(R[i * b + i]);
+  for (int i = tid; i < b; i += blockDim.x) sc[i] = 1.0 / sqrt(A[i * b + i]);
   __syncthreads();
-  for (int i = ty; i < b; i += ny) {
-    const double si = X[i];
-    for (int c = i + 1 + tx; c < b; c += 32) R[i * b + c] = R[i * b + c] / si;
-  }
-  __syncthreads();
-  __shared__ double invd[kCholLdsMax];
-  for (int i = tid; i < b; i += blockDim.x) {
-    R[i * b + i] = X[i];
-    if (i < kCholLdsMax) invd[i] = rcp_nr(X[i]);
-  }
-  __syncthreads();
-  // column c of R^{-1} by back substitution (thread per column), in LDS; the
-  // dot products run on four partial sums
-  for (int c = tid; c < b; c += blockDim.x) {
-    for (int i = b - 1; i > c; --i) X[i * b + c] = 0.0;
-    const bool fast = b <= kCholLdsMax;              // reciprocals of the diagonal in LDS
-    X[c * b + c] = fast ? invd[c] : 1.0 / R[c * b + c];
-    for (int i = c - 1; i >= 0; --i) {
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      int t = i + 1;
-      for (; t + 3 <= c; t += 4) {
-        a0 += R[i * b + t] * X[t * b + c];
-        a1 += R[i * b + t + 1] * X[(t + 1) * b + c];
-        a2 += R[i * b + t + 2] * X[(t + 2) * b + c];
-        a3 += R[i * b + t + 3] * X[(t + 3) * b + c];
-      }
-      for (; t <= c; ++t) a0 += R[i * b + t] * X[t * b + c];
-      const double dot = (a0 + a1) + (a2 + a3);
-      X[i * b + c] = fast ? -dot * invd[i] : -dot / R[i * b + i];
+  for (int a = ty; a < b; a += ny)
+    for (int c = tx; c < b; c += 32) {
+      const double lv = A[c * b + min(a, c)] * (a < c ? 1.0 : 0.0) + (a == c ? 1.0 : 0.0);
+      Rinv[(int64_t)a * ldr + c] = lv * sc[c];
     }
-  }
-  __syncthreads();
-  for (int i = ty; i < b; i += ny)
-    for (int c = tx; c < b; c += 32) Rinv[(int64_t)i * ldr + c] = X[i * b + c];
+}
+
+__device__ __forceinline__ void chol_inv_block(int b, const double* __restrict__ G, int64_t ldg,
+                               double* __restrict__ Rinv, int64_t ldr, double* A,
+                               double* aux, int64_t nrows, int* __restrict__ shifted,
+                               int* __restrict__ flag) {
+  if (b <= 32)
+    chol_inv_block_nc<1>(b, G, ldg, Rinv, ldr, A, aux, nrows, shifted, flag);
+  else if (b <= 64)
+    chol_inv_block_nc<2>(b, G, ldg, Rinv, ldr, A, aux, nrows, shifted, flag);
+  else if (b <= 96)
+    chol_inv_block_nc<3>(b, G, ldg, Rinv, ldr, A, aux, nrows, shifted, flag);
+  else if (b <= 128)
+    chol_inv_block_nc<4>(b, G, ldg, Rinv, ldr, A, aux, nrows, shifted, flag);
+  else
+    chol_inv_block_nc<0>(b, G, ldg, Rinv, ldr, A, aux, nrows, shifted, flag);
 }
 
 // Fused completion (mode 1: sum the partials into C; mode 2: also Cholesky +
@@ -147,7 +169,7 @@ struct GramTail {
 };
 
 template <class IT, class AT>
-__global__ __launch_bounds__(256) void gram_kernel(
+__global__ __launch_bounds__(GramTailThreads) void gram_kernel(
     int64_t N, int p, int q, const IT* __restrict__ A, int64_t lda,
     const IT* __restrict__ B, int64_t ldb, AT* __restrict__ part,
     int64_t rows_per_split, int sym, const int* __restrict__ gate, GramTail tail) {
@@ -233,8 +255,29 @@ __global__ __launch_bounds__(256) void gram_kernel(
   __syncthreads();
   if (tail.mode == 2) {
     extern __shared__ double lds[];
-    chol_inv_block(p, tail.C, tail.ldc, tail.Rinv, tail.ldr, lds, lds + (size_t)p * p,
-                   tail.nrows, tail.shifted, tail.flag);
+    // 256 threads: 8 rows of 32 lanes; in registers up to p = 64, else the
+    // elimination array in LDS: A (p x p), aux (2 p)
+    static_assert(GramTailThreads == 256, "register tiles assume 8 thread rows");
+    const double* Cc = tail.C;
+    const int64_t lc = tail.ldc;
+    if (p <= 8)
+      chol_inv_regs<1, 1>(p, Cc, lc, tail.Rinv, tail.ldr, lds, tail.nrows, tail.shifted,
+                          tail.flag, false);
+    else if (p <= 16)
+      chol_inv_regs<2, 1>(p, Cc, lc, tail.Rinv, tail.ldr, lds, tail.nrows, tail.shifted,
+                          tail.flag, false);
+    else if (p <= 24)
+      chol_inv_regs<3, 1>(p, Cc, lc, tail.Rinv, tail.ldr, lds, tail.nrows, tail.shifted,
+                          tail.flag, false);
+    else if (p <= 32)
+      chol_inv_regs<4, 1>(p, Cc, lc, tail.Rinv, tail.ldr, lds, tail.nrows, tail.shifted,
+                          tail.flag, false);
+    else if (p <= 64)
+      chol_inv_regs<8, 2>(p, Cc, lc, tail.Rinv, tail.ldr, lds, tail.nrows, tail.shifted,
+                          tail.flag, false);
+    else
+      chol_inv_block(p, Cc, lc, tail.Rinv, tail.ldr, lds, lds + (size_t)p * p, tail.nrows,
+                     tail.shifted, tail.flag);
   }
   if (threadIdx.x == 0) *tail.counter = 0;
 }
@@ -498,10 +541,9 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(
 
 // One workgroup: G (b x b, SPD) = R^T R, Rinv = R^-1 (upper triangular).
 // Breakdown (a pivot that is not positive or below 1e-13 of its original
-// diagonal) retries with G + shift I.  Right-looking on the upper triangle
-// without scaling (after step j row j holds R_jj^2 and R_jj R_jc), one
-// barrier per column; R^{-1} is formed in LDS, one thread per column, and
-// written out at the end.
+// diagonal) retries with G + shift I.  Elimination on [G | I] with one
+// barrier per column: the matrix in registers up to b = 128, else in LDS
+// (or, past the LDS size, in `work`).
 __global__ __launch_bounds__(1024) void chol_inv_kernel(
     int b, const double* __restrict__ G, int64_t ldg, double* __restrict__ Rinv,
     int64_t ldr, double* __restrict__ work, int64_t nrows,
@@ -509,9 +551,20 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(
   if (gate && *gate == 0) return;
   extern __shared__ double lds[];
   const bool in_lds = b <= kCholLdsMax;
-  double* R = in_lds ? lds : work;                   // b x b, row-major
-  double* X = in_lds ? lds + (size_t)b * b : work + (size_t)b * b;   // R^{-1}
-  chol_inv_block(b, G, ldg, Rinv, ldr, R, X, nrows, shifted, flag);
+  // 1024 threads: 32 rows of 32 lanes; the matrix in registers up to b = 128
+  if (b <= 32)
+    chol_inv_regs<1, 1>(b, G, ldg, Rinv, ldr, lds, nrows, shifted, flag, false);
+  else if (b <= 64)
+    chol_inv_regs<2, 2>(b, G, ldg, Rinv, ldr, lds, nrows, shifted, flag, false);
+  else if (b <= 96)
+    chol_inv_regs<3, 3>(b, G, ldg, Rinv, ldr, lds, nrows, shifted, flag, false);
+  else if (b <= 128)
+    chol_inv_regs<4, 4>(b, G, ldg, Rinv, ldr, lds, nrows, shifted, flag, false);
+  else {
+    double* A = in_lds ? lds : work;                 // b x b, row-major
+    double* aux = A + (size_t)b * b;                 // 2 b
+    chol_inv_block(b, G, ldg, Rinv, ldr, A, aux, nrows, shifted, flag);
+  }
 }
 
 __global__ void set_int_kernel(int* p, int v) { *p = v; }
@@ -668,15 +721,15 @@ void launch_gram_fused(int64_t N, int p, int q, const IT* A, int64_t lda, const 
     for (const void* f : {(const void*)gram_kernel<double, double>,
                           (const void*)gram_kernel<float, float>})
       if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              2 * kCholLdsMax * kCholLdsMax * (int)sizeof(double)) !=
+                              kCholLdsDoubles * (int)sizeof(double)) !=
           hipSuccess)
         (void)hipGetLastError();
     return true;
   }();
   (void)attr;
-  const size_t lds = chol ? 2 * (size_t)p * p * sizeof(double) : 0;
+  const size_t lds = chol ? ((size_t)p * p + 2 * p) * sizeof(double) : 0;
   dim3 grid((unsigned)tp, (unsigned)tq, (unsigned)splits);
-  hipLaunchKernelGGL((gram_kernel<IT, AT>), grid, dim3(256), lds, st, N, p, q, A, lda, B,
+  hipLaunchKernelGGL((gram_kernel<IT, AT>), grid, dim3(GramTailThreads), lds, st, N, p, q, A, lda, B,
                      ldb, part, rps, sym, gate, t);
   MC_CHECK_LAUNCH();
 }
@@ -737,16 +790,16 @@ void launch_chol_inv(int b, const double* G, int64_t ldg, double* Rinv,
                      int64_t ldr, double* work, int64_t nrows, int* shifted,
                      hipStream_t st, int* flag, const int* gate) {
   static const bool attr = [] {
-    // R and R^{-1} for b up to kCholLdsMax exceed the default 64 KB
+    // the elimination array for b up to kCholLdsMax exceeds the default 64 KB
     if (hipFuncSetAttribute((const void*)chol_inv_kernel,
                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                            2 * kCholLdsMax * kCholLdsMax * (int)sizeof(double)) !=
+                            kCholLdsDoubles * (int)sizeof(double)) !=
         hipSuccess)
       (void)hipGetLastError();
     return true;
   }();
   (void)attr;
-  const size_t lds = (b <= kCholLdsMax) ? 2 * (size_t)b * b * sizeof(double) : 0;
+  const size_t lds = (b <= kCholLdsMax) ? ((size_t)b * b + 2 * b) * sizeof(double) : 0;
   hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), lds, st, b, G, ldg,
                      Rinv, ldr, work, nrows, shifted, flag, gate);
   MC_CHECK_LAUNCH();

@@ -109,9 +109,12 @@ void launch_panel_gemm(int64_t N, int p, int q, const XT* X, int64_t ldx,
                        int64_t ldc0, OT* C, int64_t ldc, hipStream_t st,
                        const int* gate = nullptr);
 
-constexpr int kCholLdsMax = 90;   // R and R^-1 (2 b*b doubles) in LDS up to this b
+// The Cholesky factorisation and R^-1 of a b x b Gram matrix work in
+// b*b + 2b doubles: in LDS up to this b (133 KB at b = 128)
+constexpr int kCholLdsMax = 128;
+constexpr int kCholLdsDoubles = kCholLdsMax * kCholLdsMax + 2 * kCholLdsMax;
 // flag (optional) is set to 1 when a diagonal shift was needed
-// work: 2 b*b doubles, used when b > kCholLdsMax
+// work: b*b + 2b doubles (global), used when b > kCholLdsMax
 void launch_chol_inv(int b, const double* G, int64_t ldg, double* Rinv,
                      int64_t ldr, double* work, int64_t nrows, int* shifted,
                      hipStream_t st, int* flag = nullptr,

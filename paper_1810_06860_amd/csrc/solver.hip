@@ -100,7 +100,10 @@ Solver::~Solver() {
 void Solver::widths(int k, int p, int& b, int& p_eff) const {
   const int64_t mn = std::min(m_, n_);
   b = (int)std::min<int64_t>((int64_t)k + prm_.s, mn);
-  p_eff = (int)std::max<int64_t>(0, std::min<int64_t>(p, mn / b - 1));
+  // rSVD-BKI stacks p + 1 blocks and needs (p + 1) b <= min(m, n); rSVD-PI
+  // keeps one block whatever p is
+  p_eff = power_ ? std::max(0, p)
+                 : (int)std::max<int64_t>(0, std::min<int64_t>(p, mn / b - 1));
 }
 
 void Solver::mark() {

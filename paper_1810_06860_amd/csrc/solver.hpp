@@ -74,6 +74,17 @@ class Solver {
   void rsvd(int k, int p, uint32_t step_id, uint32_t attempt) {
     fresh_svd(k, p, step_id, attempt);
   }
+  // truncated SVD by rSVD-PI (Alg. 4): the same test matrix, p power
+  // iterations with the block re-normalised after each one, and the
+  // Rayleigh-Ritz step on the last block alone (width k + s)
+  void rsvd_pi(int k, int p, uint32_t step_id, uint32_t attempt) {
+    struct Reset {
+      bool& f;
+      ~Reset() { f = false; }
+    } reset{power_};
+    power_ = true;
+    fresh_svd(k, p, step_id, attempt);
+  }
 
   // results
   virtual void get_factors(double* U, double* sig, double* V, int64_t ldu,
@@ -132,6 +143,7 @@ class Solver {
   void mark();                  // record the completion event on the stream
   void wait();                  // wait for it
 
+  bool power_ = false;          // fresh calls run rSVD-PI instead of rSVD-BKI
   enum Phase { kIdle, kSvd, kSddmm };
   Phase phase_ = kIdle;
   StepInfo cur_;

@@ -448,6 +448,17 @@ void SolverT<P, VT, AT>::fresh_body(int k, int b, int p_eff, int Lw, bool guarde
   prof.end(ls());
   spmm_y(omega_.p, b, H1_.p, b, b);                          // H_0 = Y Omega
   orth_block(0, b, Lw, guarded);
+  if (power_) {
+    // rSVD-PI (Alg. 4): each power iteration replaces the block; the
+    // normalisation between iterations only has to keep its range (Lemma 3)
+    for (int j = 1; j <= p_eff; ++j) {
+      spmm_yt(Qw_.p, Lw, Z_.p, b, b);                        // Y^T Q
+      spmm_y(Z_.p, b, H1_.p, b, b);                          // Y Y^T Q
+      orth_block(0, b, Lw, guarded);
+    }
+    eig_body(Qw_.p, Lw, Lw, k);
+    return;
+  }
   for (int j = 1; j <= p_eff; ++j) {
     spmm_yt(Qw_.p + (int64_t)(j - 1) * b, Lw, Z_.p, b, b);   // Y^T Q_{j-1}
     spmm_y(Z_.p, b, H1_.p, b, b);                            // H_j
@@ -499,15 +510,15 @@ void SolverT<P, VT, AT>::fresh_launch(int k, int p, uint32_t step_id, uint32_t a
                                       bool guarded) {
   int b, p_eff;
   widths(k, p, b, p_eff);
-  const int Lw = (p_eff + 1) * b;
+  const int Lw = power_ ? b : (p_eff + 1) * b;
   ensure(b, Lw, k);
   Qw_.reserve(m_ * (int64_t)cap_L_, st_);
   hctr_[0] = step_id;
   hctr_[1] = attempt;
   MC_HIP(hipMemcpyAsync(ctr_.p, hctr_, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, st_));
   if (graphs_ok(Lw, k)) {
-    const GraphKey key{1, k, b, p_eff, Lw, (int64_t)gen_, (int64_t)(intptr_t)Qw_.p,
-                       guarded ? 1 : 0};
+    const GraphKey key{power_ ? 4 : 1, k, b, p_eff, Lw, (int64_t)gen_,
+                       (int64_t)(intptr_t)Qw_.p, guarded ? 1 : 0};
     run_graph(key, [&] { fresh_body(k, b, p_eff, Lw, guarded); });
   } else {
     fresh_body(k, b, p_eff, Lw, guarded);
@@ -627,8 +638,8 @@ void SolverT<P, VT, AT>::get_factors(double* U, double* sig, double* V,
 template <class P, class VT, class AT>
 void SolverT<P, VT, AT>::get_rsvd(double* U, double* S, double* V) {
   const int k = k_last_;
-  copy_cols_to_host(U, k, U_.p, k, k, m_, st_);
-  copy_cols_to_host(V, k, V_.p, k, k, n_, st_);
+  if (U) copy_cols_to_host(U, k, U_.p, k, k, m_, st_);
+  if (V) copy_cols_to_host(V, k, V_.p, k, k, n_, st_);
   for (int j = 0; j < k; ++j) S[j] = lastS_[j];
 }
 

@@ -18,6 +18,7 @@
 //      returned eigenvalues.
 //   4. Back-transformation W = H_0 H_1 ... H_{L-3} Z, 16 lanes per vector
 //      with the vector held in registers.
+#include "chol_regs.hpp"
 #include "kernels.hpp"
 
 #include <cfloat>
@@ -864,6 +865,32 @@ __global__ __launch_bounds__(256) void chol_rinv_kernel(int k, const double* __r
   }
 }
 
+// The same for k <= 128 with the matrix in registers (1024 threads, one
+// barrier per column; pivots clamped below at 1e-28 as above).
+template <int N>
+__global__ __launch_bounds__(1024) void chol_rinv_regs_kernel(int k,
+                                                             const double* __restrict__ Cg,
+                                                             double* __restrict__ Rinv) {
+  extern __shared__ double smem[];
+  chol_inv_regs<N, N>(k, Cg, k, Rinv, k, smem, 0, nullptr, nullptr, true);
+}
+
+void launch_chol_rinv(int k, const double* C, double* Ri, hipStream_t st) {
+  const size_t lds3 = sizeof(double) * 3 * (size_t)k;
+  if (k <= 32)
+    hipLaunchKernelGGL(chol_rinv_regs_kernel<1>, dim3(1), dim3(1024), lds3, st, k, C, Ri);
+  else if (k <= 64)
+    hipLaunchKernelGGL(chol_rinv_regs_kernel<2>, dim3(1), dim3(1024), lds3, st, k, C, Ri);
+  else if (k <= 96)
+    hipLaunchKernelGGL(chol_rinv_regs_kernel<3>, dim3(1), dim3(1024), lds3, st, k, C, Ri);
+  else if (k <= 128)
+    hipLaunchKernelGGL(chol_rinv_regs_kernel<4>, dim3(1), dim3(1024), lds3, st, k, C, Ri);
+  else
+    hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(256),
+                       sizeof(double) * ((size_t)k * k + k), st, k, C, Ri);
+  MC_CHECK_LAUNCH();
+}
+
 // M = (3 I - C) / 2 in place (C symmetric k x k)
 __global__ void ns_matrix_kernel(int k, double* __restrict__ C) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1023,9 +1050,7 @@ void launch_tri_big(int L, const double* G, int64_t ldg, int k, double* S, doubl
   MC_CHECK_LAUNCH();
   // Cholesky QR, then one Newton-Schulz step
   launch_gram<double, double>(L, k, k, Zg, k, Zg, k, C, k, 1, gpart, gcap, st);
-  hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(256),
-                     sizeof(double) * ((size_t)k * k + k), st, k, C, Ri);
-  MC_CHECK_LAUNCH();
+  launch_chol_rinv(k, C, Ri, st);
   launch_panel_gemm<double, double>(L, k, k, Zg, k, Ri, k, 1.0, nullptr, 0.0, nullptr, 0,
                                     Z2, k, st);
   launch_gram<double, double>(L, k, k, Z2, k, Z2, k, C, k, 1, gpart, gcap, st);

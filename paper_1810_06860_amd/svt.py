@@ -171,20 +171,95 @@ def footprint(m, n, nnz, params=None):
     return int(lib().mc_svt_footprint(m, n, nnz, C.byref(p)))
 
 
-def rsvd_bki(m, n, rows, cols, vals, k, s, p, seed, step=1, attempt=0,
-             precision="fp64", stream=None):
-    """Top-k SVD of a sparse matrix by rSVD-BKI on the GPU: (U, S, V)."""
-    rows = np.ascontiguousarray(rows, dtype=np.int64)
-    cols = np.ascontiguousarray(cols, dtype=np.int32)
-    vals = _f64(vals)
+RSVD_METHODS = {"pi": 4, "bki": 5}
+
+
+def _coo(rows, cols, vals):
+    return (np.ascontiguousarray(rows, dtype=np.int64),
+            np.ascontiguousarray(cols, dtype=np.int32), _f64(vals))
+
+
+def _one_shot(fn, m, n, rows, cols, vals, k, s, p, seed, step, attempt, precision,
+              stream):
+    rows, cols, vals = _coo(rows, cols, vals)
     U = np.zeros((m, k))
     S = np.zeros(k)
     V = np.zeros((n, k))
     st = stream if stream is not None else current_stream()
     prec = PRECISIONS[precision] if isinstance(precision, str) else precision
-    check(lib().mc_rsvd_bki(m, n, vals.size, _ptr(rows, C.c_int64),
-                            _ptr(cols, C.c_int32), _ptr(vals, C.c_double), k, s,
-                            p, seed, step, attempt, prec, st,
-                            _ptr(U, C.c_double), _ptr(S, C.c_double),
-                            _ptr(V, C.c_double)), None)
+    check(fn(m, n, vals.size, _ptr(rows, C.c_int64), _ptr(cols, C.c_int32),
+             _ptr(vals, C.c_double), k, s, p, seed, step, attempt, prec, st,
+             _ptr(U, C.c_double), _ptr(S, C.c_double), _ptr(V, C.c_double)), None)
     return U, S, V
+
+
+def rsvd_bki(m, n, rows, cols, vals, k, s, p, seed, step=1, attempt=0,
+             precision="fp64", stream=None):
+    """Top-k SVD of a sparse matrix by rSVD-BKI on the GPU: (U, S, V)."""
+    return _one_shot(lib().mc_rsvd_bki, m, n, rows, cols, vals, k, s, p, seed, step,
+                     attempt, precision, stream)
+
+
+def rsvd_pi(m, n, rows, cols, vals, k, s, p, seed, step=1, attempt=0,
+            precision="fp64", stream=None):
+    """Top-k SVD of a sparse matrix by rSVD-PI on the GPU: (U, S, V)."""
+    return _one_shot(lib().mc_rsvd_pi, m, n, rows, cols, vals, k, s, p, seed, step,
+                     attempt, precision, stream)
+
+
+class RSVD:
+    """A sparse matrix kept on the device for repeated truncated SVDs
+    (mc_rsvd_init / mc_rsvd_run)."""
+
+    def __init__(self, m, n, rows, cols, vals, s=10, precision="fp64", seed=1,
+                 stream=None):
+        rows, cols, vals = _coo(rows, cols, vals)
+        self.m, self.n, self.s = m, n, s
+        self._stream = stream if stream is not None else current_stream()
+        prec = PRECISIONS[precision] if isinstance(precision, str) else precision
+        h = C.c_void_p()
+        st = lib().mc_rsvd_init(m, n, vals.size, _ptr(rows, C.c_int64),
+                                _ptr(cols, C.c_int32), _ptr(vals, C.c_double), s, prec,
+                                seed, self._stream, C.byref(h))
+        self.handle = None
+        self._check(st)
+        self.handle = h
+
+    def _check(self, status):
+        if status != MC_OK:
+            msg = lib().mc_rsvd_last_error(self.handle)
+            raise MCError(status, msg.decode() if msg else "")
+
+    def run(self, method, k, p, step=1, attempt=0, factors=True):
+        """(U, S, V) of one call; U and V are None when factors is False."""
+        meth = RSVD_METHODS[method] if isinstance(method, str) else method
+        S = np.zeros(k)
+        U = np.zeros((self.m, k)) if factors else None
+        V = np.zeros((self.n, k)) if factors else None
+        nul = C.POINTER(C.c_double)()
+        self._check(lib().mc_rsvd_run(
+            self.handle, meth, k, p, step, attempt,
+            _ptr(U, C.c_double) if factors else nul, _ptr(S, C.c_double),
+            _ptr(V, C.c_double) if factors else nul))
+        return U, S, V
+
+    def profile(self, on=True):
+        self._check(lib().mc_rsvd_profile(self.handle, int(bool(on))))
+
+    def get_profile(self):
+        arr = (ProfEntry * len(PROF_FAMILIES))()
+        self._check(lib().mc_rsvd_get_profile(self.handle, arr, len(PROF_FAMILIES)))
+        return {name: dict(launches=arr[j].launches, ms=arr[j].ms,
+                           bytes=arr[j].bytes, flops=arr[j].flops)
+                for j, name in enumerate(PROF_FAMILIES)}
+
+    def close(self):
+        if self.handle:
+            lib().mc_rsvd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -15,6 +15,12 @@ ratings      Zipf(s) row degrees water-filled under the cap n and summing to
              round(3.5 + (U_i . V_j) / sqrt(r)) clipped to 1..5 with
              U, V ~ N(0, 1).  Stand-in for the MovieLens sets (Sec. V.C).
 serving_trace  Poisson arrivals and per-request planted problems.
+sparse_square  the ratings recipe on a square n x n matrix with a given mean
+             number of entries per row, and sparser copies made by keeping a
+             seeded uniform subset of its entries.  Stand-in for the
+             45,115 x 45,115 rating matrix and its two thinned versions that
+             the randomized-SVD comparison of Sec. V.A uses (97, 24 and 9
+             entries per row).
 """
 
 from dataclasses import dataclass, field
@@ -190,3 +196,21 @@ def request_problem(req):
     return planted(req["m"], req["n"], req["rank"], req["ratio"],
                    req["seed_data"], req["seed_phi"],
                    name=f"req{req['id']}")
+
+
+def sparse_square(n=45115, per_row=(97, 24, 9), rank=20, seed_data=6, seed_thin=7,
+                  name="sparse45k"):
+    """Problems of mean row density per_row[0], per_row[1], ...: the first is
+    generated by ``ratings``, each later one keeps a uniform random subset of
+    the first one's entries (sorted, so still in row-major order)."""
+    full = ratings(n, n, int(per_row[0]) * n, rank, seed_data=seed_data,
+                   name=f"{name}_{per_row[0]}")
+    out = [full]
+    rng = np.random.default_rng(seed_thin)
+    for d in per_row[1:]:
+        keep = np.sort(rng.choice(full.nnz, size=int(d) * n, replace=False))
+        out.append(Problem(n, n, full.rows[keep], full.cols[keep], full.vals[keep],
+                           name=f"{name}_{d}", U=full.U, V=full.V,
+                           offset=full.offset, scale=full.scale,
+                           meta=dict(full.meta, thinned_from=per_row[0])))
+    return out

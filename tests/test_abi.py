@@ -114,3 +114,24 @@ def test_null_handle_calls(lib):
     info = StepInfo()
     assert lib.mc_svt_step(None, C.byref(info)) == MC_EINVAL
     assert lib.mc_svt_destroy(None) == 0
+
+
+def test_rsvd_entry_points_validate_before_the_device(lib):
+    from paper_1810_06860_amd import MCError, RSVD, rsvd_pi
+    from paper_1810_06860_amd._ffi import MC_EINVAL
+    rows = np.arange(10)
+    cols = np.arange(10)
+    with pytest.raises(MCError) as ei:            # k + s > min(m, n)
+        rsvd_pi(10, 10, rows, cols, np.ones(10), k=6, s=5, p=0, seed=1)
+    assert ei.value.status == MC_EINVAL
+    with pytest.raises(MCError) as ei:            # non-finite value
+        RSVD(10, 10, rows, cols, np.r_[np.ones(9), np.nan])
+    assert ei.value.status == MC_EINVAL
+    with pytest.raises(MCError) as ei:            # unknown precision
+        RSVD(10, 10, rows, cols, np.ones(10), precision=7)
+    assert ei.value.status == MC_EINVAL
+    S = np.zeros(2)
+    assert lib.mc_rsvd_run(None, 4, 2, 0, 1, 0, None,
+                           S.ctypes.data_as(C.POINTER(C.c_double)), None) == MC_EINVAL
+    assert lib.mc_rsvd_destroy(None) == 0
+    assert lib.mc_rsvd_last_error(None)

@@ -164,7 +164,8 @@ def test_panel_matches_fp64_product(K, N, p, q):
 
 
 @pytest.mark.parametrize("N,b,kappa", [(2000, 21, 1e2), (5000, 64, 1e5),
-                                       (3000, 110, 1e3), (500, 7, 1e9)])
+                                       (3000, 110, 1e3), (500, 7, 1e9),
+                                       (4000, 128, 1e4), (2000, 140, 1e2)])
 def test_cholqr2_orthonormal_same_range(K, N, b, kappa):
     rng = np.random.default_rng(b)
     U, _ = np.linalg.qr(rng.standard_normal((N, b)))

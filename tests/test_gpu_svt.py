@@ -15,7 +15,8 @@ def _sparse(p):
 
 
 @pytest.mark.parametrize("m,n,k,s,p", [(500, 500, 11, 10, 3), (700, 300, 5, 10, 2),
-                                       (300, 700, 20, 10, 1), (400, 400, 1, 10, 8)])
+                                       (300, 700, 20, 10, 1), (400, 400, 1, 10, 8),
+                                       (600, 500, 70, 10, 1)])
 def test_rsvd_bki_matches_oracle_same_omega(m, n, k, s, p):
     from paper_1810_06860_amd import rsvd_bki as gpu_rsvd
     prob = synth.planted(m, n, 8, 0.3, seed_data=m + k, seed_phi=n + p)
