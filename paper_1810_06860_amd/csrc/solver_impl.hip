@@ -42,6 +42,10 @@ void swap_buf(DevBuf<T>& a, DevBuf<T>& b) {
 // Gram products over at most this many rows finish (and factor) in the same
 // launch; taller panels keep many row splits and a separate reduction
 constexpr int64_t kFuseRows = 8192;
+// the fused completion factors the Gram in registers up to this width; wider
+// blocks go to the 1024-thread Cholesky kernel, which keeps its registers
+// for b up to 128
+constexpr int kFuseCholMax = 64;
 
 double spmm_bytes(int64_t nnz, int64_t rows, int64_t cols, int b, int sv, int sx) {
   return (double)nnz * (sv + 4) + 4.0 * (rows + 1) + (double)cols * b * sx +
@@ -322,7 +326,7 @@ void SolverT<P, VT, AT>::cholqr_pass(const P* Hin, int64_t ldin, P* out, int64_t
   // Gram, its completion and the Cholesky inverse in one launch
   prof.begin(kProfGram, (double)sizeof(P) * m_ * b,
              1.0 * m_ * b * (b + 1) + (double)b * b * b, ls());
-  if (b <= kCholLdsMax && m_ <= kFuseRows) {
+  if (b <= kFuseCholMax && m_ <= kFuseRows) {
     launch_gram_fused<P, AT>(m_, b, b, Hin, ldin, Hin, ldin, G_.p, b, 1, gram_part_.p,
                              gram_cap_, fuse_ctr_.p, Rinv_.p, b, m_, shift_count_.p,
                              blk_flag_.p, ls(), gate);

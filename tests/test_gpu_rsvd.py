@@ -29,7 +29,7 @@ def _proj_dist(Ua, Ub):
 
 
 # block widths b = k + s from 7 to 80: every register tiling of the fused
-# Gram's Cholesky (b <= 8, 16, 24, 32, 64) and its LDS form (b > 64)
+# Gram's Cholesky (b <= 8, 16, 24, 32, 64) and the Cholesky kernel beyond
 @pytest.mark.parametrize("m,n,k,s,p", [(500, 500, 11, 10, 3), (700, 300, 5, 10, 0),
                                        (300, 700, 20, 10, 1), (400, 400, 1, 10, 8),
                                        (257, 1031, 7, 3, 5), (130, 90, 30, 40, 2),
