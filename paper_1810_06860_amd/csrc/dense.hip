@@ -232,34 +232,67 @@ __global__ __launch_bounds__(GramTailThreads) void gram_kernel(
   __syncthreads();
   if (!is_last) return;
   __threadfence();
+  extern __shared__ double lds[];
+  // the register Cholesky (p <= 64) reads the summed Gram from LDS, after its
+  // own 3 p doubles
+  const bool g_lds = tail.mode == 2 && p <= 64;
+  double* Gl = lds + 3 * p;
   const int64_t tot = (int64_t)p * q;
-  for (int64_t t = threadIdx.x; t < tot; t += blockDim.x) {
-    const int i = (int)(t / q), j = (int)(t % q);
-    int si = i, sj = j;
-    if (sym && (i / GT) > (j / GT)) { si = j; sj = i; }   // mirrored tile
-    // splits in groups of eight independent loads, summed in split order
-    const AT* pp = part + (int64_t)si * q + sj;
-    double acc = 0.0;
-    int sp2 = 0;
-    for (; sp2 + 8 <= tail.nsplit; sp2 += 8) {
-      double v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = (double)pp[(int64_t)(sp2 + u) * tot];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc += v[u];
+  const int nt = (int)blockDim.x;
+  for (int64_t t = threadIdx.x; t < tot; t += 2 * nt) {
+    // two entries per thread, the split loads of both in flight together
+    // (groups of 16), each summed in split order
+    const int64_t t2 = t + nt < tot ? t + nt : t;
+    const AT* pp[2];
+    for (int e = 0; e < 2; ++e) {
+      const int64_t te = e ? t2 : t;
+      const int i = (int)(te / q), j = (int)(te % q);
+      int si = i, sj = j;
+      if (sym && (i / GT) > (j / GT)) { si = j; sj = i; }   // mirrored tile
+      pp[e] = part + (int64_t)si * q + sj;
     }
-    for (; sp2 < tail.nsplit; ++sp2) acc += (double)pp[(int64_t)sp2 * tot];
-    tail.C[(int64_t)i * tail.ldc + j] = acc;
+    double acc[2] = {0.0, 0.0};
+    int sp2 = 0;
+    for (; sp2 + 16 <= tail.nsplit; sp2 += 16) {
+      double v[2][16];
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[e][u] = (double)pp[e][(int64_t)(sp2 + u) * tot];
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc[e] += v[e][u];
+    }
+    for (; sp2 + 4 <= tail.nsplit; sp2 += 4) {
+      double v[2][4];
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[e][u] = (double)pp[e][(int64_t)(sp2 + u) * tot];
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[e] += v[e][u];
+    }
+    for (; sp2 < tail.nsplit; ++sp2)
+      for (int e = 0; e < 2; ++e) acc[e] += (double)pp[e][(int64_t)sp2 * tot];
+    for (int e = 0; e < 2; ++e) {
+      if (e == 1 && t2 == t) break;
+      const int64_t te = e ? t2 : t;
+      const int i = (int)(te / q), j = (int)(te % q);
+      tail.C[(int64_t)i * tail.ldc + j] = acc[e];
+      if (g_lds) Gl[te] = acc[e];
+    }
   }
-  __threadfence();
+  if (!g_lds) __threadfence();                       // the LDS form reads C back
   __syncthreads();
   if (tail.mode == 2) {
-    extern __shared__ double lds[];
     // 256 threads: 8 rows of 32 lanes; in registers up to p = 64, else the
     // elimination array in LDS: A (p x p), aux (2 p)
     static_assert(GramTailThreads == 256, "register tiles assume 8 thread rows");
-    const double* Cc = tail.C;
-    const int64_t lc = tail.ldc;
+    const double* Cc = g_lds ? Gl : tail.C;
+    const int64_t lc = g_lds ? p : tail.ldc;
     if (p <= 8)
       chol_inv_regs<1, 1>(p, Cc, lc, tail.Rinv, tail.ldr, lds, tail.nrows, tail.shifted,
                           tail.flag, false);
@@ -727,7 +760,7 @@ void launch_gram_fused(int64_t N, int p, int q, const IT* A, int64_t lda, const 
     return true;
   }();
   (void)attr;
-  const size_t lds = chol ? ((size_t)p * p + 2 * p) * sizeof(double) : 0;
+  const size_t lds = chol ? ((size_t)p * p + 3 * p) * sizeof(double) : 0;
   dim3 grid((unsigned)tp, (unsigned)tq, (unsigned)splits);
   hipLaunchKernelGGL((gram_kernel<IT, AT>), grid, dim3(GramTailThreads), lds, st, N, p, q, A, lda, B,
                      ldb, part, rps, sym, gate, t);

@@ -110,9 +110,9 @@ void launch_panel_gemm(int64_t N, int p, int q, const XT* X, int64_t ldx,
                        const int* gate = nullptr);
 
 // The Cholesky factorisation and R^-1 of a b x b Gram matrix work in
-// b*b + 2b doubles: in LDS up to this b (133 KB at b = 128)
+// b*b + 3b doubles: in LDS up to this b (134 KB at b = 128)
 constexpr int kCholLdsMax = 128;
-constexpr int kCholLdsDoubles = kCholLdsMax * kCholLdsMax + 2 * kCholLdsMax;
+constexpr int kCholLdsDoubles = kCholLdsMax * kCholLdsMax + 3 * kCholLdsMax;
 // flag (optional) is set to 1 when a diagonal shift was needed
 // work: b*b + 2b doubles (global), used when b > kCholLdsMax
 void launch_chol_inv(int b, const double* G, int64_t ldg, double* Rinv,

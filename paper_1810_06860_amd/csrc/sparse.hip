@@ -434,10 +434,18 @@ void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
     MC_SPMM(8, 1);
   else if (b <= 16)
     MC_SPMM(16, 1);
+  else if (b <= 24)
+    MC_SPMM(8, 3);
   else if (b <= 32)
     MC_SPMM(16, 2);
+  else if (b <= 48)
+    MC_SPMM(16, 3);
   else if (b <= 64)
     MC_SPMM(16, 4);
+  else if (b <= 80)
+    MC_SPMM(16, 5);
+  else if (b <= 96)
+    MC_SPMM(16, 6);
   else if (b <= 128)
     MC_SPMM(32, 4);
   else
