@@ -448,8 +448,24 @@ void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
     MC_SPMM(16, 6);
   else if (b <= 128)
     MC_SPMM(32, 4);
-  else
-    MC_SPMM(64, 4);
+  else {
+    // wide panels: 64 lanes per nonzero and the fewest passes of at most
+    // 512 columns, each as narrow as covers b
+    const int passes = (int)ceil_div(b, 512);
+    const int cpl = (int)ceil_div(ceil_div(b, passes), 64);   // 3..8
+    if (cpl <= 3)
+      MC_SPMM(64, 3);
+    else if (cpl == 4)
+      MC_SPMM(64, 4);
+    else if (cpl == 5)
+      MC_SPMM(64, 5);
+    else if (cpl == 6)
+      MC_SPMM(64, 6);
+    else if (cpl == 7)
+      MC_SPMM(64, 7);
+    else
+      MC_SPMM(64, 8);
+  }
 #undef MC_SPMM
   MC_CHECK_LAUNCH();
   if (S.nfix) {

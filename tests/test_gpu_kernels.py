@@ -60,7 +60,8 @@ def test_layout_rejects_duplicates_and_range(K):
     assert e.value.status == MC_ERANGE
 
 
-@pytest.mark.parametrize("b", [1, 5, 16, 21, 24, 33, 48, 64, 70, 80, 90, 110, 128, 330])
+@pytest.mark.parametrize("b", [1, 5, 16, 21, 24, 33, 48, 64, 70, 80, 90, 110, 128, 200, 300,
+                               330, 400, 448, 520, 1100])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_spmm_fp64(K, b, transpose):
     m, n = 700, 530
