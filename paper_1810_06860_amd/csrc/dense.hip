@@ -572,6 +572,138 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(
     }
 }
 
+// Gram (or cross-Gram) of a short block in one workgroup on the matrix
+// cores: C = A^T B for A (N x p), B (N x q), N <= kSmallRows, at most
+// kSmallTiles 16 x 16 output tiles (TP x TQ, or the TP (TP + 1) / 2 upper
+// tiles of a symmetric product: SYM, B is A).  Each of the 16 wavefronts
+// takes every 16th 4-row step (16x16x4 MFMA; a lane loads row 4 s + lane / 16,
+// column lane % 16 of each tile, so operands come straight from memory), the
+// wavefronts' tiles are summed in a fixed tree in LDS, and mode 2 (SYM) then
+// forms R^{-1} of C = R^T R in registers.  No partial buffer, no counter.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallWaves = kSmallThreads / 64;
+constexpr int kSmallTiles = 6;
+constexpr int64_t kSmallRows = 2048;
+constexpr int kSmallUnroll = 4;    // 4-row steps in flight per wavefront (16 measured no faster)
+
+template <class T, bool SYM, int TP, int TQ>
+__global__ __launch_bounds__(kSmallThreads) void gram_small_kernel(
+    int64_t N, int p, int q, const T* __restrict__ A, int64_t lda,
+    const T* __restrict__ B, int64_t ldb, const int* __restrict__ gate, GramTail tail) {
+  if (gate && *gate == 0) return;
+  using M = Mfma16<T>;
+  using V = typename M::V;
+  static_assert(!SYM || TP == TQ, "a symmetric product has square tiling");
+  constexpr int NT = SYM ? TP * (TP + 1) / 2 : TP * TQ;
+  static_assert(NT <= kSmallTiles, "tile count");
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lr = lane >> 4, lc = lane & 15;
+  // this lane's column in each tile (clamped, zeroed by a factor)
+  const T* Ap[TP];
+  T fa[TP];
+#pragma unroll
+  for (int ti = 0; ti < TP; ++ti) {
+    const int c = ti * 16 + lc;
+    fa[ti] = c < p ? T(1) : T(0);
+    Ap[ti] = A + (c < p ? c : 0);
+  }
+  const T* Bp[TQ];
+  T fb[TQ];
+#pragma unroll
+  for (int tj = 0; tj < TQ; ++tj) {
+    const int c = tj * 16 + lc;
+    fb[tj] = c < q ? T(1) : T(0);
+    Bp[tj] = B + (c < q ? c : 0);
+  }
+  V acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = V{0, 0, 0, 0};
+  const int64_t steps = (N + 3) / 4;
+  for (int64_t s0 = w; s0 < steps; s0 += (int64_t)kSmallWaves * kSmallUnroll) {
+    T a[kSmallUnroll][TP], b[kSmallUnroll][TQ];
+#pragma unroll
+    for (int u = 0; u < kSmallUnroll; ++u) {
+      const int64_t r = 4 * (s0 + (int64_t)kSmallWaves * u) + lr;
+      const bool rin = r < N;
+      const int64_t rr = rin ? r : 0;
+      const T m = rin ? T(1) : T(0);
+#pragma unroll
+      for (int ti = 0; ti < TP; ++ti) a[u][ti] = Ap[ti][rr * lda] * (m * fa[ti]);
+      if (!SYM) {
+#pragma unroll
+        for (int tj = 0; tj < TQ; ++tj) b[u][tj] = Bp[tj][rr * ldb] * (m * fb[tj]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSmallUnroll; ++u) {
+      int t = 0;
+#pragma unroll
+      for (int ti = 0; ti < TP; ++ti)
+#pragma unroll
+        for (int tj = SYM ? ti : 0; tj < TQ; ++tj, ++t)
+          acc[t] = M::op(a[u][ti], SYM ? a[u][tj] : b[u][tj], acc[t]);
+    }
+  }
+  // fixed-order tree over the wavefronts: in round h, wavefronts h .. 2h-1
+  // hand their tiles to wavefronts 0 .. h-1 through LDS
+  double sum[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sum[t][v] = (double)acc[t][v];
+  for (int h = kSmallWaves / 2; h >= 1; h >>= 1) {
+    if (w >= h && w < 2 * h) {
+      double* dst = lds + (size_t)(w - h) * NT * 256;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[(t * 4 + v) * 64 + lane] = sum[t][v];
+    }
+    __syncthreads();
+    if (w < h) {
+      const double* src = lds + (size_t)w * NT * 256;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sum[t][v] += src[(t * 4 + v) * 64 + lane];
+    }
+    __syncthreads();
+  }
+  // wavefront 0 writes C (and, for the Cholesky, a copy in LDS)
+  double* Gl = lds;
+  const bool chol = tail.mode == 2;
+  if (w == 0) {
+    int t = 0;
+#pragma unroll
+    for (int ti = 0; ti < TP; ++ti)
+#pragma unroll
+      for (int tj = SYM ? ti : 0; tj < TQ; ++tj, ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = ti * 16 + M::row(lane, v), j = tj * 16 + lc;
+          if (i < p && j < q) {
+            tail.C[(int64_t)i * tail.ldc + j] = sum[t][v];
+            if (chol) Gl[i * q + j] = sum[t][v];
+            if (SYM && ti != tj) {
+              tail.C[(int64_t)j * tail.ldc + i] = sum[t][v];
+              if (chol) Gl[j * q + i] = sum[t][v];
+            }
+          }
+        }
+  }
+  if (!chol) return;
+  __syncthreads();
+  // 1024 threads: 32 rows of 32 lanes
+  double* cl = lds + (size_t)p * q;
+  if (p <= 32)
+    chol_inv_regs<1, 1>(p, Gl, q, tail.Rinv, tail.ldr, cl, tail.nrows, tail.shifted,
+                        tail.flag, false);
+  else
+    chol_inv_regs<2, 2>(p, Gl, q, tail.Rinv, tail.ldr, cl, tail.nrows, tail.shifted,
+                        tail.flag, false);
+}
+
 // One workgroup: G (b x b, SPD) = R^T R, Rinv = R^-1 (upper triangular).
 // Breakdown (a pivot that is not positive or below 1e-13 of its original
 // diagonal) retries with G + shift I.  Elimination on [G | I] with one
@@ -716,6 +848,78 @@ template void launch_gram<float, float>(int64_t, int, int, const float*,
                                         int64_t, int, float*, int64_t,
                                         hipStream_t, const int*);
 
+// The one-workgroup form for short blocks with few tiles; false when the
+// shape is outside it (the caller then takes the split form).
+template <class T>
+bool launch_gram_small(int64_t N, int p, int q, const T* A, int64_t lda, const T* B,
+                       int64_t ldb, double* C, int64_t ldc, int sym, double* Rinv,
+                       int64_t ldr, int64_t nrows, int* shifted, int* flag, hipStream_t st,
+                       const int* gate) {
+  const bool chol = Rinv != nullptr;
+  const int tp = (int)ceil_div(p, 16), tq = (int)ceil_div(q, 16);
+  if (N > kSmallRows || tp > 4 || tq > 4) return false;
+  if ((sym || chol) && (p != q || A != B || lda != ldb)) return false;
+  const bool sq = sym || chol;
+  const int nt = sq ? tp * (tp + 1) / 2 : tp * tq;
+  if (nt > kSmallTiles || (chol && p > 64)) return false;
+  GramTail t;
+  t.mode = chol ? 2 : 1;
+  t.C = C;
+  t.ldc = ldc;
+  t.Rinv = Rinv;
+  t.ldr = ldr;
+  t.nrows = nrows;
+  t.shifted = shifted;
+  t.flag = flag;
+  // the reduction tree (8 wavefronts' tiles) and, after it, G and the
+  // Cholesky's 3 p doubles
+  const size_t red = (size_t)(kSmallWaves / 2) * nt * 256;
+  const size_t lds = sizeof(double) * std::max(red, (size_t)p * q + 3 * p);
+  static const bool attr = [] {
+    const int bytes = (int)sizeof(double) * (kSmallWaves / 2) * kSmallTiles * 256;
+#define MC_SMALL_ATTR(T_, S_, P_, Q_)                                                   \
+  if (hipFuncSetAttribute((const void*)gram_small_kernel<T_, S_, P_, Q_>,                \
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes) != hipSuccess) \
+    (void)hipGetLastError();
+#define MC_SMALL_ALL(T_)                                                                \
+  MC_SMALL_ATTR(T_, true, 1, 1) MC_SMALL_ATTR(T_, true, 2, 2) MC_SMALL_ATTR(T_, true, 3, 3) \
+  MC_SMALL_ATTR(T_, false, 1, 1) MC_SMALL_ATTR(T_, false, 1, 2) MC_SMALL_ATTR(T_, false, 1, 3) \
+  MC_SMALL_ATTR(T_, false, 1, 4) MC_SMALL_ATTR(T_, false, 2, 1) MC_SMALL_ATTR(T_, false, 2, 2) \
+  MC_SMALL_ATTR(T_, false, 2, 3) MC_SMALL_ATTR(T_, false, 3, 1) MC_SMALL_ATTR(T_, false, 3, 2) \
+  MC_SMALL_ATTR(T_, false, 4, 1)
+    MC_SMALL_ALL(double)
+    MC_SMALL_ALL(float)
+#undef MC_SMALL_ALL
+#undef MC_SMALL_ATTR
+    return true;
+  }();
+  (void)attr;
+#define MC_SMALL(S_, P_, Q_)                                                              \
+  hipLaunchKernelGGL((gram_small_kernel<T, S_, P_, Q_>), dim3(1), dim3(kSmallThreads), lds, \
+                     st, N, p, q, A, lda, B, ldb, gate, t)
+  if (sq) {
+    if (tp == 1) MC_SMALL(true, 1, 1);
+    else if (tp == 2) MC_SMALL(true, 2, 2);
+    else MC_SMALL(true, 3, 3);
+  } else {
+    switch (tp * 8 + tq) {
+      case 9: MC_SMALL(false, 1, 1); break;
+      case 10: MC_SMALL(false, 1, 2); break;
+      case 11: MC_SMALL(false, 1, 3); break;
+      case 12: MC_SMALL(false, 1, 4); break;
+      case 17: MC_SMALL(false, 2, 1); break;
+      case 18: MC_SMALL(false, 2, 2); break;
+      case 19: MC_SMALL(false, 2, 3); break;
+      case 25: MC_SMALL(false, 3, 1); break;
+      case 26: MC_SMALL(false, 3, 2); break;
+      default: MC_SMALL(false, 4, 1); break;
+    }
+  }
+#undef MC_SMALL
+  MC_CHECK_LAUNCH();
+  return true;
+}
+
 // Gram (or cross-Gram) with its completion in the same launch: C = A^T B
 // (mode 1) or, with A = B, also Rinv = R^{-1} of C = R^T R (mode 2).
 template <class IT, class AT>
@@ -727,6 +931,9 @@ void launch_gram_fused(int64_t N, int p, int q, const IT* A, int64_t lda, const 
   if (p <= 0 || q <= 0) return;
   const bool chol = Rinv != nullptr;
   MC_REQUIRE(!chol || (p == q && p <= kCholLdsMax), kEINVAL, "fused Cholesky size");
+  if (launch_gram_small<IT>(N, p, q, A, lda, B, ldb, C, ldc, sym, Rinv, ldr, nrows, shifted,
+                            flag, st, gate))
+    return;
   // at most 64 row splits: one workgroup sums the partials
   int64_t splits = std::min<int64_t>(64, fused_splits(N, p, q, sym));
   while (splits > 1 && splits * p * q > part_cap) --splits;
