@@ -135,3 +135,30 @@ def test_rsvd_entry_points_validate_before_the_device(lib):
                            S.ctypes.data_as(C.POINTER(C.c_double)), None) == MC_EINVAL
     assert lib.mc_rsvd_destroy(None) == 0
     assert lib.mc_rsvd_last_error(None)
+
+
+def test_headers_compile_as_c_and_link_against_the_library(tmp_path):
+    """The public headers are plain C: a C99 program that includes both and
+    calls an entry point compiles with -pedantic and links to libmcsvt.so."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text(
+        '#include "mcsvt.h"\n#include "mcsvt_kernels.h"\n'
+        "int main(void) {\n"
+        "  mc_svt_params p;\n"
+        "  mc_svt_default_params(&p);\n"
+        "  mc_rsvd_t h = 0;\n"
+        "  (void)h;\n"
+        "  return (mc_abi_version() == MCSVT_ABI_VERSION && p.l == 5) ? 0 : 1;\n"
+        "}\n")
+    exe = tmp_path / "use"
+    subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+                    "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                    LIB, "-Wl,-rpath," + os.path.dirname(LIB)],
+                   check=True, capture_output=True)
+    run = subprocess.run([str(exe)], capture_output=True, timeout=60)
+    assert run.returncode == 0, run.stderr
