@@ -748,10 +748,18 @@ __global__ void copy_gated_kernel(int64_t rows, int cols, const T* __restrict__ 
 
 __global__ void recip_kernel(int k, const double* __restrict__ S,
                              double* __restrict__ out, const int* __restrict__ count,
-                             double* __restrict__ count_out) {
+                             double* __restrict__ count_out, double* __restrict__ host) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < k) out[j] = S[j] > 0.0 ? 1.0 / S[j] : 0.0;
-  if (j == 0 && count) count_out[0] = (double)*count;
+  if (j < k) {
+    const double s = S[j];
+    out[j] = s > 0.0 ? 1.0 / s : 0.0;
+    if (host) host[j] = s;
+  }
+  if (j == 0 && count) {
+    const double c = (double)*count;
+    count_out[0] = c;
+    if (host) host[k] = c;
+  }
 }
 
 // partial[blk * k + j] = sum over the block's rows of (R_ij - S_j U_ij)^2
@@ -1065,9 +1073,9 @@ template void launch_copy_gated<float>(int64_t, int, const float*, int64_t, floa
                                        int64_t, const int*, hipStream_t);
 
 void launch_recip(int k, const double* S, double* out, hipStream_t st, const int* count,
-                  double* count_out) {
+                  double* count_out, double* host) {
   hipLaunchKernelGGL(recip_kernel, dim3((unsigned)ceil_div(k, 128)), dim3(128), 0,
-                     st, k, S, out, count, count_out);
+                     st, k, S, out, count, count_out, host);
   MC_CHECK_LAUNCH();
 }
 

@@ -70,7 +70,7 @@ void launch_sddmm_update(const Layout& L, const double* mvals, double* y, VT* yv
                          VT* ycv, WT* yw, WT* ycw, const FT* U, int64_t ldu,
                          const FT* V, int64_t ldv, const double* sig, int r,
                          double delta, int apply, double* partial, double* out_sum,
-                         hipStream_t st);
+                         hipStream_t st);   // out_sum: device or pinned host memory
 template <class FT>
 void launch_eval_observed(const Layout& L, const FT* U, int64_t ldu,
                           const FT* V, int64_t ldv, const double* sig, int r,
@@ -124,10 +124,13 @@ template <class T>
 void launch_copy_gated(int64_t rows, int cols, const T* src, int64_t lds_, T* dst,
                        int64_t ldd, const int* gate, hipStream_t st);
 
-// out = 1 / S (0 where S <= 0); with `count`, also count_out[0] = *count (so
-// one copy to the host can carry both)
+// out = 1 / S (0 where S <= 0); with `count`, also count_out[0] = *count.
+// With `host` (pinned host memory), also host[0..k) = S and, with `count`,
+// host[k] = *count: the values reach the host without a copy launch, and
+// are there once the stream has passed this kernel.
 void launch_recip(int k, const double* S, double* out, hipStream_t st,
-                  const int* count = nullptr, double* count_out = nullptr);
+                  const int* count = nullptr, double* count_out = nullptr,
+                  double* host = nullptr);
 // out[j] = ||R_j - S_j U_j|| / S_j  (Ritz residual ratios, k columns)
 int ritz_blocks(int64_t m);
 template <class T>

@@ -212,7 +212,9 @@ void SolverT<P, VT, AT>::ensure(int bmax, int Lmax, int kmax) {
   const size_t need = (size_t)(2 * std::max(Lc, k) + 64);
   if (!hbuf_ || hbuf_n_ < need) {
     if (hbuf_) MC_HIP(hipHostFree(hbuf_));
-    MC_HIP(hipHostMalloc((void**)&hbuf_, need * sizeof(double)));
+    // coherent: kernels write the per-call results (S, the shift count, the
+    // residual) here directly, and the host reads them after the stream event
+    MC_HIP(hipHostMalloc((void**)&hbuf_, need * sizeof(double), hipHostMallocCoherent));
     hbuf_n_ = need;
   }
 }
@@ -396,9 +398,10 @@ void SolverT<P, VT, AT>::orth_block(int j, int b, int Lw, bool guarded) {
 // to pinned host memory, read once the stream has reached them
 template <class P, class VT, class AT>
 void SolverT<P, VT, AT>::read_launch(int k, bool ritz, bool count) {
-  // with `count`, the shift count that the eigSVD step stored behind S
-  MC_HIP(hipMemcpyAsync(hbuf_, S_.p, (k + (count ? 1 : 0)) * sizeof(double),
-                        hipMemcpyDeviceToHost, st_));
+  // S (and, with `count`, the shift count behind it) were written to hbuf_ by
+  // the eigSVD step's reciprocal kernel; the Ritz ratios are copied over the
+  // count's slot
+  (void)count;
   if (ritz)
     MC_HIP(hipMemcpyAsync(hbuf_ + k, ritz_out_.p, k * sizeof(double),
                           hipMemcpyDeviceToHost, st_));
@@ -432,7 +435,8 @@ void SolverT<P, VT, AT>::eig_body(const P* basis, int64_t ldb, int w, int k) {
              2.0 * (m_ + n_) * w * k, ls());
   launch_panel_gemm<P, P>(m_, w, k, basis, ldb, Wk_.p, k, 1.0, nullptr, 0.0, nullptr,
                           0, U_.p, k, ls());                 // U = Q W
-  launch_recip(k, S_.p, Sinv_.p, ls(), shift_count_.p, S_.p + k);
+  // S and the shift count go straight to the pinned read-back buffer
+  launch_recip(k, S_.p, Sinv_.p, ls(), shift_count_.p, S_.p + k, hbuf_);
   launch_panel_gemm<P, P>(n_, w, k, Bt_.p, w, Wk_.p, k, 1.0, Sinv_.p, 0.0, nullptr, 0,
                           V_.p, k, ls());                    // V = B^T W S^-1
   prof.end(ls());
@@ -598,9 +602,8 @@ void SolverT<P, VT, AT>::sddmm_launch(int r) {
                                     ycv_.p, kSplit ? yw_.p : nullptr,
                                     kSplit ? ycw_.p : nullptr, U_.p, k_last_, V_.p,
                                     k_last_, sig_.p, r, prm_.delta, 1, sdd_part_.p,
-                                    scal_.p, st_);
+                                    hbuf_, st_);       // the residual sum straight to the host
   prof.end(st_);
-  MC_HIP(hipMemcpyAsync(hbuf_, scal_.p, sizeof(double), hipMemcpyDeviceToHost, st_));
 }
 
 template <class P, class VT, class AT>
