@@ -118,6 +118,10 @@ def roofline(prof, prec, workload):
         roof = dict(bound="alu", achieved=round(achieved, 4), peak=peak,
                     unit="TFLOP/s")
     roof["frac"] = round(roof["achieved"] / roof["peak"], 5)
+    g = gather_bytes(dom, v["flops"], prec)
+    if g:
+        # what the product actually moves from L2 / MALL / HBM per second
+        roof["gather_GBps"] = round(g / v["launches"] / (per_launch_ms * 1e-3) / 1e9, 1)
     roof["traffic"] = measured_traffic(workload, dom, prec)
     roof["kernel"] = dom
     roof["launches"] = v["launches"]
@@ -125,7 +129,16 @@ def roofline(prof, prec, workload):
     return dom, roof
 
 
-def family_table(prof, total_s):
+def gather_bytes(family, flops, prec):
+    """Panel bytes a sparse product gathers: one b-wide row of X per nonzero
+    (nnz b = flops / 2), in the panel type (FP64, else FP32).  Not counted in
+    the algorithmic bytes, which read X once."""
+    if not family.startswith("spmm"):
+        return None
+    return flops / 2.0 * (8 if prec == "fp64" else 4)
+
+
+def family_table(prof, total_s, prec="fp64"):
     out = {}
     for k, v in prof.items():
         if v["launches"] == 0:
@@ -137,6 +150,9 @@ def family_table(prof, total_s):
             ent["GBps"] = round(v["bytes"] / (ms * 1e-3) / 1e9, 1)
         if v["flops"] and ms > 0:
             ent["TFLOPs"] = round(v["flops"] / (ms * 1e-3) / 1e12, 4)
+        g = gather_bytes(k, v["flops"], prec)
+        if g and ms > 0:
+            ent["gather_GBps"] = round(g / (ms * 1e-3) / 1e9, 1)
         out[k] = ent
     return out
 
@@ -318,7 +334,8 @@ def rsvd_main(a):
         "cpu_baseline": cpu,
         "accuracy": acc,
         "cases": cases,
-        "kernels": family_table(prof, sum(v["ms"] for v in prof.values()) * 1e-3),
+        "kernels": family_table(prof, sum(v["ms"] for v in prof.values()) * 1e-3,
+                                a.precision),
     }
     print(json.dumps(line))
 
@@ -485,7 +502,7 @@ def main():
         "cpu_baseline": cpu,
         "accuracy": acc,
         "serving": serve,
-        "kernels": family_table(prof, tp1 - tp0),
+        "kernels": family_table(prof, tp1 - tp0, a.precision),
         "profiled_pass": {"steps": pdone,
                           "ms_per_step": round(prof_ms, 4) if prof_ms else None,
                           "launch": "kernel by kernel, HIP events per launch"},

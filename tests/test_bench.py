@@ -53,3 +53,17 @@ def test_measured_traffic_is_tied_to_sources():
     v = b.measured_traffic("image1024", "gram", "fp64")
     assert v is None or v > 0
     assert b.measured_traffic("image1024", "gram", "bf16") is None
+
+
+def test_sparse_families_report_their_gathers():
+    b = _bench()
+    prof = {"spmm_bwd": dict(launches=4, ms=2.0, bytes=1e9, flops=8e9),
+            "gram": dict(launches=4, ms=1.0, bytes=1e8, flops=1e9)}
+    t = b.family_table(prof, 3e-3, "fp64")
+    # nnz b = flops / 2 rows of 8 bytes in 2 ms
+    assert t["spmm_bwd"]["gather_GBps"] == round(4e9 * 8 / 2e-3 / 1e9, 1)
+    assert "gather_GBps" not in t["gram"]
+    t32 = b.family_table(prof, 3e-3, "bf16")
+    assert t32["spmm_bwd"]["gather_GBps"] == round(4e9 * 4 / 2e-3 / 1e9, 1)
+    dom, roof = b.roofline(prof, "fp64", "no-such-workload")
+    assert dom == "spmm_bwd" and roof["gather_GBps"] == t["spmm_bwd"]["gather_GBps"]
