@@ -85,6 +85,33 @@ mc_status mc_k_sddmm(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
                      const double* sig, const double* V, double delta,
                      void* stream, double* x, double* y_new, double* sumsq);
 
+/* Banded work schedule of the SpMM for a CSR-like structure (host code only:
+ * no device is touched).  This is the schedule the SpMM uses once the dense
+ * panel it gathers from outgrows one XCD's L2: the gathered index range
+ * [0, gathered) is cut into `bands` equal ranges (a positive multiple of 8);
+ * rows of at least 256 entries are split at the range boundaries, then into
+ * pieces of at most `cap` entries; shorter rows into pieces of at most `cap`.
+ * Band r belongs to XCD r % 8, which takes its bands in increasing r; rows
+ * shorter than 256 go to the XCDs with the fewest segments.
+ *
+ * Inputs: ptr (rows + 1, ptr[0] = 0, non-decreasing) and idx (ptr[rows]
+ * entries in [0, gathered), increasing within each row), both host arrays
+ * owned by the caller.  Outputs, caller allocated: segs, 4 int32 per segment
+ * (row, begin, end, slot) in launch order -- segment s runs in workgroup
+ * s / 4 and workgroup w on XCD w % 8; row -1 marks padding and slot -1 a row
+ * done in one segment; fix, 4 int32 per row done in several segments (row,
+ * first slot, count, 0), whose partial rows occupy consecutive slots.
+ * On entry *nseg and *nfix hold the capacities of segs and fix in records; on
+ * return they hold the counts, and *nslot the number of partial rows.  If a
+ * capacity is too small (NULL buffers with capacity 0 included) nothing is
+ * written to the buffers, the counts are still returned and the status is
+ * MC_ERANGE.  Errors: MC_EINVAL for bad sizes, a bad ptr, an index out of
+ * range or not increasing within its row. */
+mc_status mc_k_band_schedule(int64_t rows, const int32_t* ptr, const int32_t* idx,
+                             int64_t gathered, int32_t cap, int32_t bands,
+                             int32_t* segs, int64_t* nseg, int32_t* fix,
+                             int64_t* nfix, int64_t* nslot);
+
 #ifdef __cplusplus
 }
 #endif

@@ -117,6 +117,10 @@ _SIGNATURES = {
                               _P(C.c_int32), C.c_void_p, _P(C.c_int32),
                               _P(C.c_int32), _P(C.c_int32), _P(C.c_int32),
                               _P(C.c_int32), _P(C.c_int32)]),
+    "mc_k_band_schedule": (C.c_int, [C.c_int64, _P(C.c_int32), _P(C.c_int32),
+                                     C.c_int64, C.c_int32, C.c_int32,
+                                     _P(C.c_int32), _P(C.c_int64), _P(C.c_int32),
+                                     _P(C.c_int64), _P(C.c_int64)]),
     "mc_k_spmm": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _P(C.c_int64),
                             _P(C.c_int32), _P(C.c_double), C.c_int32, C.c_int32,
                             _P(C.c_double), C.c_int32, C.c_void_p,

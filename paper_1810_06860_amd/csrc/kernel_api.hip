@@ -308,4 +308,46 @@ mc_status mc_k_sddmm(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
   });
 }
 
+mc_status mc_k_band_schedule(int64_t rows, const int32_t* ptr, const int32_t* idx,
+                             int64_t gathered, int32_t cap, int32_t bands,
+                             int32_t* segs, int64_t* nseg, int32_t* fix,
+                             int64_t* nfix, int64_t* nslot) {
+  return kguard([&] {
+    MC_REQUIRE(rows >= 1 && ptr && nseg && nfix && nslot && gathered >= 1 &&
+                   gathered <= INT32_MAX && cap >= 1 && bands >= mcsvt::kBands &&
+                   bands % mcsvt::kBands == 0 && *nseg >= 0 && *nfix >= 0,
+               mcsvt::kEINVAL, "bad sizes or NULL argument");
+    MC_REQUIRE(ptr[0] == 0, mcsvt::kEINVAL, "ptr[0] must be 0");
+    for (int64_t i = 0; i < rows; ++i) {
+      MC_REQUIRE(ptr[i + 1] >= ptr[i], mcsvt::kEINVAL, "ptr decreases");
+      for (int32_t e = ptr[i]; e < ptr[i + 1]; ++e)
+        MC_REQUIRE(idx[e] >= 0 && idx[e] < gathered &&
+                       (e == ptr[i] || idx[e] > idx[e - 1]),
+                   mcsvt::kEINVAL, "index out of range or not increasing in its row");
+    }
+    MC_REQUIRE(ptr[rows] == 0 || idx, mcsvt::kEINVAL, "NULL idx");
+    std::vector<int4> s, f;
+    int32_t slot = 0;
+    mcsvt::band_schedule(ptr, idx, rows, gathered, cap, bands, s, f, slot);
+    const bool fits = (int64_t)s.size() <= *nseg && (int64_t)f.size() <= *nfix &&
+                      (segs || s.empty()) && (fix || f.empty());
+    *nseg = (int64_t)s.size();
+    *nfix = (int64_t)f.size();
+    *nslot = slot;
+    MC_REQUIRE(fits, mcsvt::kERANGE, "output capacity too small");
+    for (size_t q = 0; q < s.size(); ++q) {
+      segs[4 * q] = s[q].x;
+      segs[4 * q + 1] = s[q].y;
+      segs[4 * q + 2] = s[q].z;
+      segs[4 * q + 3] = s[q].w;
+    }
+    for (size_t q = 0; q < f.size(); ++q) {
+      fix[4 * q] = f[q].x;
+      fix[4 * q + 1] = f[q].y;
+      fix[4 * q + 2] = f[q].z;
+      fix[4 * q + 3] = f[q].w;
+    }
+  });
+}
+
 }  // extern "C"

@@ -11,10 +11,32 @@ namespace mcsvt {
 // Work schedule of a CSR-like structure for the segmented SpMM:
 // segs[w] = (row, begin, end, slot) with slot = -1 for whole rows, and
 // fix[f] = (row, first_slot, count, 0) for rows split into several segments.
+// A segment with row -1 is padding and does nothing.
+//
+// Structures whose gathered dimension (the rows of the dense panel) is large
+// also get a banded form: the gathered rows are cut into kBands equal ranges,
+// long rows are split at the range boundaries, and the pieces of range r go
+// to workgroups r, r + kBands, r + 2 kBands, ...; the hardware hands
+// consecutive workgroups to the eight XCDs in turn, so each XCD's caches see
+// one range of the panel instead of all of it.  Splitting costs a partial row
+// and a reduction per piece: the banded form pays off for wide panels, and
+// for structures whose rows are mostly short enough to stay whole.
+constexpr int kBands = 8;
+constexpr int kSpmmWaves = 4;                      // wavefronts per SpMM workgroup
+constexpr int64_t kBandMinRows = 8192;             // gathered rows for a banded form
+constexpr int64_t kBandMinLen = 256;               // shorter rows are not split by band
+constexpr int64_t kBandPanelBytes = 2 << 20;       // smaller panels stay unbanded
+constexpr int kBandWide = 128;                     // wider panels take it regardless
 struct Schedule {
-  int64_t nseg = 0, nfix = 0, nslot = 0;
+  int64_t nseg = 0, nfix = 0;
+  int64_t nslot = 0;                           // partial rows, either form
   DevBuf<int4> segs;
   DevBuf<int4> fix;
+  int64_t gathered = 0;                        // rows of the gathered panel
+  bool short_rows = false;                     // mean row length < kBandMinLen
+  int64_t band_nseg = 0, band_nfix = 0;        // banded form; 0 if not built
+  DevBuf<int4> band_segs;
+  DevBuf<int4> band_fix;
 };
 
 // Canonical layout of the sampled set Phi.
@@ -34,8 +56,16 @@ struct Layout {
 int build_layout(int64_t m, int64_t n, int64_t nnz, const int64_t* d_rows,
                  const int32_t* d_cols, const double* d_vals, Layout& L,
                  hipStream_t st);
+// The banded segments and fix-up records of a host CSR-like structure (host
+// code only; build_schedule uploads them).
+void band_schedule(const int32_t* ptr, const int32_t* idx, int64_t rows,
+                   int64_t gathered, int64_t cap, int nb, std::vector<int4>& segs,
+                   std::vector<int4>& fix, int32_t& slot);
+// host_idx (the gathered index of every entry, sorted within each row) may
+// be null: then no banded form is built
 void build_schedule(const int32_t* host_ptr, int64_t rows, Schedule& S,
-                    hipStream_t st);
+                    hipStream_t st, const int32_t* host_idx = nullptr,
+                    int64_t gathered = 0);
 
 template <class S, class D>
 void launch_cast(int64_t n, const S* src, D* dst, hipStream_t st);

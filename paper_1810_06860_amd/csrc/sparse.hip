@@ -14,6 +14,9 @@
 //   and the squares e^2 are summed per block for the stop test.
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+#include <vector>
+
 #include "kernels.hpp"
 
 namespace mcsvt {
@@ -216,24 +219,115 @@ int build_layout(int64_t m, int64_t n, int64_t nnz, const int64_t* d_rows,
                      nnz, n, col_of.p, L.col_ptr.p);
   MC_CHECK_LAUNCH();
 
-  // host copies of the pointers -> SpMM segment schedules
+  // host copies of the pointers (and, for a large gathered dimension, of
+  // the indices) -> SpMM segment schedules
   std::vector<int32_t> hptr(std::max(m, n) + 1);
-  MC_HIP(hipMemcpyAsync(hptr.data(), L.row_ptr.p, (m + 1) * sizeof(int32_t),
-                        hipMemcpyDeviceToHost, st));
-  MC_HIP(hipStreamSynchronize(st));
-  build_schedule(hptr.data(), m, L.sched_csr, st);
-  MC_HIP(hipMemcpyAsync(hptr.data(), L.col_ptr.p, (n + 1) * sizeof(int32_t),
-                        hipMemcpyDeviceToHost, st));
-  MC_HIP(hipStreamSynchronize(st));
-  build_schedule(hptr.data(), n, L.sched_csc, st);
+  std::vector<int32_t> hidx;
+  auto schedule = [&](const int32_t* d_ptr, int64_t rows, const int32_t* d_idx,
+                      int64_t gathered, Schedule& S) {
+    MC_HIP(hipMemcpyAsync(hptr.data(), d_ptr, (rows + 1) * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, st));
+    const bool band = gathered >= kBandMinRows;
+    if (band) {
+      hidx.resize(nnz);
+      MC_HIP(hipMemcpyAsync(hidx.data(), d_idx, nnz * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, st));
+    }
+    MC_HIP(hipStreamSynchronize(st));
+    build_schedule(hptr.data(), rows, S, st, band ? hidx.data() : nullptr, gathered);
+  };
+  schedule(L.row_ptr.p, m, L.col_idx.p, n, L.sched_csr);
+  schedule(L.col_ptr.p, n, L.row_idx.p, m, L.sched_csc);
   MC_HIP(hipStreamSynchronize(st));
   return kOK;
 }
 
 // Split rows into work segments of at most `cap` entries.  Rows that need
 // several segments get partial slots and a fix-up record.
+namespace {
+
+// pieces of [b, e) of at most `cap` entries each
+int64_t cap_pieces(int64_t len, int64_t cap) { return len <= cap ? 1 : ceil_div(len, cap); }
+
+// Appends the segments of row i's range [b, e) cut into `pieces` near-equal
+// parts, with slots from `slot` on when the row has partial rows.
+template <class Push>
+void push_pieces(int64_t i, int32_t b, int32_t e, int64_t pieces, bool partial,
+                 int32_t& slot, Push&& push) {
+  const int64_t len = e - b;
+  for (int64_t q = 0; q < pieces; ++q) {
+    const int32_t sb = b + (int32_t)(q * len / pieces);
+    const int32_t se = b + (int32_t)((q + 1) * len / pieces);
+    push(make_int4((int)i, sb, se, partial ? slot++ : -1));
+  }
+}
+
+void upload_segs(const std::vector<int4>& v, DevBuf<int4>& d, hipStream_t st) {
+  d.reserve(std::max<int64_t>((int64_t)v.size(), 1), st);
+  if (!v.empty())
+    MC_HIP(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(int4),
+                          hipMemcpyHostToDevice, st));
+}
+
+}  // namespace
+
+// Banded form (see Schedule) with nb = kBands * t bands: rows of at least
+// kBandMinLen entries are cut at the band boundaries of their (sorted)
+// gathered indices, then by `cap`; band r belongs to XCD r % kBands, which
+// takes its bands in the order r % kBands, r % kBands + kBands, ... so that
+// its L2 holds one band at a time.  Shorter rows stay whole (or cut by `cap`)
+// and go to the XCDs with the fewest segments.  XCD x's segments take
+// workgroup slots x, x + kBands, ...; the slots left over hold padding.
+void band_schedule(const int32_t* ptr, const int32_t* idx, int64_t rows,
+                   int64_t gathered, int64_t cap, int nb, std::vector<int4>& segs,
+                   std::vector<int4>& fix, int32_t& slot) {
+  std::vector<std::vector<int4>> band(nb);
+  std::vector<int4> loose;
+  std::vector<int32_t> bound(nb + 1), cut(nb + 1);
+  for (int r = 0; r <= nb; ++r) bound[r] = (int32_t)(r * gathered / nb);
+  for (int64_t i = 0; i < rows; ++i) {
+    const int32_t b = ptr[i], e = ptr[i + 1];
+    const int64_t len = e - b;
+    if (len < kBandMinLen) {
+      const int64_t pieces = cap_pieces(len, cap);
+      if (pieces > 1) fix.push_back(make_int4((int)i, slot, (int)pieces, 0));
+      push_pieces(i, b, e, pieces, pieces > 1, slot,
+                  [&](int4 sg) { loose.push_back(sg); });
+      continue;
+    }
+    cut[0] = b;
+    cut[nb] = e;
+    for (int r = 1; r < nb; ++r)
+      cut[r] = (int32_t)(std::lower_bound(idx + cut[r - 1], idx + e, bound[r]) - idx);
+    int64_t pieces = 0;
+    for (int r = 0; r < nb; ++r)
+      if (cut[r + 1] > cut[r]) pieces += cap_pieces(cut[r + 1] - cut[r], cap);
+    if (pieces > 1) fix.push_back(make_int4((int)i, slot, (int)pieces, 0));
+    for (int r = 0; r < nb; ++r)
+      if (cut[r + 1] > cut[r])
+        push_pieces(i, cut[r], cut[r + 1], cap_pieces(cut[r + 1] - cut[r], cap),
+                    pieces > 1, slot, [&](int4 sg) { band[r].push_back(sg); });
+  }
+  std::vector<std::vector<int4>> xcd(kBands);
+  for (int r = 0; r < nb; ++r)
+    xcd[r % kBands].insert(xcd[r % kBands].end(), band[r].begin(), band[r].end());
+  for (const int4& sg : loose) {
+    int x = 0;
+    for (int t = 1; t < kBands; ++t)
+      if (xcd[t].size() < xcd[x].size()) x = t;
+    xcd[x].push_back(sg);
+  }
+  size_t nwg = 0;
+  for (int x = 0; x < kBands; ++x)
+    nwg = std::max(nwg, (size_t)ceil_div((int64_t)xcd[x].size(), kSpmmWaves));
+  segs.assign(nwg * kBands * kSpmmWaves, make_int4(-1, 0, 0, -1));
+  for (int x = 0; x < kBands; ++x)
+    for (size_t q = 0; q < xcd[x].size(); ++q)
+      segs[((q / kSpmmWaves) * kBands + x) * kSpmmWaves + q % kSpmmWaves] = xcd[x][q];
+}
+
 void build_schedule(const int32_t* ptr, int64_t rows, Schedule& S,
-                    hipStream_t st) {
+                    hipStream_t st, const int32_t* idx, int64_t gathered) {
   const int64_t nnz = ptr[rows];
   // segment length: about 16K segments in flight fill the chip (256 CUs x
   // several waves), capped so long rows of power-law matrices are split
@@ -244,31 +338,30 @@ void build_schedule(const int32_t* ptr, int64_t rows, Schedule& S,
   int32_t slot = 0;
   for (int64_t i = 0; i < rows; ++i) {
     const int32_t b = ptr[i], e = ptr[i + 1];
-    const int64_t len = e - b;
-    if (len <= cap) {
-      segs.push_back(make_int4((int)i, b, e, -1));
-      continue;
-    }
-    const int64_t pieces = ceil_div(len, cap);
-    fix.push_back(make_int4((int)i, slot, (int)pieces, 0));
-    for (int64_t q = 0; q < pieces; ++q) {
-      const int32_t sb = b + (int32_t)(q * len / pieces);
-      const int32_t se = b + (int32_t)((q + 1) * len / pieces);
-      segs.push_back(make_int4((int)i, sb, se, slot++));
-    }
+    const int64_t pieces = cap_pieces(e - b, cap);
+    if (pieces > 1) fix.push_back(make_int4((int)i, slot, (int)pieces, 0));
+    push_pieces(i, b, e, pieces, pieces > 1, slot, [&](int4 sg) { segs.push_back(sg); });
   }
   S.nseg = (int64_t)segs.size();
   S.nfix = (int64_t)fix.size();
   S.nslot = slot;
-  S.segs.reserve(std::max<int64_t>(S.nseg, 1), st);
-  S.fix.reserve(std::max<int64_t>(S.nfix, 1), st);
-  if (S.nseg)
-    MC_HIP(hipMemcpyAsync(S.segs.p, segs.data(), S.nseg * sizeof(int4),
-                          hipMemcpyHostToDevice, st));
-  if (S.nfix)
-    MC_HIP(hipMemcpyAsync(S.fix.p, fix.data(), S.nfix * sizeof(int4),
-                          hipMemcpyHostToDevice, st));
+  upload_segs(segs, S.segs, st);
+  upload_segs(fix, S.fix, st);
   MC_HIP(hipStreamSynchronize(st));
+  S.gathered = gathered;
+  S.short_rows = nnz < kBandMinLen * rows;
+  S.band_nseg = S.band_nfix = 0;
+  if (idx && gathered >= kBandMinRows && nnz > 0) {
+    std::vector<int4> bsegs, bfix;
+    int32_t bslot = 0;
+    band_schedule(ptr, idx, rows, gathered, cap, kBands, bsegs, bfix, bslot);
+    S.band_nseg = (int64_t)bsegs.size();
+    S.band_nfix = (int64_t)bfix.size();
+    S.nslot = std::max<int64_t>(S.nslot, bslot);
+    upload_segs(bsegs, S.band_segs, st);
+    upload_segs(bfix, S.band_fix, st);
+    MC_HIP(hipStreamSynchronize(st));
+  }
 }
 
 namespace {
@@ -351,6 +444,7 @@ __global__ __launch_bounds__(256) void spmm_kernel(
   const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (wave >= nseg) return;
   const int4 sg = segs[wave];
+  if (sg.x < 0) return;                        // padding of a banded schedule
   const int g = lane / BW;
   const int c = lane % BW;
   for (int c0 = 0; c0 < b; c0 += CB) {
@@ -425,11 +519,19 @@ void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
                  const XT* X, int64_t ldx, OT* out, int64_t ldo, int b,
                  AT* part, hipStream_t st) {
   if (S.nseg == 0 || b <= 0) return;
-  const int T = 256;
-  const unsigned grid = (unsigned)ceil_div(S.nseg, T / 64);
+  const int T = 64 * kSpmmWaves;
+  // the banded form for large panels: wide ones, or when most rows stay whole
+  const bool band = S.band_nseg > 0 &&
+                    S.gathered * (int64_t)b * (int64_t)sizeof(XT) >= kBandPanelBytes &&
+                    (b > kBandWide || S.short_rows);
+  const int64_t nseg = band ? S.band_nseg : S.nseg;
+  const int4* segs = band ? S.band_segs.p : S.segs.p;
+  const int64_t nfix = band ? S.band_nfix : S.nfix;
+  const int4* fix = band ? S.band_fix.p : S.fix.p;
+  const unsigned grid = (unsigned)ceil_div(nseg, kSpmmWaves);
 #define MC_SPMM(BW, CPL)                                                          \
   hipLaunchKernelGGL((spmm_kernel<VT, XT, AT, OT, BW, CPL>), dim3(grid), dim3(T), 0, \
-                     st, S.nseg, S.segs.p, idx, val, X, ldx, out, ldo, part, b)
+                     st, nseg, segs, idx, val, X, ldx, out, ldo, part, b)
   if (b <= 8)
     MC_SPMM(8, 1);
   else if (b <= 16)
@@ -468,10 +570,10 @@ void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
   }
 #undef MC_SPMM
   MC_CHECK_LAUNCH();
-  if (S.nfix) {
-    const int64_t work = S.nfix * b;
+  if (nfix) {
+    const int64_t work = nfix * b;
     hipLaunchKernelGGL((spmm_fixup_kernel<AT, OT>), dim3((unsigned)ceil_div(work, T)),
-                       dim3(T), 0, st, S.nfix, S.fix.p, part, out, ldo, b);
+                       dim3(T), 0, st, nfix, fix, part, out, ldo, b);
     MC_CHECK_LAUNCH();
   }
 }

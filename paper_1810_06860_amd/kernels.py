@@ -56,6 +56,31 @@ def spmm(m, n, rows, cols, vals, X, transpose=False, precision="fp64"):
     return out
 
 
+def band_schedule(ptr, idx, gathered, cap, bands=8):
+    """Banded SpMM schedule of a host CSR-like structure (host code only).
+
+    Returns (segs, fix, nslot): segs (nseg x 4: row, begin, end, slot) in
+    launch order, fix (nfix x 4: row, first slot, count, 0).
+    """
+    ptr = np.ascontiguousarray(ptr, dtype=np.int32)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    rows = ptr.size - 1
+    nseg, nfix, nslot = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    st = lib().mc_k_band_schedule(rows, _p(ptr, C.c_int32), _p(idx, C.c_int32),
+                                  gathered, cap, bands, None, C.byref(nseg), None,
+                                  C.byref(nfix), C.byref(nslot))
+    from ._ffi import MC_ERANGE
+    if st != MC_ERANGE:
+        check(st)
+    segs = np.zeros((max(nseg.value, 1), 4), np.int32)
+    fix = np.zeros((max(nfix.value, 1), 4), np.int32)
+    check(lib().mc_k_band_schedule(rows, _p(ptr, C.c_int32), _p(idx, C.c_int32),
+                                   gathered, cap, bands, _p(segs, C.c_int32),
+                                   C.byref(nseg), _p(fix, C.c_int32), C.byref(nfix),
+                                   C.byref(nslot)))
+    return segs[:nseg.value], fix[:nfix.value], nslot.value
+
+
 def gram(A, B=None, precision="fp64"):
     A = np.ascontiguousarray(A, dtype=np.float64)
     sym = B is None

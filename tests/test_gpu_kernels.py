@@ -292,3 +292,37 @@ def test_spmm_empty_rows_and_columns(K, transpose):
         assert np.max(np.abs(got - want) / scale) < 1e-14
         empty = np.flatnonzero(np.asarray(abs(A.T if transpose else A).sum(axis=1)).ravel() == 0)
         assert empty.size > 0 and np.all(got[empty] == 0.0)
+
+
+@pytest.mark.parametrize("m,n,b,precision", [
+    (20000, 4000, 40, "fp64"), (20000, 4000, 90, "fp32"), (20000, 4000, 300, "fp64"),
+    (20000, 600, 40, "fp64"), (20000, 600, 300, "fp64")])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_spmm_banded_large_panel(K, m, n, b, precision, transpose):
+    # a gathered dimension of 20,000 rows and a panel above 2 MiB have a
+    # banded schedule: rows of at least 256 entries are split at eight equal
+    # ranges of the gathered index (one per XCD) and summed by the fix-up.  It
+    # runs for wide panels (b > 128) and for structures with a mean row length
+    # under 256; the 600-column cases at b = 40 take the plain schedule of the
+    # same structure.  Power-law rows: some short and whole, some split.
+    if not transpose:
+        m, n = n, m
+    p = synth.ratings(m, n, 400_000, 3, seed_data=31)
+    rng = np.random.default_rng(b)
+    vals = rng.standard_normal(p.nnz)
+    A = scipy.sparse.csr_matrix((vals, (p.rows, p.cols)), shape=(m, n))
+    Ao = A.T.tocsr() if transpose else A
+    X = rng.standard_normal(((m if transpose else n), b))
+    assert X.shape[0] * b * (8 if precision == "fp64" else 4) >= 2 << 20
+    got = K.spmm(m, n, p.rows, p.cols, vals, X, transpose=transpose, precision=precision)
+    want = Ao @ X
+    scale = abs(Ao) @ np.abs(X) + 1e-300
+    lens = np.diff(Ao.indptr)
+    assert lens.max() >= 1024 and (lens < 256).any()
+    if precision == "fp64":
+        assert np.max(np.abs(got - want) / scale) < 1e-14
+    else:
+        u = 2.0 ** -24
+        assert np.max(np.abs(got - want) / scale) < (lens.max() + 2) * u * 1.01
+    empty = np.flatnonzero(lens == 0)
+    assert np.all(got[empty] == 0.0)
