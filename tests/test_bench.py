@@ -39,13 +39,18 @@ def test_roofline_picks_the_dominant_family():
     prof = {"spmm_fwd": dict(launches=10, ms=1.0, bytes=8e9, flops=1e9),
             "eigensolve": dict(launches=2, ms=3.0, bytes=0.0, flops=6e9),
             "rng": dict(launches=0, ms=0.0, bytes=0.0, flops=0.0)}
-    dom, roof = b.roofline(prof, "fp64", "no-such-workload")
-    assert dom == "eigensolve" and roof["bound"] == "alu" and roof["traffic"] is None
-    assert abs(roof["achieved"] - 6e9 / 2 / 1.5e-3 / 1e12) < 1e-3
-    prof["spmm_fwd"]["ms"] = 10.0
+    # the eigensolve (latency-bound) never takes the roofline while another
+    # family has time, even a larger share
     dom, roof = b.roofline(prof, "fp64", "no-such-workload")
     assert dom == "spmm_fwd" and roof["bound"] == "hbm" and roof["unit"] == "GB/s"
     assert abs(roof["frac"] - roof["achieved"] / 8000.0) < 1e-4
+    prof["gram"] = dict(launches=5, ms=2.0, bytes=1e8, flops=4e9)
+    dom, roof = b.roofline(prof, "fp64", "no-such-workload")
+    assert dom == "gram"
+    # alone, it reports its flop rate against the FP64 vector peak
+    dom, roof = b.roofline({"eigensolve": prof["eigensolve"]}, "fp64", "no-such-workload")
+    assert dom == "eigensolve" and roof["bound"] == "alu" and roof["traffic"] is None
+    assert abs(roof["achieved"] - 6e9 / 2 / 1.5e-3 / 1e12) < 1e-3
 
 
 def test_measured_traffic_is_tied_to_sources():
