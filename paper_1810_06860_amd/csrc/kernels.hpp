@@ -19,8 +19,10 @@ namespace mcsvt {
 // to workgroups r, r + kBands, r + 2 kBands, ...; the hardware hands
 // consecutive workgroups to the eight XCDs in turn, so each XCD's caches see
 // one range of the panel instead of all of it.  Splitting costs a partial row
-// and a reduction per piece: the banded form pays off for wide panels, and
-// for structures whose rows are mostly short enough to stay whole.
+// and a reduction per piece: narrow panels take the banded form when most
+// rows are short enough to stay whole, wide panels when a good share of the
+// entries lies in rows the bands split (without such rows the form only
+// reorders whole rows, which wide products lose by).
 constexpr int kBands = 8;
 constexpr int kSpmmWaves = 4;                      // wavefronts per SpMM workgroup
 constexpr int64_t kBandMinRows = 8192;             // gathered rows for a banded form
@@ -34,6 +36,7 @@ struct Schedule {
   DevBuf<int4> fix;
   int64_t gathered = 0;                        // rows of the gathered panel
   bool short_rows = false;                     // mean row length < kBandMinLen
+  bool long_share = false;                     // >= 1/4 of nnz in rows the bands split
   int64_t band_nseg = 0, band_nfix = 0;        // banded form; 0 if not built
   DevBuf<int4> band_segs;
   DevBuf<int4> band_fix;

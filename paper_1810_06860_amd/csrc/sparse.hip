@@ -350,6 +350,10 @@ void build_schedule(const int32_t* ptr, int64_t rows, Schedule& S,
   MC_HIP(hipStreamSynchronize(st));
   S.gathered = gathered;
   S.short_rows = nnz < kBandMinLen * rows;
+  int64_t in_long = 0;
+  for (int64_t i = 0; i < rows; ++i)
+    if (ptr[i + 1] - ptr[i] >= kBandMinLen) in_long += ptr[i + 1] - ptr[i];
+  S.long_share = 4 * in_long >= nnz;
   S.band_nseg = S.band_nfix = 0;
   if (idx && gathered >= kBandMinRows && nnz > 0) {
     std::vector<int4> bsegs, bfix;
@@ -520,10 +524,10 @@ void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
                  AT* part, hipStream_t st) {
   if (S.nseg == 0 || b <= 0) return;
   const int T = 64 * kSpmmWaves;
-  // the banded form for large panels: wide ones, or when most rows stay whole
+  // the banded form for large panels (see Schedule)
   const bool band = S.band_nseg > 0 &&
                     S.gathered * (int64_t)b * (int64_t)sizeof(XT) >= kBandPanelBytes &&
-                    (b > kBandWide || S.short_rows);
+                    (b > kBandWide ? S.long_share : S.short_rows);
   const int64_t nseg = band ? S.band_nseg : S.nseg;
   const int4* segs = band ? S.band_segs.p : S.segs.p;
   const int64_t nfix = band ? S.band_nfix : S.nfix;

@@ -301,10 +301,11 @@ def test_spmm_empty_rows_and_columns(K, transpose):
 def test_spmm_banded_large_panel(K, m, n, b, precision, transpose):
     # a gathered dimension of 20,000 rows and a panel above 2 MiB have a
     # banded schedule: rows of at least 256 entries are split at eight equal
-    # ranges of the gathered index (one per XCD) and summed by the fix-up.  It
-    # runs for wide panels (b > 128) and for structures with a mean row length
-    # under 256; the 600-column cases at b = 40 take the plain schedule of the
-    # same structure.  Power-law rows: some short and whole, some split.
+    # ranges of the gathered index (one per XCD) and summed by the fix-up.
+    # Narrow panels run it when the mean row length is under 256, wide ones
+    # (b > 128) when a quarter of the entries lie in split rows: every case
+    # here but the 600-row structures at b = 40, which take the plain
+    # schedule.  Power-law rows: some short and whole, some split.
     if not transpose:
         m, n = n, m
     p = synth.ratings(m, n, 400_000, 3, seed_data=31)
