@@ -612,21 +612,18 @@ double SolverT<P, VT, AT>::sddmm_finish() {
 }
 
 namespace {
+// The first `cols` columns of a row-major device panel into the caller's
+// (pageable) host array: one contiguous copy into library-owned host memory,
+// then the columns are picked and widened on the host.
 template <class P>
 void copy_cols_to_host(double* dst, int64_t ldd, const P* src, int64_t lds_,
                        int cols, int64_t rows, hipStream_t st) {
-  if constexpr (std::is_same<P, double>::value) {
-    MC_HIP(hipMemcpy2DAsync(dst, ldd * sizeof(double), src, lds_ * sizeof(double),
-                            cols * sizeof(double), rows, hipMemcpyDeviceToHost, st));
-    MC_HIP(hipStreamSynchronize(st));
-  } else {
-    std::vector<P> tmp((size_t)rows * lds_);
-    MC_HIP(hipMemcpyAsync(tmp.data(), src, tmp.size() * sizeof(P),
-                          hipMemcpyDeviceToHost, st));
-    MC_HIP(hipStreamSynchronize(st));
-    for (int64_t i = 0; i < rows; ++i)
-      for (int j = 0; j < cols; ++j) dst[i * ldd + j] = (double)tmp[i * lds_ + j];
-  }
+  std::vector<P> tmp((size_t)rows * lds_);
+  MC_HIP(hipMemcpyAsync(tmp.data(), src, tmp.size() * sizeof(P),
+                        hipMemcpyDeviceToHost, st));
+  MC_HIP(hipStreamSynchronize(st));
+  for (int64_t i = 0; i < rows; ++i)
+    for (int j = 0; j < cols; ++j) dst[i * ldd + j] = (double)tmp[i * lds_ + j];
 }
 }  // namespace
 
