@@ -89,10 +89,11 @@ mc_status mc_k_sddmm(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
  * no device is touched).  This is the schedule the SpMM uses once the dense
  * panel it gathers from outgrows one XCD's L2: the gathered index range
  * [0, gathered) is cut into `bands` equal ranges (a positive multiple of 8);
- * rows of at least 256 entries are split at the range boundaries, then into
- * pieces of at most `cap` entries; shorter rows into pieces of at most `cap`.
- * Band r belongs to XCD r % 8, which takes its bands in increasing r; rows
- * shorter than 256 go to the XCDs with the fewest segments.
+ * rows of at least max(256, 4 cap) entries are split at the range
+ * boundaries, then into pieces of at most `cap` entries; shorter rows into
+ * pieces of at most `cap`.  Band r belongs to XCD r % 8, which takes its
+ * bands in increasing r; the shorter rows go to the XCDs with the fewest
+ * segments.
  *
  * Inputs: ptr (rows + 1, ptr[0] = 0, non-decreasing) and idx (ptr[rows]
  * entries in [0, gathered), increasing within each row), both host arrays

@@ -18,24 +18,25 @@ namespace mcsvt {
 // long rows are split at the range boundaries, and the pieces of range r go
 // to workgroups r, r + kBands, r + 2 kBands, ...; the hardware hands
 // consecutive workgroups to the eight XCDs in turn, so each XCD's caches see
-// one range of the panel instead of all of it.  Splitting costs a partial row
-// and a reduction per piece: narrow panels take the banded form when most
-// rows are short enough to stay whole, wide panels when a good share of the
-// entries lies in rows the bands split (without such rows the form only
-// reorders whole rows, which wide products lose by).
+// one range of the panel instead of all of it.  Only rows long enough that
+// their band pieces stay near the segment length are split (band_split_len),
+// so the banded form has about as many segments as the plain one.  Narrow
+// panels take it whenever the panel is large; wide panels when a good share
+// of the entries lies in split rows (without such rows the form only
+// reorders whole rows across the XCDs, which gives them no locality).
 constexpr int kBands = 8;
 constexpr int kSpmmWaves = 4;                      // wavefronts per SpMM workgroup
 constexpr int64_t kBandMinRows = 8192;             // gathered rows for a banded form
-constexpr int64_t kBandMinLen = 256;               // shorter rows are not split by band
 constexpr int64_t kBandPanelBytes = 2 << 20;       // smaller panels stay unbanded
-constexpr int kBandWide = 128;                     // wider panels take it regardless
+constexpr int kBandWide = 128;                     // wider panels need split rows
+// shortest row the banded form splits, for segments of at most `cap` entries
+inline int64_t band_split_len(int64_t cap) { return cap * 4 > 256 ? cap * 4 : 256; }
 struct Schedule {
   int64_t nseg = 0, nfix = 0;
   int64_t nslot = 0;                           // partial rows, either form
   DevBuf<int4> segs;
   DevBuf<int4> fix;
   int64_t gathered = 0;                        // rows of the gathered panel
-  bool short_rows = false;                     // mean row length < kBandMinLen
   bool long_share = false;                     // >= 1/4 of nnz in rows the bands split
   int64_t band_nseg = 0, band_nfix = 0;        // banded form; 0 if not built
   DevBuf<int4> band_segs;

@@ -272,7 +272,7 @@ void upload_segs(const std::vector<int4>& v, DevBuf<int4>& d, hipStream_t st) {
 }  // namespace
 
 // Banded form (see Schedule) with nb = kBands * t bands: rows of at least
-// kBandMinLen entries are cut at the band boundaries of their (sorted)
+// band_split_len(cap) entries are cut at the band boundaries of their (sorted)
 // gathered indices, then by `cap`; band r belongs to XCD r % kBands, which
 // takes its bands in the order r % kBands, r % kBands + kBands, ... so that
 // its L2 holds one band at a time.  Shorter rows stay whole (or cut by `cap`)
@@ -285,10 +285,11 @@ void band_schedule(const int32_t* ptr, const int32_t* idx, int64_t rows,
   std::vector<int4> loose;
   std::vector<int32_t> bound(nb + 1), cut(nb + 1);
   for (int r = 0; r <= nb; ++r) bound[r] = (int32_t)(r * gathered / nb);
+  const int64_t split = band_split_len(cap);
   for (int64_t i = 0; i < rows; ++i) {
     const int32_t b = ptr[i], e = ptr[i + 1];
     const int64_t len = e - b;
-    if (len < kBandMinLen) {
+    if (len < split) {
       const int64_t pieces = cap_pieces(len, cap);
       if (pieces > 1) fix.push_back(make_int4((int)i, slot, (int)pieces, 0));
       push_pieces(i, b, e, pieces, pieces > 1, slot,
@@ -349,10 +350,9 @@ void build_schedule(const int32_t* ptr, int64_t rows, Schedule& S,
   upload_segs(fix, S.fix, st);
   MC_HIP(hipStreamSynchronize(st));
   S.gathered = gathered;
-  S.short_rows = nnz < kBandMinLen * rows;
   int64_t in_long = 0;
   for (int64_t i = 0; i < rows; ++i)
-    if (ptr[i + 1] - ptr[i] >= kBandMinLen) in_long += ptr[i + 1] - ptr[i];
+    if (ptr[i + 1] - ptr[i] >= band_split_len(cap)) in_long += ptr[i + 1] - ptr[i];
   S.long_share = 4 * in_long >= nnz;
   S.band_nseg = S.band_nfix = 0;
   if (idx && gathered >= kBandMinRows && nnz > 0) {
@@ -527,7 +527,7 @@ void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
   // the banded form for large panels (see Schedule)
   const bool band = S.band_nseg > 0 &&
                     S.gathered * (int64_t)b * (int64_t)sizeof(XT) >= kBandPanelBytes &&
-                    (b > kBandWide ? S.long_share : S.short_rows);
+                    (b <= kBandWide || S.long_share);
   const int64_t nseg = band ? S.band_nseg : S.nseg;
   const int4* segs = band ? S.band_segs.p : S.segs.p;
   const int64_t nfix = band ? S.band_nfix : S.nfix;

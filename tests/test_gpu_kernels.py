@@ -299,13 +299,11 @@ def test_spmm_empty_rows_and_columns(K, transpose):
     (20000, 600, 40, "fp64"), (20000, 600, 300, "fp64")])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_spmm_banded_large_panel(K, m, n, b, precision, transpose):
-    # a gathered dimension of 20,000 rows and a panel above 2 MiB have a
-    # banded schedule: rows of at least 256 entries are split at eight equal
-    # ranges of the gathered index (one per XCD) and summed by the fix-up.
-    # Narrow panels run it when the mean row length is under 256, wide ones
-    # (b > 128) when a quarter of the entries lie in split rows: every case
-    # here but the 600-row structures at b = 40, which take the plain
-    # schedule.  Power-law rows: some short and whole, some split.
+    # a gathered dimension of 20,000 rows and a panel above 2 MiB run the
+    # banded schedule: rows of at least max(256, 4 cap) entries (256 at this
+    # nnz) are split at eight equal ranges of the gathered index (one per XCD)
+    # and summed by the fix-up.  Power-law rows: some short and whole, some
+    # split; the wide cases have over a quarter of their entries in split rows.
     if not transpose:
         m, n = n, m
     p = synth.ratings(m, n, 400_000, 3, seed_data=31)

@@ -10,7 +10,12 @@ import pytest
 
 import synth
 
-WAVES, XCDS, MIN_LEN = 4, 8, 256
+WAVES, XCDS = 4, 8
+
+
+def split_len(cap):
+    # shortest row the banded form splits at the band boundaries
+    return max(256, 4 * cap)
 
 
 @pytest.fixture(scope="module")
@@ -19,12 +24,12 @@ def K():
     return kernels
 
 
-def _structure(rows, gathered, seed):
+def _structure(rows, gathered, cap, seed):
     rng = np.random.default_rng(seed)
-    lens = np.where(rng.random(rows) < 0.25, rng.integers(0, 3000, rows),
+    lens = np.where(rng.random(rows) < 0.25, rng.integers(0, 12 * cap, rows),
                     rng.integers(0, 300, rows))
     lens[rng.random(rows) < 0.1] = 0
-    edge = [MIN_LEN - 1, MIN_LEN, MIN_LEN + 1]             # around the split threshold
+    edge = [split_len(cap) - 1, split_len(cap), split_len(cap) + 1]   # around the threshold
     lens[:3] = edge[:min(rows, 3)]
     lens = np.minimum(lens, gathered)
     idx = [np.sort(rng.choice(gathered, size=int(k), replace=False)) for k in lens]
@@ -53,7 +58,7 @@ def _check(ptr, idx, gathered, cap, bands, segs, fix, nslot):
         else:
             assert slot_owner[slot] == -1
             slot_owner[slot] = row
-        if ptr[row + 1] - ptr[row] >= MIN_LEN and e > b:
+        if ptr[row + 1] - ptr[row] >= split_len(cap) and e > b:
             band = np.searchsorted(bound, idx[b], side="right") - 1
             # the whole piece lies in one band, and that band is this XCD's
             assert bound[band] <= idx[b] and idx[e - 1] < bound[band + 1]
@@ -75,7 +80,7 @@ def _check(ptr, idx, gathered, cap, bands, segs, fix, nslot):
     (2, 20000, 64, 8, 1), (37, 16384, 64, 8, 2), (500, 50021, 611, 8, 3),
     (300, 9000, 128, 16, 4), (800, 70001, 1024, 32, 5)])
 def test_band_schedule_invariants(K, rows, gathered, cap, bands, seed):
-    ptr, idx = _structure(rows, gathered, seed)
+    ptr, idx = _structure(rows, gathered, cap, seed)
     segs, fix, nslot = K.band_schedule(ptr, idx, gathered, cap, bands)
     _check(ptr, idx, gathered, cap, bands, segs, fix, nslot)
 
