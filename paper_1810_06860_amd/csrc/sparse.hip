@@ -544,10 +544,16 @@ void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
     MC_SPMM(8, 3);
   else if (b <= 32)
     MC_SPMM(16, 2);
+  else if (b <= 40)
+    MC_SPMM(8, 5);
   else if (b <= 48)
     MC_SPMM(16, 3);
+  else if (b <= 56)
+    MC_SPMM(8, 7);
   else if (b <= 64)
     MC_SPMM(16, 4);
+  else if (b <= 72)
+    MC_SPMM(8, 9);
   else if (b <= 80)
     MC_SPMM(16, 5);
   else if (b <= 96)

@@ -60,7 +60,7 @@ def test_layout_rejects_duplicates_and_range(K):
     assert e.value.status == MC_ERANGE
 
 
-@pytest.mark.parametrize("b", [1, 5, 16, 21, 24, 33, 48, 64, 70, 80, 90, 110, 128, 200, 300,
+@pytest.mark.parametrize("b", [1, 5, 16, 21, 24, 33, 40, 48, 52, 64, 70, 72, 80, 90, 110, 128, 200, 300,
                                330, 400, 448, 520, 1100])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_spmm_fp64(K, b, transpose):
@@ -295,7 +295,8 @@ def test_spmm_empty_rows_and_columns(K, transpose):
 
 
 @pytest.mark.parametrize("m,n,b,precision", [
-    (20000, 4000, 40, "fp64"), (20000, 4000, 90, "fp32"), (20000, 4000, 300, "fp64"),
+    (20000, 4000, 40, "fp64"), (20000, 4000, 55, "fp32"), (20000, 4000, 90, "fp32"),
+    (20000, 4000, 300, "fp64"),
     (20000, 600, 40, "fp64"), (20000, 600, 300, "fp64")])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_spmm_banded_large_panel(K, m, n, b, precision, transpose):
