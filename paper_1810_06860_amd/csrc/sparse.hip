@@ -558,6 +558,8 @@ void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
     MC_SPMM(16, 5);
   else if (b <= 96)
     MC_SPMM(16, 6);
+  else if (b <= 112)
+    MC_SPMM(16, 7);
   else if (b <= 128)
     MC_SPMM(32, 4);
   else {

@@ -60,7 +60,7 @@ def test_layout_rejects_duplicates_and_range(K):
     assert e.value.status == MC_ERANGE
 
 
-@pytest.mark.parametrize("b", [1, 5, 16, 21, 24, 33, 40, 48, 52, 64, 70, 72, 80, 90, 110, 128, 200, 300,
+@pytest.mark.parametrize("b", [1, 5, 16, 21, 24, 33, 40, 48, 52, 64, 70, 72, 80, 90, 97, 110, 112, 113, 128, 200, 300,
                                330, 400, 448, 520, 1100])
 @pytest.mark.parametrize("transpose", [False, True])
 def test_spmm_fp64(K, b, transpose):
