@@ -31,6 +31,18 @@ constexpr int64_t kBandPanelBytes = 2 << 20;       // smaller panels stay unband
 constexpr int kBandWide = 128;                     // wider panels need split rows
 // shortest row the banded form splits, for segments of at most `cap` entries
 inline int64_t band_split_len(int64_t cap) { return cap * 4 > 256 ? cap * 4 : 256; }
+// segment length of the work schedules of a structure with nnz entries: about
+// 16K segments in flight fill the chip (256 CUs x several waves), capped so
+// long rows of power-law matrices are split
+inline int64_t spmm_segment_cap(int64_t nnz) {
+  return std::min<int64_t>(1024, std::max<int64_t>(64, ceil_div(nnz, 16384)));
+}
+// upper bound of the partial rows of either schedule form: a row split in the
+// plain form (len > cap) has ceil(len / cap) < 2 len / cap pieces, one split
+// at the bands (len >= 4 cap) at most len / cap + kBands <= 3 len / cap
+inline int64_t spmm_slot_bound(int64_t nnz) {
+  return 3 * ceil_div(nnz, spmm_segment_cap(nnz));
+}
 struct Schedule {
   int64_t nseg = 0, nfix = 0;
   int64_t nslot = 0;                           // partial rows, either form

@@ -273,7 +273,14 @@ size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& p
   const int64_t mx = std::max(m, n);
   size_t bytes = 0;
   bytes += (size_t)nnz * (8 * 3 + 4 * 6);                 // values + layout
-  bytes += (size_t)(m + n + 2) * 4 + (size_t)(m + n) * 16; // pointers + schedules
+  // pointers; work schedules of both directions: plain segments and fix-ups
+  // (at most rows + slots each), and where a banded form is built its
+  // segments with their padding (at most kBands times the live ones)
+  const int64_t slots = spmm_slot_bound(nnz);
+  bytes += (size_t)(m + n + 2) * 4 + (size_t)16 * (2 * (m + n) + 4 * slots);
+  for (int64_t g : {n, m})
+    if (g >= kBandMinRows)
+      bytes += (size_t)16 * (kBands * (mx + slots) + mx + slots);
   bytes += (size_t)8 * (n * b + 2 * m * L + m * std::max(b, k) + m * b + n * b +
                         n * L + L * L + L * b + 2 * b * b + m * k + n * k +
                         L * k + 4 * L);
@@ -284,7 +291,8 @@ size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& p
   const int64_t Lb = std::min<int64_t>(L, 1024), kb = std::min<int64_t>(Lb, 140);
   bytes += (size_t)8 * (L * L);
   bytes += (size_t)8 * TriBigWork::doubles((int)Lb, (int)kb);
-  bytes += (size_t)8 * (mx * L / 4 + ceil_div(nnz, 256) + nnz);
+  // SpMM partial rows (slots x the widest panel), SDDMM partials, P_Phi(X)
+  bytes += (size_t)8 * (slots * std::max({b, L, k}) + ceil_div(nnz, 256) + nnz);
   return bytes;
 }
 

@@ -330,9 +330,7 @@ void band_schedule(const int32_t* ptr, const int32_t* idx, int64_t rows,
 void build_schedule(const int32_t* ptr, int64_t rows, Schedule& S,
                     hipStream_t st, const int32_t* idx, int64_t gathered) {
   const int64_t nnz = ptr[rows];
-  // segment length: about 16K segments in flight fill the chip (256 CUs x
-  // several waves), capped so long rows of power-law matrices are split
-  const int64_t cap = std::min<int64_t>(1024, std::max<int64_t>(64, ceil_div(nnz, 16384)));
+  const int64_t cap = spmm_segment_cap(nnz);
   std::vector<int4> segs;
   std::vector<int4> fix;
   segs.reserve(rows + 16);

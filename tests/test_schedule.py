@@ -74,6 +74,10 @@ def _check(ptr, idx, gathered, cap, bands, segs, fix, nslot):
         assert pieces[row] == count and direct[row] == 0
     assert np.all(direct + fixed == 1)
     assert np.all(pieces[direct == 1] == 1)
+    # a split row has at most len / cap + bands <= (1 + bands / 4) len / cap
+    # pieces (it is split only from 4 cap entries on): with the 8 bands of
+    # the library, the 3 len / cap the footprint reserves partial rows for
+    assert nslot <= (1 + bands // 4) * -(-idx.size // cap)
 
 
 @pytest.mark.parametrize("rows,gathered,cap,bands,seed", [
