@@ -242,8 +242,6 @@ int build_layout(int64_t m, int64_t n, int64_t nnz, const int64_t* d_rows,
   return kOK;
 }
 
-// Split rows into work segments of at most `cap` entries.  Rows that need
-// several segments get partial slots and a fix-up record.
 namespace {
 
 // pieces of [b, e) of at most `cap` entries each
@@ -327,6 +325,9 @@ void band_schedule(const int32_t* ptr, const int32_t* idx, int64_t rows,
       segs[((q / kSpmmWaves) * kBands + x) * kSpmmWaves + q % kSpmmWaves] = xcd[x][q];
 }
 
+// Split rows into work segments of at most `cap` entries.  Rows that need
+// several segments get partial slots and a fix-up record.  With the gathered
+// indices given and a large gathered dimension, the banded form as well.
 void build_schedule(const int32_t* ptr, int64_t rows, Schedule& S,
                     hipStream_t st, const int32_t* idx, int64_t gathered) {
   const int64_t nnz = ptr[rows];
