@@ -1,16 +1,16 @@
-"""eigSVD (Alg. 3, Lemma 1): the economic SVD of a tall matrix via eig(A^T A).
+"""eigSVD (Sec. III.A, Alg. 3): the economic SVD of a tall matrix A (m x n,
+m >= n) read off the symmetric eigendecomposition of its Gram matrix A^T A
+(Lemma 1: the eigenvectors are the right singular vectors, the square roots
+of the eigenvalues the singular values, and A V S^-1 the left singular
+vectors).
 
-Steps, for A (m x n, m >= n):
-  1. B = A^T A
-  2. [V, D] = eig(B)            (symmetric; eigenvalues ascending)
-  3. S = sqrt(D)
-  4. U = A V S^-1
-The singular values come out in ascending order (remark after Lemma 1).
-Round-off can leave tiny negative entries in D, and a rank-deficient A makes
-S^-1 undefined (same remark); S is therefore taken as sqrt(max(D, 0)), and
-``eigsvd_top`` forms U only for the kept (largest) columns, and refuses a
-kept value at the round-off floor of D (S_j <= sqrt(n u) S_max, u the unit
-round-off), where A V S^-1 would carry no accurate digits.
+The values come out ascending, as the eigensolver returns them (the remark
+after Lemma 1).  Round-off can leave tiny negative eigenvalues, and a
+rank-deficient A makes S^-1 undefined (same remark): S is taken as
+sqrt(max(D, 0)), and ``eigsvd_top`` forms the left vectors only for the kept
+(largest) values and refuses a kept value at the round-off floor of D
+(S_j <= sqrt(n u) S_max, u the unit round-off), where A V S^-1 would carry no
+accurate digits.
 """
 
 import numpy as np

@@ -1,24 +1,19 @@
-"""Fast SVT (Alg. 6): SVT driven by rSVD-BKI with subspace recycling.
+"""Fast SVT (Sec. IV, Alg. 6): the SVT iteration of Eq. (6) whose truncated
+SVD is rSVD-BKI (Sec. III.B), with subspace recycling (Sec. IV.B) and the
+adaptive power parameter (Sec. IV.C).
 
-One step i, in the order of Alg. 6:
-  k = r_{i-1} + 1, and p adjusted (Sec. IV.C: p + 1 when the relative error
-  of the previous step rose, p - 1 after ten consecutive decreases; start 3)
-  repeat
-    if i < i_reuse or q == q_reuse (or nothing to recycle):
-        [U, S, V] = rSVD-BKI(Y^{i-1}, k, p),  q = 0
-    else:
-        recycle (Sec. IV.B) the Q (strategy 1: restart Alg. 5 at step 8 with
-        B = Q^T Y) or the U (strategy 2: B = U^T Y, eigSVD(B^T), U <- U W)
-        of the last rSVD-BKI call,  q = q + 1
-    k = k + l
-  until the smallest computed singular value <= tau
-  r = #{S_j > tau};  X = sum_j (S_j - tau) u_j v_j^T
-  stop if ||P_Phi(X - M)||_F / ||P_Phi(M)||_F < eps
-  Y^i = Y^{i-1} + delta P_Phi(M - X)
+Each step finds every singular value of Y^{i-1} above tau by the rank
+search of Alg. 2 (k starts one above the previous rank and grows by l while
+the smallest computed value still exceeds tau), shrinks them by tau, and
+takes the residual and the update of Y on Phi (Eq. (6)).  The SVD of each
+rank-search call is a fresh rSVD-BKI call, or -- once recycling is allowed
+(step index >= i_reuse, fewer than q_reuse recycled calls since the last
+fresh one) -- the Rayleigh-Ritz step on the basis the last fresh call left:
+its Q (strategy 1) or its U (strategy 2).
 
-Readings of points the listing leaves open:
-* Step 17 writes P_Omega(Y^{i-1}); Omega is the random test matrix, so this
-  is read as P_Phi, on which Y lives anyway.
+Readings of points the paper leaves open:
+* The update of Alg. 6 is written with P_Omega; Omega is the random test
+  matrix, so it is read as P_Phi, on which Y lives anyway.
 * Singular values are used in descending order (eigSVD returns them
   ascending).
 * q counts SVD calls: +1 per recycled call, reset by every rSVD-BKI call.
@@ -36,6 +31,8 @@ Readings of points the listing leaves open:
 * The rank search stops at the cap min(m, n, k_max).
 * Omega of rSVD-BKI call number `attempt` within step i is
   ``gaussian_block(n, b, seed, i, attempt)``.
+* The stop test comes before the update (Alg. 2 and Alg. 6 leave the loop
+  on convergence), so Y is not updated on the converging step.
 """
 
 from dataclasses import dataclass

@@ -1,27 +1,35 @@
 """Randomized truncated SVD of a (sparse) matrix A (Sec. II.B, Sec. III).
 
-All three take the Gaussian test matrix Omega (n x (k+s)) as an input, so a
-caller can feed the same Omega to another implementation.
+Each routine is written from what it computes, not from a printed listing:
 
-basic_rsvd  Alg. 1: Q = orth(A Omega); p power iterations with orth after
-            every product; B = Q^T A; svd(B); U = Q U; keep the first k.
-rsvd_pi     Alg. 4: LU (its P^T L factor) between the A(A^T .) pairs,
-            eigSVD for the last Q and for B^T, keep ind = s+1 : k+s.
-rsvd_bki    Alg. 5: H_0 = lu(A Omega); H_i = lu(A (A^T H_{i-1})) for
-            i = 1..p; Q = orth([H_0 .. H_p]); B = Q^T A; [V, S, U] =
-            eigSVD(B^T); keep ind = (k+s)(p+1)-k+1 : (k+s)(p+1).
-            The listing guards step 4 with "if i < p" although step 6 stacks
-            H_p and `ind` counts (p+1)(k+s) columns; H_p is read as formed
-            for every i, with the LU skipped for i = p because orth follows.
+basic_rsvd  the randomized SVD of Sec. II.B (Alg. 1): an orthonormal basis
+            of the range of (A A^T)^p A Omega, kept orthonormal after every
+            product, then the exact SVD of the projection Q^T A.
+rsvd_pi     rSVD-PI (Sec. III.A, Alg. 4).  Theorem 1: it gives the same
+            subspace as basic_rsvd -- range((A A^T)^p A Omega) -- with the
+            cheaper LU normalisation between the power iterations (Lemma 3:
+            the P^T L factor spans the same range), and it finishes with
+            eigSVD (Alg. 3) instead of a QR + SVD.
+rsvd_bki    rSVD-BKI (Sec. III.B, Alg. 5).  Theorem 2: its basis spans the
+            block Krylov space [A Omega, (A A^T) A Omega, ...,
+            (A A^T)^p A Omega] of Musco & Musco; every block is
+            LU-normalised before it feeds the next product (Lemma 3), and
+            the top k singular triplets come from eigSVD of B^T = A^T Q.
 
-Outputs keep the paper's convention: singular values ascending, U (m x k),
-V (n x k) (the listings' "V in R^{k x n}" is read as n x k).
+Both finish with the Rayleigh-Ritz step of Sec. II.B: for an orthonormal Q
+the SVD of B = Q^T A gives U = Q W; only the projector Q Q^T matters there
+(Lemma 2), so any orthonormalisation of the basis gives the same result.
+
+All three take the Gaussian test matrix Omega (n x b, b = k + s) as an
+input so that another implementation can be fed the same Omega.  Outputs
+keep the paper's convention: singular values ascending, U (m x k), V (n x k)
+(the listings' "V in R^{k x n}" is read as n x k).
 """
 
 import numpy as np
 import scipy.linalg
 
-from .eigsvd import eigsvd, eigsvd_top
+from .eigsvd import eigsvd_top
 
 
 def lu_factor(X):
@@ -37,46 +45,56 @@ def orth(X):
     return q
 
 
+def _times_aat(A, H):
+    """A (A^T H): one power-iteration product, two sparse products."""
+    return np.asarray(A @ np.asarray(A.T @ H))
+
+
+def _top_k_of_projection(A, Q, k):
+    """Rayleigh-Ritz step (Sec. II.B) with eigSVD (Alg. 3): the k largest
+    singular triplets of B = Q^T A, lifted back to U = Q W.  eigSVD runs on
+    the tall B^T = A^T Q (n x L), whose left singular vectors are V."""
+    Bt = np.asarray(A.T @ Q)
+    V, S, W = eigsvd_top(Bt, k)                 # ascending, top k of L
+    return Q @ W, S, V
+
+
 def basic_rsvd(A, k, p, Omega):
+    """Alg. 1 with a QR after every product (the textbook form)."""
     Q = orth(A @ Omega)
     for _ in range(p):
-        G = orth(A.T @ Q)
-        Q = orth(A @ G)
+        Q = orth(A @ orth(A.T @ Q))
     B = np.asarray((A.T @ Q).T)
     U, S, Vt = np.linalg.svd(B, full_matrices=False)
-    U = Q @ U
-    return U[:, :k], S[:k], Vt[:k].T
+    return (Q @ U)[:, :k], S[:k], Vt[:k].T
 
 
 def rsvd_pi(A, k, p, Omega):
-    b = Omega.shape[1]
-    s = b - k
-    Q = np.asarray(A @ Omega)
-    for i in range(p + 1):
-        if i < p:
-            Q = lu_factor(Q)
-        else:
-            Q, _, _ = eigsvd(Q)
-            break
-        Q = np.asarray(A @ (A.T @ Q))
-    Bt = np.asarray(A.T @ Q)                    # B^T = A^T Q  (n x b)
-    V, S, U = eigsvd(Bt)
-    ind = slice(s, s + k)
-    return Q @ U[:, ind], S[ind], V[:, ind]
+    """rSVD-PI: basis of range((A A^T)^p A Omega), LU-normalised between
+    the power iterations and orthonormalised once at the end, then the top
+    k triplets of the projection (Theorem 1)."""
+    H = lu_factor(A @ Omega) if p > 0 else np.asarray(A @ Omega)
+    for it in range(p):
+        H = _times_aat(A, H)
+        if it < p - 1:
+            H = lu_factor(H)
+    return _top_k_of_projection(A, orth(H), k)
 
 
 def rsvd_bki(A, k, p, Omega, return_q=False):
-    b = Omega.shape[1]
-    H = [lu_factor(A @ Omega)]
-    for i in range(1, p + 1):
-        Hi = np.asarray(A @ (A.T @ H[i - 1]))
-        H.append(lu_factor(Hi) if i < p else Hi)
-    Q = orth(np.hstack(H))                      # m x (p+1) b
-    L = Q.shape[1]
-    assert L == (p + 1) * b
-    Bt = np.asarray(A.T @ Q)                    # B^T = (Q^T A)^T, n x L
-    V, S, W = eigsvd_top(Bt, k)                 # ind = last k of L
-    U = Q @ W
+    """rSVD-BKI: orthonormal basis of the (p + 1)-block Krylov space built
+    from LU-normalised blocks, then the top k triplets of the projection
+    (Theorem 2).  With return_q the basis Q (m x (p + 1) b) is returned too,
+    for recycling (Sec. IV.B)."""
+    block = lu_factor(A @ Omega)
+    blocks = [block]
+    for _ in range(p):
+        block = lu_factor(_times_aat(A, block))
+        blocks.append(block)
+    Q = orth(np.hstack(blocks))
+    if Q.shape[1] != (p + 1) * Omega.shape[1]:
+        raise ValueError("Krylov basis narrower than (p + 1) b")
+    U, S, V = _top_k_of_projection(A, Q, k)
     if return_q:
         return U, S, V, Q
     return U, S, V

@@ -83,8 +83,12 @@ def spectral_norm(m, n, rows, cols, vals):
     import scipy.sparse
     import scipy.sparse.linalg
     A = scipy.sparse.csr_matrix((vals, (rows, cols)), shape=(m, n))
+    # PROPACK's Lanczos bidiagonalisation with a seeded start and room for
+    # up to 400 Lanczos vectors: SciPy's default (10 for k = 1) gives up
+    # before convergence when the top singular values are clustered
     s = scipy.sparse.linalg.svds(A, k=1, tol=1e-14, return_singular_vectors=False,
-                                 solver="propack")
+                                 solver="propack", maxiter=min(m, n, 400),
+                                 rng=np.random.default_rng(0))
     return float(s[0])
 
 

@@ -140,9 +140,10 @@ def test_guarded_recycling_matches_plain(strategy):
     plain = fast_svt(p.m, p.n, p.rows, p.cols, p.vals, base)
     rec = fast_svt(p.m, p.n, p.rows, p.cols, p.vals,
                    dict(base, recycle=strategy, i_reuse=20, q_reuse=3,
-                        ritz_tol=1e-4))
+                        ritz_tol=1e-3))
     assert plain.converged and rec.converged
-    assert rec.extra["recycled"] > 0
+    # recycled counts every attempt, rejected ones included
+    assert rec.extra["recycled"] - rec.extra["rejected"] > 0
     rel = np.linalg.norm(rec.dense() - plain.dense()) / np.linalg.norm(plain.dense())
     assert rel < 1e-3
 
