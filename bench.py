@@ -2,14 +2,20 @@
 """Fast-SVT benchmark on one MI355X: SVT steps/s plus the roofline of the
 dominant kernel and the CPU oracle timed beside it.
 
-    python bench.py [--steps K] [--warmup W] [--workload image1024]
+    python bench.py [--steps K] [--warmup W] [--workload ratings140k]
                     [--precision fp64] [--cpu-seconds 30]
 
-A "step" is one iteration of the fast SVT algorithm: the rank search with
-rSVD-BKI (or a recycled basis), shrinkage, the residual on Phi and the update
-of Y.  The solve starts untimed (problem set-up and W warm-up steps), then K
+A "step" is one iteration of the fast SVT algorithm (Alg. 6): the rank
+search with rSVD-BKI (or a recycled basis), shrinkage, the residual on Phi
+and the update of Y.  The default workload is the largest rating shape
+(140,000 x 27,000, 2.0e7 observed integer ratings, rank cap 100) in FP64.
+The solve starts untimed (problem set-up and W warm-up steps), then K
 consecutive steps are timed with the stream synchronised on both sides.  All
 inputs and solver state are resident in HBM for the whole timed region.
+Beside that window the line reports the same solve run whole (steps/s from
+the first step to i_max or convergence), the BF16 form against it, per-kernel
+times of the window, the CPU oracle on the host cores and its step-by-step
+agreement with a fresh GPU solve.
 
 Prints one JSON line.
 """
@@ -71,9 +77,9 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=290)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="image1024")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="ratings140k")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
     ap.add_argument("--prof-steps", type=int, default=0,
@@ -98,10 +104,16 @@ def parse():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for "
                          "calibrating HBM counters under a profiler)")
+    ap.add_argument("--whole", type=int, default=1,
+                    help="1: also run the workload's whole solve (and its BF16 "
+                         "form) and report steps/s over it")
+    ap.add_argument("--modes", default="bf16",
+                    help="reduced-precision forms run whole beside the FP64 "
+                         "one (comma list of fp32, bf16; empty: none)")
     return ap.parse_args()
 
 
-def roofline(prof, prec, workload):
+def roofline(prof, prec, workload, copy_gbps=None):
     fams = {k: v for k, v in prof.items() if v["launches"] > 0 and v["ms"] > 0}
     if not fams:
         return None, None
@@ -112,16 +124,24 @@ def roofline(prof, prec, workload):
     dom = max(cand, key=lambda k: fams[k]["ms"])
     v = fams[dom]
     per_launch_ms = v["ms"] / v["launches"]
-    if dom in HBM_FAMILIES:
+    # FP64 arithmetic in the FP64 form, FP32 accumulation in the others
+    peak = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
+    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)            # FLOP per byte
+    intensity = v["flops"] / v["bytes"] if v["bytes"] else float("inf")
+    if dom in HBM_FAMILIES and intensity < ridge:
         achieved = v["bytes"] / v["launches"] / (per_launch_ms * 1e-3) / 1e9
         roof = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS,
                     unit="GB/s")
     else:
-        peak = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
         achieved = v["flops"] / v["launches"] / (per_launch_ms * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=round(achieved, 4), peak=peak,
+        bound = "mfma" if dom in ("gram", "panel_gemm") else "alu"
+        roof = dict(bound=bound, achieved=round(achieved, 4), peak=peak,
                     unit="TFLOP/s")
     roof["frac"] = round(roof["achieved"] / roof["peak"], 5)
+    roof["intensity_flop_per_byte"] = round(intensity, 3)
+    if roof["bound"] == "hbm" and copy_gbps:
+        roof["copy_roof_GBps"] = round(copy_gbps, 1)
+        roof["frac_of_copy_roof"] = round(roof["achieved"] / copy_gbps, 5)
     g = gather_bytes(dom, v["flops"], prec)
     if g:
         # what the product actually moves from L2 / MALL / HBM per second
@@ -131,6 +151,27 @@ def roofline(prof, prec, workload):
     roof["launches"] = v["launches"]
     roof["avg_launch_us"] = round(per_launch_ms * 1e3, 3)
     return dom, roof
+
+
+def copy_roof(torch, mib=2048, reps=5):
+    """Measured device-to-device copy rate (bytes read + written per second):
+    the HBM roof the box actually gives, beside the 8 TB/s datasheet figure."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    return 2.0 * n * 8 / (best * 1e-3) / 1e9
 
 
 def gather_bytes(family, flops, prec):
@@ -183,19 +224,30 @@ def cpu_baseline(prob, prm, budget_s, max_steps):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = len(os.sched_getaffinity(0))
+    try:
+        import numpy as np
+        blas = ",".join(sorted({i.get("internal_api", "?") for i in threadpool_info()
+                                if i.get("user_api") == "blas"})) or "unknown"
+    except Exception:
+        blas = "unknown"
+    t0 = time.perf_counter()
     orc = oracle.FastSVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    t_init = time.perf_counter() - t0
     steps = 0
+    infos = []
     t0 = time.perf_counter()
     while steps < max_steps and time.perf_counter() - t0 < budget_s:
         info = orc.step()
+        infos.append(info)
         steps += 1
         if info.converged:
             break
     dt = time.perf_counter() - t0
-    return orc, dict(value=round(steps / dt, 4), unit="steps/s", cores=int(threads),
-                     kind="oracle",
-                     sample=(f"first {steps} fast-SVT steps of the same workload "
-                             f"(NumPy/SciPy FP64, {dt:.1f} s wall)"))
+    return orc, infos, dict(value=round(steps / dt, 4), unit="steps/s", cores=int(threads),
+                            kind="oracle", blas=blas,
+                            sample=(f"first {steps} fast-SVT steps of the same workload "
+                                    f"(NumPy/SciPy FP64, {dt:.1f} s wall after a "
+                                    f"{t_init:.1f} s set-up)"))
 
 
 def serving_leg(a):
@@ -206,7 +258,8 @@ def serving_leg(a):
     import torch
     import synth
     from paper_1810_06860_amd import serving
-    desc = synth.serving_trace()[: a.serve]
+    trace = synth.serving_trace()
+    desc = trace[: a.serve]
     t0 = time.perf_counter()
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
     with cf.ThreadPoolExecutor(workers) as ex:
@@ -234,7 +287,8 @@ def serving_leg(a):
                graphs=bool(a.serve_graphs),
                slots=a.serve_slots, streams=a.serve_streams,
                nnz_total=int(sum(p.nnz for p in problems)),
-               arrivals="Poisson, mean gap 50 ms", generation_s=round(gen_s, 1))
+               arrivals="Poisson, mean gap 50 ms", generation_s=round(gen_s, 1),
+               subset=f"the first {len(desc)} of the {len(trace)}-request trace")
     for key in ("p50_s", "p99_s", "mean_s", "max_s", "makespan_s", "steps_per_s"):
         if out.get(key) is not None:
             out[key] = round(out[key], 4)
@@ -344,6 +398,35 @@ def rsvd_main(a):
     print(json.dumps(line))
 
 
+def per_kp_times(infos, step_ms):
+    """Mean step time per (k, p) of the steps in a window."""
+    acc = {}
+    for inf, ms in zip(infos, step_ms):
+        key = f"k={inf['k']},p={inf['p']}"
+        n, t = acc.get(key, (0, 0.0))
+        acc[key] = (n + 1, t + ms)
+    return {key: dict(steps=n, ms=round(t / n, 3)) for key, (n, t) in acc.items()}
+
+
+def run_whole(SVT, prob, prm, log_name):
+    """One solve from its first step to i_max or convergence, timed whole."""
+    import torch
+    s = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = s.solve()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    f = s.factors()
+    s.close()
+    rec = dict(steps=out["iters"], steps_per_s=round(out["iters"] / dt, 4),
+               s=round(dt, 3), converged=bool(out["converged"]), res_last=out["res"],
+               rank=out["rank"], fresh=out["fresh"], recycled=out["recycled"],
+               rejected=out["rejected"])
+    log(f"{log_name}: {rec}")
+    return rec, f
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -363,7 +446,10 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     log(f"workload {a.workload}")
+    g0 = time.perf_counter()
     prob, prm = synth.make_problem(a.workload)
+    log(f"generated in {time.perf_counter() - g0:.1f} s: {prob.m} x {prob.n}, "
+        f"nnz {prob.nnz}")
     prm = dict(prm)
     prm["precision"] = a.precision
     prm["i_max"] = max(prm["i_max"], a.warmup + a.steps)
@@ -371,23 +457,40 @@ def main():
         prm["ritz_tol"] = a.ritz_tol
     if a.eager:
         prm["use_graphs"] = 0
+    copy_gbps = copy_roof(torch)
+    log(f"device copy roof: {copy_gbps:.0f} GB/s")
     solver = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+    warm = []
     for _ in range(a.warmup):
         info = solver.step()
+        warm.append(info)
         if info["converged"]:
             raise SystemExit("workload converged during warm-up; lower --warmup")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = []
+    infos, step_ms = [], []
     for _ in range(a.steps):
+        s0 = time.perf_counter()
         info = solver.step()
+        step_ms.append((time.perf_counter() - s0) * 1e3)
         infos.append(info)
         if info["converged"]:
             break
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    log(f"timed: {len(infos)} steps in {t1 - t0:.3f} s")
-    # Per-kernel durations: the same workload re-run with kernel-by-kernel
+    done = len(infos)
+    dt = t1 - t0
+    value = done / dt
+    log(f"timed: {done} steps in {dt:.3f} s")
+    window = dict(first_step=a.warmup + 1, last_step=a.warmup + done,
+                  rank=[min(i["r"] for i in infos), max(i["r"] for i in infos)],
+                  k=[min(i["k"] for i in infos), max(i["k"] for i in infos)],
+                  p=sorted({i["p"] for i in infos}),
+                  fresh=sum(i["fresh"] for i in infos),
+                  recycled=sum(i["recycled"] for i in infos),
+                  rejected=sum(i["rejected"] for i in infos),
+                  per_kp=per_kp_times(infos, step_ms))
+    # Per-kernel durations: the same window re-run with kernel-by-kernel
     # launches and HIP events around each launch on the solve's stream.
     prof_solver = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals,
                       dict(prm, use_graphs=0))
@@ -408,19 +511,20 @@ def main():
     prof_solver.profile(False)
     prof_solver.close()
     prof_ms = (tp1 - tp0) * 1e3 / pdone if pdone else None
-    done = len(infos)
-    dt = t1 - t0
-    value = done / dt
-
     log(f"profiled pass: {pdone} steps")
-    dom, roof = roofline(prof, a.precision, a.workload)
+    dom, roof = roofline(prof, a.precision, a.workload, copy_gbps)
     U, sig, V = solver.factors()
-    res_last = infos[-1]["res"]
-    acc = dict(res_last=res_last, rank=infos[-1]["r"], steps_total=a.warmup + done,
-               converged=bool(infos[-1]["converged"]),
-               fresh=sum(i["fresh"] for i in infos),
-               recycled=sum(i["recycled"] for i in infos),
-               rejected=sum(i["rejected"] for i in infos))
+    solver.close()
+    acc = dict(res_last=infos[-1]["res"], rank=infos[-1]["r"],
+               steps_total=a.warmup + done, converged=bool(infos[-1]["converged"]))
+    # the solve run whole, and its reduced-precision forms against it
+    whole, modes, whole_f = None, {}, None
+    if a.whole:
+        whole, whole_f = run_whole(SVT, prob, prm, "whole solve")
+        for mode in [x for x in a.modes.split(",") if x and x != a.precision]:
+            rec, f = run_whole(SVT, prob, dict(prm, precision=mode), f"whole {mode}")
+            rec["rel_err_vs_" + a.precision] = float(factored_rel_diff(f, whole_f))
+            modes[mode] = rec
     if a.precision != "fp64":
         # the plain FP64 form on the same GPU, same steps: speed and distance
         ref = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals,
@@ -457,24 +561,29 @@ def main():
                                                     np.linalg.norm(t))
     cpu = None
     if not a.no_cpu_baseline:
-        orc, cpu = cpu_baseline(prob, prm, a.cpu_seconds, a.warmup + done)
-        log(f"cpu baseline: {cpu['value']} steps/s")
-        if orc.i == a.warmup + done:
-            Xo = (orc.U * orc.sig) @ orc.V.T
-            X = (U * sig) @ V.T
-            acc["rel_err_vs_oracle"] = float(np.linalg.norm(X - Xo) /
-                                             max(np.linalg.norm(Xo), 1e-300))
-        acc["oracle_steps_compared"] = orc.i
-        common = orc.err_hist
-        gpu_hist = []  # residuals of the warm-up steps are not kept; compare
-        # the timed ones that the oracle also reached
-        for j, inf in enumerate(infos):
-            step_i = a.warmup + j + 1
-            if step_i <= len(common):
-                gpu_hist.append((inf["res"], common[step_i - 1]))
-        if gpu_hist:
-            acc["res_hist_max_rel_diff"] = float(max(
-                abs(g - o) / max(abs(o), 1e-300) for g, o in gpu_hist))
+        orc, oinfos, cpu = cpu_baseline(prob, prm, a.cpu_seconds, a.warmup + done)
+        log(f"cpu baseline: {cpu['value']} steps/s over {len(oinfos)} steps")
+        # a fresh GPU solve against the oracle, step by step from step 1
+        gpu_hist = warm + infos
+        j = len(oinfos)
+        same = all((g["r"], g["k"], g["p"], g["fresh"], g["recycled"], g["rejected"]) ==
+                   (o.r, o.k, o.p, o.fresh, o.recycled, o.rejected)
+                   for g, o in zip(gpu_hist, oinfos))
+        acc["oracle_steps_compared"] = j
+        acc["oracle_same_control"] = bool(same)
+        acc["res_hist_max_rel_diff"] = float(max(
+            abs(g["res"] - o.res) / max(abs(o.res), 1e-300)
+            for g, o in zip(gpu_hist, oinfos)))
+        chk = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
+        for _ in range(j):
+            chk.step()
+        acc["rel_err_vs_oracle"] = float(factored_rel_diff(chk.factors(),
+                                                           (orc.U, orc.sig, orc.V)))
+        acc["sigma_max_rel_diff_vs_oracle"] = float(np.max(
+            np.abs(chk.sigma() - oinfos[-1].S) / np.abs(oinfos[-1].S)))
+        chk.close()
+        log(f"oracle agreement over {j} steps: X {acc['rel_err_vs_oracle']:.2e}, "
+            f"residuals {acc['res_hist_max_rel_diff']:.2e}")
     serve = serving_leg(a) if a.serve > 0 else None
     if a.copy_calib_mib:
         n = a.copy_calib_mib * (1 << 20) // 4
@@ -499,12 +608,15 @@ def main():
         "config": {"workload": a.workload, "m": prob.m, "n": prob.n,
                    "nnz": prob.nnz, "precision": a.precision,
                    "recycle": prm["recycle"], "ritz_tol": prm["ritz_tol"],
-                   "p_init": prm["p_init"],
+                   "p_init": prm["p_init"], "k_max": prm["k_max"],
                    "adaptive_p": prm["adaptive_p"], "tau": prm["tau"],
-                   "delta": prm["delta"], "eps": prm["eps"]},
+                   "delta": prm["delta"], "eps": prm["eps"], "i_max": prm["i_max"]},
+        "window": window,
         "roofline": roof,
         "cpu_baseline": cpu,
         "accuracy": acc,
+        "whole_solve": whole,
+        "modes": modes or None,
         "serving": serve,
         "kernels": family_table(prof, tp1 - tp0, a.precision),
         "profiled_pass": {"steps": pdone,

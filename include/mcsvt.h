@@ -65,7 +65,7 @@ typedef struct {
   double tau;       /* threshold; <= 0 -> 5 n (Sec. II.C) */
   double delta;     /* step size; <= 0 -> 1.2 m n / |Phi| */
   double eps;       /* stop when ||P_Phi(X - M)||_F / ||P_Phi(M)||_F < eps
-                       (Alg. 2 step 10, Alg. 6 step 16) */
+                       (Alg. 2, Alg. 6) */
   double ritz_tol;  /* guarded recycling: a recycled SVD whose Ritz residual
                        max_j ||Y v_j - s_j u_j|| / s_j exceeds this is
                        discarded and rSVD-BKI runs instead, and the next
@@ -76,11 +76,11 @@ typedef struct {
   int32_t i_max;    /* maximum SVT steps (default 200) */
   int32_t l;        /* rank increment of the rank search (default 5) */
   int32_t s;        /* oversampling of rSVD-BKI (default 10, Sec. II.B) */
-  int32_t p_init;   /* initial power parameter (default 3, Alg. 6 step 1) */
+  int32_t p_init;   /* initial power parameter (default 3, Alg. 6) */
   int32_t p_min, p_max;  /* bounds of the adaptive p (default 1, 8) */
   int32_t adaptive_p;    /* 1: p+1 after a rise of the error, p-1 after ten
                             consecutive decreases (Sec. IV.C); 0: fixed */
-  int32_t i_reuse;  /* first step allowed to recycle (Alg. 6 step 5) */
+  int32_t i_reuse;  /* first step allowed to recycle (Alg. 6) */
   int32_t q_reuse;  /* recycled calls per rSVD-BKI basis (default 10) */
   int32_t recycle;  /* 0 none, 1 reuse Q, 2 reuse U (Sec. IV.B) */
   int32_t k_max;    /* rank cap; 0 -> min(m, n) */
@@ -94,7 +94,7 @@ typedef struct {
 /* What one SVT step did (Alg. 6, one iteration of the outer loop). */
 typedef struct {
   int32_t i;          /* 1-based step index */
-  int32_t r;          /* rank of X^i: #{S_j > tau} (Alg. 6 step 14) */
+  int32_t r;          /* rank of X^i: #{S_j > tau} (Alg. 6) */
   int32_t k;          /* rank parameter of the last SVD call */
   int32_t p;          /* power parameter used in this step */
   int32_t fresh;      /* rSVD-BKI calls in this step */
@@ -119,24 +119,38 @@ typedef struct {
                        pass because a factorisation needed a shift */
 } mc_svt_result;
 
-/* Optional allocator hooks (e.g. a framework's caching allocator).  alloc
- * returns device memory of at least `bytes` usable on `stream`, or NULL.
- * Both must be thread-safe.  NULL hooks restore hipMalloc / hipFree. */
+/* Optional allocator hooks (e.g. a framework's caching allocator): every
+ * device buffer of the library (the iterate, the panels of Alg. 5, the
+ * workspaces) is then taken from and returned to the caller's allocator.
+ * alloc returns device memory of at least `bytes` usable on `stream`, or
+ * NULL (the library then fails with MC_ENOMEM); release may be called while
+ * work that used the block is still queued on `stream` (stream-ordered
+ * reuse, as a caching allocator gives).  Both must be thread-safe.  NULL
+ * hooks restore hipMalloc / hipFree.  Errors: MC_EINVAL if only one is NULL. */
 typedef void* (*mc_alloc_fn)(size_t bytes, void* stream, void* ctx);
 typedef void (*mc_free_fn)(void* ptr, size_t bytes, void* stream, void* ctx);
 mc_status mc_set_allocator(mc_alloc_fn alloc, mc_free_fn release, void* ctx);
 
+/* MCSVT_ABI_VERSION of the built library. */
 int32_t mc_abi_version(void);
+/* The paper's settings (Sec. II.C: tau = 5 n, l = 5; Sec. II.B: s = 10;
+ * Alg. 6: p = 3; Sec. IV.C: the adaptive p) and the build's defaults
+ * for the rest (eps 1e-4, i_max 200, q_reuse 10, no recycling, ritz_tol
+ * 1e-4, FP64, graphs on). */
 void mc_svt_default_params(mc_svt_params* p);
 
-/* Device bytes one handle holds for a problem of this size, with the rank
- * search bounded by k_max (or min(m, n, 256) when k_max = 0) and p <= p_max.
- * Used by admission control of the serving loop. */
+/* Device bytes one handle can hold for a problem of this size: the layouts
+ * of Phi, the iterate, and the panels and workspaces of the largest SVD call
+ * the solve can make -- rank search bounded by min(m, n, k_max) (min(m, n)
+ * when k_max = 0; the rank search of Alg. 6), block width k + s, Krylov basis
+ * (p_max + 1)(k + s) (Alg. 5).  The solver never grows its buffers past
+ * these sizes, so this is an upper bound; the serving loop admits requests
+ * by it.  Returns 0 for sizes < 1; params NULL -> defaults. */
 size_t mc_svt_footprint(int64_t m, int64_t n, int64_t nnz,
                         const mc_svt_params* p);
 
 /*
- * mc_svt_init -- set up one completion problem (Alg. 6 step 1).
+ * mc_svt_init -- set up one completion problem (the start of Alg. 6).
  *   m, n        matrix size (each >= 1; m*n may exceed 2^31)
  *   nnz         |Phi| (>= 1, < 2^31)
  *   rows        is_csr = 0: COO row index of each observed entry (nnz)
@@ -157,10 +171,26 @@ mc_status mc_svt_init(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
                       const mc_svt_params* params, void* stream,
                       mc_svt_t* out);
 
+/* mc_svt_init with Phi and M_Phi already in device memory (e.g. tensors of a
+ * framework): rows (int64: COO row ids, nnz, or with is_csr the CSR row
+ * pointer, m + 1), cols (int32, nnz) and vals (double, nnz) are device
+ * pointers readable on `stream`, owned by the caller and only read during
+ * the call (the layout is copied).  The same set-up as mc_svt_init (the start of
+ * Alg. 6, Sec. II.C), with the checks made on the device.  Returns after the
+ * stream has finished the set-up.  Errors: as mc_svt_init (a non-finite
+ * value or a bad CSR pointer gives MC_EINVAL). */
+mc_status mc_svt_init_dev(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
+                          const int32_t* cols, const double* vals, int32_t is_csr,
+                          const mc_svt_params* params, void* stream,
+                          mc_svt_t* out);
+
 /* One step of Alg. 6: rank search with rSVD-BKI or a recycled basis, shrink,
- * residual, and the update Y^i = Y^{i-1} + delta P_Phi(M - X^i).  The update
- * is also applied on the converging step (the returned X is X^i).
- * Errors: MC_EDONE after convergence, MC_ENUMERIC, MC_EDEVICE, MC_ENOMEM. */
+ * residual, and the update Y^i = Y^{i-1} + delta P_Phi(M - X^i) (Eq. (6)).
+ * The residual and the update come out of one pass over Phi, so the update
+ * is also applied on the converging step, where Alg. 2 and Alg. 6 stop
+ * before it: X^i is the paper's, Y is one update further (see
+ * mc_svt_get_y).  Errors: MC_EDONE after convergence, MC_ENUMERIC,
+ * MC_EDEVICE, MC_ENOMEM. */
 mc_status mc_svt_step(mc_svt_t h, mc_svt_step_info* info);
 
 /* Advance `count` independent solves by one step each (continuous batching
@@ -178,31 +208,44 @@ mc_status mc_svt_step(mc_svt_t h, mc_svt_step_info* info);
 mc_status mc_svt_step_many(mc_svt_t* hs, int32_t count,
                            mc_svt_step_info* info, mc_status* status);
 
-/* Steps until convergence or i_max (Alg. 6 outer loop). */
+/* Steps until convergence or i_max (Alg. 6 outer loop); MC_ENOTCONV at
+ * i_max, with X^{i_max} available as Alg. 2 returns it.  out may be NULL. */
 mc_status mc_svt_solve(mc_svt_t h, mc_svt_result* out);
 
-/* Summary of the solve so far (valid after init). */
+/* Summary of the solve so far (valid after init): iteration count, rank and
+ * residual of Alg. 6, and the constants of its set-up (c, ||P_Phi(M)||_2,
+ * Sec. II.C).  Errors: MC_EINVAL for a NULL argument. */
 mc_status mc_svt_get_result(mc_svt_t h, mc_svt_result* out);
 
-/* X^i = U diag(sig) V^T with U (m x r, row stride ldu >= r), sig = S_j - tau
- * descending (r), V (n x r, row stride ldv >= r); host buffers sized for
- * r_cap columns.  *r receives the rank; MC_EINVAL if r > r_cap. */
+/* The factors of the current X^i = sum_{j <= r} (S_j - tau) u_j v_j^T (the
+ * shrink of Eq. (6), Alg. 6): U (m x r, row stride ldu >= r), sig =
+ * S_j - tau descending (r), V (n x r, row stride ldv >= r); caller-owned
+ * host buffers sized for r_cap columns (any may be NULL to skip it).  *r
+ * receives the rank.  Errors: MC_EINVAL if r > r_cap or a stride < r. */
 mc_status mc_svt_get_factors(mc_svt_t h, double* U, double* sig, double* V,
                              int64_t ldu, int64_t ldv, int32_t r_cap,
                              int32_t* r);
 
-/* P_Phi(X^i) at the observed cells, in the caller's input order (nnz). */
+/* P_Phi(X^i), the completed matrix at the observed cells (the term of the
+ * stop test and the update, Alg. 6), in the caller's input order:
+ * x_phi (nnz, caller-owned host buffer).  Errors: MC_EINVAL for NULL. */
 mc_status mc_svt_get_observed(mc_svt_t h, double* x_phi);
 
-/* The current iterate Y on Phi (nnz, caller's input order). */
+/* The current iterate Y (Eq. (6)) on Phi, in the caller's input order: y
+ * (nnz, caller-owned host buffer).  After the converging step this is one
+ * update past the paper's Y^{i-1} (mc_svt_step applies it in the same pass
+ * as the residual).  Errors: MC_EINVAL for NULL. */
 mc_status mc_svt_get_y(mc_svt_t h, double* y);
 
-/* Singular values (descending) of the last SVD call of the last step;
- * *k receives their count; MC_EINVAL if k_cap is too small. */
+/* Singular values (descending) of the last SVD call of the last step (the
+ * S^{i-1} of Alg. 6); *k receives their count; S is a
+ * caller-owned host buffer of k_cap values.  Errors: MC_EINVAL if k_cap is
+ * too small. */
 mc_status mc_svt_get_sigma(mc_svt_t h, double* S, int32_t k_cap, int32_t* k);
 
-/* Event timing of the solve's kernel families on its own stream (for
- * measurement; adds two hipEventRecord calls per timed launch).  Families:
+/* Event timing of the solve's kernel families on its own stream (a
+ * measurement aid of this build with no counterpart in the paper; adds two
+ * hipEventRecord calls per timed launch).  Families:
  *   0 SpMM Y X (CSR)       1 SpMM Y^T X (CSC)     2 fused SDDMM/update
  *   3 Gram / cross-Gram    4 panel GEMMs          5 Cholesky + inverse
  *   6 eigensolve (all its kernels and convergence checks)
@@ -224,7 +267,11 @@ mc_status mc_svt_profile(mc_svt_t h, int32_t on);
  * cap >= MC_PROF_FAMILIES entries. */
 mc_status mc_svt_get_profile(mc_svt_t h, mc_prof_entry* out, int32_t cap);
 
+/* Frees every device buffer of the handle (NULL is a no-op). */
 mc_status mc_svt_destroy(mc_svt_t h);
+/* Message of the last failure on h, or of the calling thread when h is NULL;
+ * owned by the library, valid until the next call on the same handle or
+ * thread. */
 const char* mc_svt_last_error(mc_svt_t h);
 
 /*
@@ -282,8 +329,10 @@ mc_status mc_rsvd_run(mc_rsvd_t h, int32_t method, int32_t k, int32_t p,
  * mc_svt_get_profile (calls run kernel by kernel while timing is on). */
 mc_status mc_rsvd_profile(mc_rsvd_t h, int32_t on);
 mc_status mc_rsvd_get_profile(mc_rsvd_t h, mc_prof_entry* out, int32_t cap);
+/* Frees the device copy of A and the workspaces (NULL is a no-op). */
 mc_status mc_rsvd_destroy(mc_rsvd_t h);
-const char* mc_rsvd_last_error(mc_rsvd_t h);   /* per thread when h is NULL */
+/* As mc_svt_last_error: per handle, or per thread when h is NULL. */
+const char* mc_rsvd_last_error(mc_rsvd_t h);
 
 #ifdef __cplusplus
 }

@@ -19,7 +19,7 @@
 extern "C" {
 #endif
 
-/* Gaussian test matrix Omega (Alg. 5 step 1): out (rows x cols) from the
+/* Gaussian test matrix Omega of rSVD-BKI (Alg. 5): out (rows x cols) from the
  * Philox4x32-10 counter stream keyed by seed, counter (pair, step, attempt),
  * Box-Muller per element pair. */
 mc_status mc_k_gaussian(int64_t rows, int64_t cols, uint64_t seed,
@@ -36,16 +36,19 @@ mc_status mc_k_layout(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
                       int32_t* col_idx, int32_t* order, int32_t* col_ptr,
                       int32_t* row_idx, int32_t* perm);
 
-/* SpMM of the sparse A (COO input) with a dense panel: transpose = 0:
- * out (m x b) = A X with X (n x b); transpose = 1: out (n x b) = A^T X with
- * X (m x b).  precision as mc_precision (FP32 runs A and X in FP32 with FP32
+/* SpMM of the sparse A (COO input) with a dense panel -- the products
+ * A Omega, A (A^T H) and A^T Q of the randomized SVDs (Alg. 4, Alg. 5):
+ * transpose = 0: out (m x b) = A X with X (n x b); transpose = 1:
+ * out (n x b) = A^T X with X (m x b).  precision as mc_precision (FP32 runs A and X in FP32 with FP32
  * accumulation; the result is returned in FP64). */
 mc_status mc_k_spmm(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
                     const int32_t* cols, const double* vals, int32_t transpose,
                     int32_t b, const double* X, int32_t precision, void* stream,
                     double* out);
 
-/* C (p x q) = A^T B for A (N x p), B (N x q); sym = 1 requires A == B. */
+/* C (p x q) = A^T B for A (N x p), B (N x q), the Gram matrix of eigSVD
+ * (Alg. 3) and of the block orthonormalisation (Lemma 2); sym = 1 requires
+ * A == B.  Host buffers; FP64 result in every precision. */
 mc_status mc_k_gram(int64_t N, int32_t p, int32_t q, const double* A,
                     const double* B, int32_t sym, int32_t precision,
                     void* stream, double* C);
@@ -53,20 +56,23 @@ mc_status mc_k_gram(int64_t N, int32_t p, int32_t q, const double* A,
 /* Panel product C (N x q) = beta C0 + alpha X W diag(colscale) with X (N x p)
  * and W (p x q), all row-major host arrays; colscale (q) and C0 may be NULL
  * (then they are not applied / beta must be 0).  This is the product behind
- * H R^-1, H - Q (Q^T H), U = Q W and V = B^T W S^-1 (Alg. 3 step 4, Alg. 5
- * step 10).  precision MC_FP32 rounds X to FP32 first (the solver's FP32
- * panels); the arithmetic is FP64 either way. */
+ * H R^-1, H - Q (Q^T H), U = Q W and V = B^T W S^-1 (Alg. 3, Alg. 5).
+ * precision MC_FP32 rounds X to FP32 first (the solver's FP32 panels); the
+ * arithmetic is FP64 either way. */
 mc_status mc_k_panel(int64_t N, int32_t p, int32_t q, const double* X,
                      const double* W, double alpha, const double* colscale,
                      double beta, const double* C0, int32_t precision,
                      void* stream, double* C);
 
 /* Orthonormal basis of range(H) for H (N x b) by two passes of Cholesky QR
- * (with a diagonal shift on breakdown): Q (N x b). */
+ * (with a diagonal shift on breakdown): Q (N x b).  This is the build's
+ * range-preserving normalisation of a Krylov block in place of the pivoted
+ * LU of Alg. 4 and Alg. 5 (Lemmas 2-3).  Errors: MC_EINVAL for b > N. */
 mc_status mc_k_cholqr2(int64_t N, int32_t b, const double* H, void* stream,
                        double* Q);
 
-/* Top-k symmetric eigensolver (FP64) of G (L x L), the solver's own dispatch:
+/* The eig step of eigSVD (Alg. 3) and the top-k selection of Alg. 5.
+ * Top-k symmetric eigensolver (FP64) of G (L x L), the solver's own dispatch:
  * one-wavefront Jacobi for L <= 16, Householder tridiagonalisation +
  * multisection + inverse iteration up to L = 1024 (k <= 140), block Jacobi
  * beyond.  The k largest eigenvalues, descending, in evals (k) and their
@@ -75,7 +81,7 @@ mc_status mc_k_cholqr2(int64_t N, int32_t b, const double* H, void* stream,
 mc_status mc_k_syev(int32_t L, const double* G, int32_t k, void* stream,
                     double* evals, double* W, int32_t* sweeps);
 
-/* Fused SDDMM + residual + update on Phi (Alg. 6 steps 15-17): given
+/* Fused SDDMM + residual + update on Phi (Eq. (6), Alg. 6): given
  * U (m x r), sig (r), V (n x r), M_Phi and Y on Phi (COO order), returns
  * x (P_Phi(X), input order), y_new = y + delta (M - x) and
  * *sumsq = sum (M - x)^2. */
@@ -86,7 +92,8 @@ mc_status mc_k_sddmm(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
                      void* stream, double* x, double* y_new, double* sumsq);
 
 /* Banded work schedule of the SpMM for a CSR-like structure (host code only:
- * no device is touched).  This is the schedule the SpMM uses once the dense
+ * a scheduling aid of this build for the products of Alg. 5, with no
+ * counterpart in the paper; no device is touched).  This is the schedule the SpMM uses once the dense
  * panel it gathers from outgrows one XCD's L2: the gathered index range
  * [0, gathered) is cut into `bands` equal ranges (a positive multiple of 8);
  * rows of at least max(256, 4 cap) entries are split at the range

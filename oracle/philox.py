@@ -1,4 +1,4 @@
-"""Counter-based Gaussian numbers for the test matrix Omega (Alg. 5, step 1).
+"""Counter-based Gaussian numbers for the test matrix Omega of rSVD-BKI (Alg. 5).
 
 Omega = randn(n, k+s) is the only random draw of the method.  To let the CPU
 oracle and the GPU library draw the *same* Omega without passing it across,

@@ -9,9 +9,9 @@ Iteration (Eq. (6)):
     Y^i = Y^{i-1} + delta P_Phi(M - X^i)
 with Y^0 = c delta P_Phi(M), c = ceil(tau / (delta ||P_Phi(M)||_2)), and the
 stop test ||P_Phi(X^i - M)||_F / ||P_Phi(M)||_F < eps checked before the
-update (Alg. 2, steps 1, 10, 11).  shrink applies the soft threshold
+update (Alg. 2).  shrink applies the soft threshold
 max(sigma - tau, 0) to every singular value.  Alg. 2's incremental rank
-search (steps 3-7) only serves to find every singular value above tau; a full
+search only serves to find every singular value above tau; a full
 SVD finds them directly.  An optional rank cap keeps the largest k_max.
 
 Defaults (Sec. II.C): tau = 5 n, l = 5.  The step size delta is not fixed by

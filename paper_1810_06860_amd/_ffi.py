@@ -74,6 +74,9 @@ _SIGNATURES = {
     "mc_svt_init": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _P(C.c_int64),
                               _P(C.c_int32), _P(C.c_double), C.c_int32,
                               _P(Params), C.c_void_p, _P(C.c_void_p)]),
+    "mc_svt_init_dev": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_int32,
+                                  _P(Params), C.c_void_p, _P(C.c_void_p)]),
     "mc_svt_step": (C.c_int, [C.c_void_p, _P(StepInfo)]),
     "mc_svt_step_many": (C.c_int, [_P(C.c_void_p), C.c_int32, _P(StepInfo),
                                    _P(C.c_int)]),
@@ -143,6 +146,38 @@ _SIGNATURES = {
 }
 
 _lib = None
+_hooks = None          # the registered allocator callbacks, kept alive
+
+
+def _use_torch_allocator(handle):
+    """Route the library's device allocations through torch's caching
+    allocator (mc_set_allocator), so that PyTorch owns the device memory of
+    every solve.  Skipped without a visible GPU or with MCSVT_ALLOCATOR=hip."""
+    global _hooks
+    if os.environ.get("MCSVT_ALLOCATOR", "torch") == "hip":
+        return
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return
+    except ImportError:
+        return
+
+    def alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        except Exception:
+            return None                      # the library reports MC_ENOMEM
+
+    def release(ptr, nbytes, stream, ctx):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    hooks = (ALLOC_FN(alloc), FREE_FN(release))
+    if handle.mc_set_allocator(hooks[0], hooks[1], None) == MC_OK:
+        _hooks = hooks
 
 
 class MCError(RuntimeError):
@@ -171,6 +206,7 @@ def lib():
             fn = getattr(handle, name)
             fn.restype = res
             fn.argtypes = args
+        _use_torch_allocator(handle)
         _lib = handle
     return _lib
 

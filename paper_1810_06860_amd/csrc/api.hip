@@ -264,6 +264,40 @@ mc_status mc_svt_init(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
   return MC_OK;
 }
 
+mc_status mc_svt_init_dev(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
+                          const int32_t* cols, const double* vals, int32_t is_csr,
+                          const mc_svt_params* params, void* stream, mc_svt_t* out) {
+  if (out) *out = nullptr;
+  mc_svt* h = nullptr;
+  mc_status st = guarded(nullptr, [&] {
+    MC_REQUIRE(out && rows && cols && vals, mcsvt::kEINVAL, "NULL argument");
+    check_sizes(m, n, nnz);
+    mc_svt_params prm;
+    if (params) prm = *params; else mc_svt_default_params(&prm);
+    h = new mc_svt();
+    h->solver = mcsvt::make_solver(m, n, nnz, prm, (hipStream_t)stream);
+    mcsvt::DevBuf<int64_t> expanded;
+    const int64_t* r = rows;
+    if (is_csr) {
+      expanded.reserve(nnz, (hipStream_t)stream);
+      if (mcsvt::csr_rows_device(m, nnz, rows, expanded.p, (hipStream_t)stream) != mcsvt::kOK)
+        throw mcsvt::Error(mcsvt::kEINVAL,
+                           "CSR row pointer must start at 0, end at nnz and not decrease");
+      r = expanded.p;
+    }
+    const int s = h->solver->init(r, cols, vals, true, true);
+    if (s == mcsvt::kERANGE) throw mcsvt::Error(s, "index out of range");
+    if (s == mcsvt::kEDUP) throw mcsvt::Error(s, "duplicate cell in Phi");
+    if (s != mcsvt::kOK) throw mcsvt::Error(s, "invalid input (a non-finite value?)");
+  });
+  if (st != MC_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return MC_OK;
+}
+
 mc_status mc_svt_step(mc_svt_t h, mc_svt_step_info* info) {
   if (!h || !h->solver) {
     mcsvt::t_err = "NULL handle";

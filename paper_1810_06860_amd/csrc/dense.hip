@@ -3,14 +3,14 @@
 // * gram:  C = A^T B for tall-skinny A (N x p), B (N x q), row-major.  The
 //   N dimension is split over workgroups; each writes its partial tile and a
 //   second kernel sums the partials in a fixed order (deterministic).  Used
-//   for the Gram B B^T of eigSVD (Alg. 3 step 1) and for the Gram / cross-Gram
+//   for the Gram B B^T of eigSVD (Alg. 3) and for the Gram / cross-Gram
 //   products of the block orthonormalisation of the Krylov blocks.  The
 //   products run on the matrix cores (16x16x4 FP64 or FP32 MFMA); the fused
 //   form for short blocks (completion and Cholesky in the last workgroup)
 //   uses vector FMAs on 32 x 32 tiles.
 // * panel GEMM:  C = beta C0 + alpha X W diag(colscale), X tall (N x p),
 //   W small (p x q).  Used for H - Q (Q^T H), H R^-1, U = Q W and
-//   V = B^T W S^-1 (Alg. 3 step 4, Alg. 5 step 10).
+//   V = B^T W S^-1 (Alg. 3, Alg. 5).
 // * Cholesky + triangular inverse of a small SPD matrix in one workgroup,
 //   with a diagonal shift when a pivot breaks down (shifted Cholesky QR).
 #include <type_traits>

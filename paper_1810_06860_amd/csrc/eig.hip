@@ -1,5 +1,5 @@
-// Symmetric eigensolver for the small Gram matrix of eigSVD (Alg. 3 step 2),
-// and the top-k selection of Alg. 5 steps 9-10.
+// Symmetric eigensolver for the small Gram matrix of eigSVD (Alg. 3),
+// and the top-k selection of Alg. 5.
 //
 // Two-sided block Jacobi in FP64.  The L x L matrix is padded to Lp (a
 // multiple of 32) with a decoupled negative diagonal and cut into nb = Lp/16

@@ -318,6 +318,7 @@ mc_status mc_k_band_schedule(int64_t rows, const int32_t* ptr, const int32_t* id
                    bands % mcsvt::kBands == 0 && *nseg >= 0 && *nfix >= 0,
                mcsvt::kEINVAL, "bad sizes or NULL argument");
     MC_REQUIRE(ptr[0] == 0, mcsvt::kEINVAL, "ptr[0] must be 0");
+    MC_REQUIRE(ptr[rows] == 0 || idx, mcsvt::kEINVAL, "NULL idx");
     for (int64_t i = 0; i < rows; ++i) {
       MC_REQUIRE(ptr[i + 1] >= ptr[i], mcsvt::kEINVAL, "ptr decreases");
       for (int32_t e = ptr[i]; e < ptr[i + 1]; ++e)
@@ -325,7 +326,6 @@ mc_status mc_k_band_schedule(int64_t rows, const int32_t* ptr, const int32_t* id
                        (e == ptr[i] || idx[e] > idx[e - 1]),
                    mcsvt::kEINVAL, "index out of range or not increasing in its row");
     }
-    MC_REQUIRE(ptr[rows] == 0 || idx, mcsvt::kEINVAL, "NULL idx");
     std::vector<int4> s, f;
     int32_t slot = 0;
     mcsvt::band_schedule(ptr, idx, rows, gathered, cap, bands, s, f, slot);

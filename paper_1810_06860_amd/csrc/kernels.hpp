@@ -72,6 +72,10 @@ struct Layout {
 int build_layout(int64_t m, int64_t n, int64_t nnz, const int64_t* d_rows,
                  const int32_t* d_cols, const double* d_vals, Layout& L,
                  hipStream_t st);
+// COO row ids (nnz) of a device CSR row pointer (m + 1); returns kEINVAL when
+// the pointer does not start at 0, end at nnz and never decrease
+int csr_rows_device(int64_t m, int64_t nnz, const int64_t* d_ptr, int64_t* d_rows,
+                    hipStream_t st);
 // The banded segments and fix-up records of a host CSR-like structure (host
 // code only; build_schedule uploads them).
 void band_schedule(const int32_t* ptr, const int32_t* idx, int64_t rows,

@@ -1,4 +1,4 @@
-// Counter-based Gaussian test matrices Omega (Alg. 5 step 1, Alg. 1 step 1).
+// Counter-based Gaussian test matrices Omega (Alg. 5, Alg. 1).
 //
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): counter c0..c3, key
 // k0, k1; a round maps (c0, c1, c2, c3) to

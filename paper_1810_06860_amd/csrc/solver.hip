@@ -91,6 +91,7 @@ Solver::Solver(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& prm,
   kcap_ = (int)std::min<int64_t>(m, n);
   if (prm_.k_max > 0) kcap_ = std::min(kcap_, prm_.k_max);
   p_ = prm_.p_init;
+  solve_dims(m, n, prm_, lim_k_, lim_b_, lim_L_);
 }
 
 Solver::~Solver() {
@@ -264,11 +265,19 @@ StepInfo Solver::step() {
   return cur_;
 }
 
-size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& p) {
+void solve_dims(int64_t m, int64_t n, const mc_svt_params& p, int64_t& k, int64_t& b,
+                int64_t& L) {
   const int64_t mn = std::min(m, n);
-  int64_t k = p.k_max > 0 ? std::min<int64_t>(p.k_max, mn) : std::min<int64_t>(mn, 256);
-  const int64_t b = std::min<int64_t>(k + std::max(p.s, 10), mn);
-  const int64_t L = std::min<int64_t>((int64_t)(p.p_max + 1) * b, mn);
+  k = p.k_max > 0 ? std::min<int64_t>(p.k_max, mn) : mn;
+  // widths(): b = min(k + s, min(m, n)); the set-up run has b = 11, p = 10
+  b = std::max(std::min<int64_t>(k + std::max(p.s, 0), mn), std::min<int64_t>(11, mn));
+  L = std::max(std::min<int64_t>((int64_t)(std::max(p.p_max, 0) + 1) * b, mn),
+               std::min<int64_t>(121, mn));
+}
+
+size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& p) {
+  int64_t k, b, L;
+  solve_dims(m, n, p, k, b, L);
   const int64_t Lp = round_up(L, 32);
   const int64_t mx = std::max(m, n);
   size_t bytes = 0;

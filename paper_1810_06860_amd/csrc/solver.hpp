@@ -56,9 +56,10 @@ class Solver {
          hipStream_t st);
   virtual ~Solver();
 
-  // Phi and M_Phi from host arrays (COO rows, int32 cols).  Returns a status.
+  // Phi and M_Phi from COO arrays (int64 rows, int32 cols), host arrays or,
+  // with on_device, device arrays on the solve's stream.  Returns a status.
   virtual int init(const int64_t* rows, const int32_t* cols, const double* vals,
-                   bool scale_for_svt) = 0;
+                   bool scale_for_svt, bool on_device = false) = 0;
   // One step, waiting for each device round trip.
   StepInfo step();
   // The same step split at its device round trips, so the host can drive
@@ -157,6 +158,7 @@ class Solver {
   mc_svt_params prm_;
   hipStream_t st_;
   int kcap_ = 1;
+  int64_t lim_k_ = 1, lim_b_ = 1, lim_L_ = 1;   // solve_dims of this solve
 
   // Alg. 6 state
   int i_ = 0, r_ = 0, q_ = 0, p_ = 3, streak_ = 0;
@@ -179,6 +181,13 @@ std::unique_ptr<Solver> make_solver(int64_t m, int64_t n, int64_t nnz,
                                     const mc_svt_params& prm, hipStream_t st);
 
 void resolve_params(int64_t m, int64_t n, int64_t nnz, mc_svt_params& p);
+// Largest rank k, block width b and Krylov basis width L a solve with these
+// parameters can reach: the rank search stops at min(m, n, k_max) (min(m, n)
+// when k_max = 0), p stays <= p_max, and the spectral-norm run at set-up
+// uses k = 1, s = 10, p = 10.  The footprint prices these, and the solver's
+// buffers never grow past them.
+void solve_dims(int64_t m, int64_t n, const mc_svt_params& p, int64_t& k, int64_t& b,
+                int64_t& L);
 size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz,
                        const mc_svt_params& p);
 

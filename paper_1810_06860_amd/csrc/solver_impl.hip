@@ -10,7 +10,7 @@
 //   U = Q W_k, V = B^T W_k S^-1.
 //
 // Precision: P is the type of the dense panels (Omega, H, Q, B^T, U, V), VT
-// the type of the copies of Y read by the Krylov SpMMs (Alg. 5 steps 2, 4),
+// the type of the copies of Y read by the Krylov SpMMs of Alg. 5,
 // AT the accumulator of SpMM / Gram / SDDMM dot products.  The Rayleigh-Ritz
 // product B^T = Y^T Q, the Ritz guard and the SDDMM read Y in the panel
 // precision P, so the singular values are those of the computed subspace to
@@ -79,7 +79,7 @@ class SolverT final : public Solver {
   }
 
   int init(const int64_t* rows, const int32_t* cols, const double* vals,
-           bool scale_for_svt) override;
+           bool scale_for_svt, bool on_device) override;
   void get_factors(double* U, double* sig, double* V, int64_t ldu,
                    int64_t ldv) override;
   void get_rsvd(double* U, double* S, double* V) override;
@@ -171,15 +171,15 @@ void SolverT<P, VT, AT>::ensure(int bmax, int Lmax, int kmax) {
   // buffers move: captured graphs hold their addresses
   ++gen_;
   clear_graphs();
-  const int64_t mn = std::min(m_, n_);
-  // grow with headroom so the rank search does not reallocate every step
-  auto grow = [&](int want, int have) {
+  // grow with headroom so the rank search does not reallocate every step,
+  // never past what the solve can reach (its footprint prices exactly that)
+  auto grow = [&](int want, int have, int64_t lim) {
     if (want <= have) return have;
-    return (int)std::min<int64_t>(mn, std::max<int64_t>(want, (int64_t)have * 5 / 4 + 8));
+    return (int)std::min<int64_t>(lim, std::max<int64_t>(want, (int64_t)have * 5 / 4 + 8));
   };
-  cap_b_ = std::max(grow(bmax, cap_b_), bmax);
-  cap_L_ = std::max(grow(Lmax, cap_L_), Lmax);
-  cap_k_ = std::max(grow(kmax, cap_k_), kmax);
+  cap_b_ = std::max(grow(bmax, cap_b_, lim_b_), bmax);
+  cap_L_ = std::max(grow(Lmax, cap_L_, lim_L_), Lmax);
+  cap_k_ = std::max(grow(kmax, cap_k_, lim_k_), kmax);
   const int64_t b = cap_b_, Lc = cap_L_, k = cap_k_;
   const int64_t wide = std::max({b, Lc, k});
   omega_.reserve(n_ * b, st_);
@@ -221,17 +221,22 @@ void SolverT<P, VT, AT>::ensure(int bmax, int Lmax, int kmax) {
 
 template <class P, class VT, class AT>
 int SolverT<P, VT, AT>::init(const int64_t* rows, const int32_t* cols,
-                             const double* vals, bool scale_for_svt) {
+                             const double* vals, bool scale_for_svt, bool on_device) {
   DevBuf<int64_t> d_rows;
   DevBuf<int32_t> d_cols;
   DevBuf<double> d_vals;
-  d_rows.reserve(nnz_, st_);
-  d_cols.reserve(nnz_, st_);
-  d_vals.reserve(nnz_, st_);
-  MC_HIP(hipMemcpyAsync(d_rows.p, rows, nnz_ * sizeof(int64_t), hipMemcpyHostToDevice, st_));
-  MC_HIP(hipMemcpyAsync(d_cols.p, cols, nnz_ * sizeof(int32_t), hipMemcpyHostToDevice, st_));
-  MC_HIP(hipMemcpyAsync(d_vals.p, vals, nnz_ * sizeof(double), hipMemcpyHostToDevice, st_));
-  const int status = build_layout(m_, n_, nnz_, d_rows.p, d_cols.p, d_vals.p, L_, st_);
+  if (!on_device) {
+    d_rows.reserve(nnz_, st_);
+    d_cols.reserve(nnz_, st_);
+    d_vals.reserve(nnz_, st_);
+    MC_HIP(hipMemcpyAsync(d_rows.p, rows, nnz_ * sizeof(int64_t), hipMemcpyHostToDevice, st_));
+    MC_HIP(hipMemcpyAsync(d_cols.p, cols, nnz_ * sizeof(int32_t), hipMemcpyHostToDevice, st_));
+    MC_HIP(hipMemcpyAsync(d_vals.p, vals, nnz_ * sizeof(double), hipMemcpyHostToDevice, st_));
+  }
+  const int64_t* pr = on_device ? rows : d_rows.p;
+  const int32_t* pc = on_device ? cols : d_cols.p;
+  const double* pv = on_device ? vals : d_vals.p;
+  const int status = build_layout(m_, n_, nnz_, pr, pc, pv, L_, st_);
   if (status != kOK) return status;
   mvals_.reserve(nnz_, st_);
   y_.reserve(nnz_, st_);
@@ -241,7 +246,7 @@ int SolverT<P, VT, AT>::init(const int64_t* rows, const int32_t* cols,
     yw_.reserve(nnz_, st_);
     ycw_.reserve(nnz_, st_);
   }
-  launch_gather(nnz_, L_.order.p, d_vals.p, mvals_.p, st_);
+  launch_gather(nnz_, L_.order.p, pv, mvals_.p, st_);
   ensure(1, 1, 1);
   sdd_part_.reserve(sddmm_partials(nnz_), st_);
   scal_.reserve(8, st_);
@@ -418,7 +423,8 @@ double SolverT<P, VT, AT>::read_finish(int k, bool ritz) {
   return worst;
 }
 
-// eigSVD of B^T = Y^T basis (Alg. 3 on B^T, Alg. 5 steps 8-10): kernels only
+// eigSVD of B^T = Y^T basis (Alg. 3 on B^T, the Rayleigh-Ritz end of Alg. 5):
+// kernels only
 template <class P, class VT, class AT>
 void SolverT<P, VT, AT>::eig_body(const P* basis, int64_t ldb, int w, int k) {
   spmm_yt_rr(basis, ldb, Bt_.p, w, w);                       // B^T = Y^T basis

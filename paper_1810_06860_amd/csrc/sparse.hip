@@ -4,12 +4,12 @@
 //   its CSR (row-major) and CSC (column-major) structures are built once on
 //   the device, canonical (entries sorted by (row, col) / (col, row)).
 // * SpMM  out = A X  for the Krylov products A Omega, A (A^T H) and
-//   B^T = A^T Q of rSVD-BKI (Alg. 5 steps 2, 4, 8), with A the CSR of Y or
+//   B^T = A^T Q of rSVD-BKI (Alg. 5), with A the CSR of Y or
 //   the CSC of Y (= CSR of Y^T).  One wavefront per row segment; lanes span
 //   the panel columns; long rows are split into segments whose partial rows
 //   are summed in a fixed order by a second kernel, so results are
 //   deterministic.
-// * Fused SDDMM + residual + update (Alg. 6 steps 15-17): for every
+// * Fused SDDMM + residual + update (Eq. (6), Alg. 6): for every
 //   (i, j) in Phi, x = sum_t U_it sig_t V_jt, e = M_ij - x, Y_ij += delta e,
 //   and the squares e^2 are summed per block for the stop test.
 #include <hipcub/hipcub.hpp>
@@ -126,6 +126,22 @@ __global__ void scatter_kernel(int64_t nnz, const int32_t* __restrict__ idx,
     dst[idx[e]] = src[e];
 }
 
+// row i's entries [ptr[i], ptr[i+1]) get row id i; a pointer that does not
+// start at 0, end at nnz or never decrease sets err and writes nothing out of
+// [0, nnz)
+__global__ void csr_rows_kernel(int64_t m, int64_t nnz, const int64_t* __restrict__ ptr,
+                                int64_t* __restrict__ rows, int* __restrict__ err) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = ptr[i], e = ptr[i + 1];
+    if ((i == 0 && b != 0) || (i == m - 1 && e != nnz) || e < b || b < 0 || e > nnz) {
+      atomicOr(err, 1);
+      continue;
+    }
+    for (int64_t q = b; q < e; ++q) rows[q] = i;
+  }
+}
+
 inline unsigned grid_for(int64_t n, int threads) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, threads),
                                                           kMaxGrid));
@@ -138,6 +154,20 @@ int bits_for(uint64_t maxval) {
 }
 
 }  // namespace
+
+int csr_rows_device(int64_t m, int64_t nnz, const int64_t* d_ptr, int64_t* d_rows,
+                    hipStream_t st) {
+  DevBuf<int> err;
+  err.reserve(1, st);
+  MC_HIP(hipMemsetAsync(err.p, 0, sizeof(int), st));
+  hipLaunchKernelGGL(csr_rows_kernel, dim3(grid_for(m, 256)), dim3(256), 0, st, m, nnz,
+                     d_ptr, d_rows, err.p);
+  MC_CHECK_LAUNCH();
+  int herr = 0;
+  MC_HIP(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  MC_HIP(hipStreamSynchronize(st));
+  return herr ? kEINVAL : kOK;
+}
 
 // ---------------------------------------------------------------------------
 // Canonical CSR / CSC build of Phi.

@@ -1,5 +1,5 @@
-// Top-k eigenpairs of the symmetric Gram matrix of eigSVD (Alg. 3 step 2 and
-// Alg. 5 steps 9-10) inside one workgroup, for L small enough that the whole
+// Top-k eigenpairs of the symmetric Gram matrix of eigSVD (Alg. 3, and the
+// top-k selection of Alg. 5) inside one workgroup, for L small enough that the whole
 // matrix sits in LDS.
 //
 //   1. Householder reduction to tridiagonal form, T = Q^T G Q.  Step j

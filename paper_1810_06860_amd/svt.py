@@ -70,6 +70,30 @@ class SVT:
                                    C.byref(self._prm), st, C.byref(self._h))
         check(status, None)
 
+    @classmethod
+    def from_device(cls, m, n, rows, cols, vals, params=None, stream=None,
+                    is_csr=False):
+        """The same solve set up from device tensors (mc_svt_init_dev): rows
+        int64 (COO row ids, or the CSR row pointer with is_csr), cols int32,
+        vals float64, all contiguous on the GPU."""
+        import torch
+        for t, dt in ((rows, torch.int64), (cols, torch.int32), (vals, torch.float64)):
+            if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+                raise ValueError("rows, cols, vals must be contiguous GPU tensors "
+                                 "of int64, int32, float64")
+        self = cls.__new__(cls)
+        self.m, self.n = int(m), int(n)
+        self.nnz = int(vals.numel())
+        self._prm = to_params(params)
+        self._h = C.c_void_p()
+        st = stream if stream is not None else current_stream()
+        status = lib().mc_svt_init_dev(self.m, self.n, self.nnz, rows.data_ptr(),
+                                       cols.data_ptr(), vals.data_ptr(),
+                                       int(bool(is_csr)), C.byref(self._prm), st,
+                                       C.byref(self._h))
+        check(status, None)
+        return self
+
     # -- lifecycle --------------------------------------------------------
     def close(self):
         if self._h:

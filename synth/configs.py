@@ -93,6 +93,12 @@ def make_problem(name):
     return prob, cfg["params"](prob.m, prob.n, prob.nnz)
 
 
+SERVING_RANK_CAP = 256
+
+
 def serving_params(m, n, nnz):
-    """Per-request settings of the serving workload (no recycling)."""
-    return _base(m, n, nnz, eps=1e-4, i_max=200)
+    """Per-request settings of the serving workload (no recycling).  Each
+    request carries a rank cap (the planted ranks are at most 50), so the
+    device footprint that admission prices bounds what the solve holds."""
+    return _base(m, n, nnz, eps=1e-4, i_max=200,
+                 k_max=min(SERVING_RANK_CAP, m, n))

@@ -63,6 +63,17 @@ def test_footprint_grows_with_size(lib):
     assert footprint(0, 5, 5) == 0
 
 
+def test_footprint_prices_the_rank_cap(lib):
+    # k_max = 0 leaves the rank search bounded by min(m, n) alone, and the
+    # footprint prices exactly that bound
+    from paper_1810_06860_amd import footprint
+    full = footprint(600, 400, 40_000)
+    assert full == footprint(600, 400, 40_000, dict(k_max=400))
+    assert footprint(600, 400, 40_000, dict(k_max=50)) < full
+    assert footprint(600, 400, 40_000, dict(k_max=50, p_max=4)) < \
+        footprint(600, 400, 40_000, dict(k_max=50))
+
+
 def _init(m, n, rows, cols, vals, params=None):
     from paper_1810_06860_amd import SVT
     return SVT(m, n, rows, cols, vals, params)

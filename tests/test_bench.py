@@ -30,7 +30,7 @@ def test_arguments_and_defaults():
         a = b.parse()
     finally:
         sys.argv = old
-    assert (a.gpus, a.workload, a.precision) == (1, "image1024", "fp64")
+    assert (a.gpus, a.workload, a.precision) == (1, "ratings140k", "fp64")
     assert a.steps > 0 and a.warmup >= 0
 
 
@@ -46,7 +46,17 @@ def test_roofline_picks_the_dominant_family():
     assert abs(roof["frac"] - roof["achieved"] / 8000.0) < 1e-4
     prof["gram"] = dict(launches=5, ms=2.0, bytes=1e8, flops=4e9)
     dom, roof = b.roofline(prof, "fp64", "no-such-workload")
-    assert dom == "gram"
+    # 40 FLOP/B is past the FP64 ridge (9.8): the matrix-core peak bounds it
+    assert dom == "gram" and roof["bound"] == "mfma" and roof["unit"] == "TFLOP/s"
+    assert abs(roof["achieved"] - 4e9 / 5 / 0.4e-3 / 1e12) < 1e-3
+    # a sparse product past the ridge is bound by the vector ALUs
+    dom, roof = b.roofline({"spmm_bwd": dict(launches=1, ms=1.0, bytes=1e8, flops=2e9)},
+                           "fp64", "no-such-workload", copy_gbps=6000.0)
+    assert roof["bound"] == "alu" and "copy_roof_GBps" not in roof
+    dom, roof = b.roofline({"spmm_bwd": dict(launches=1, ms=1.0, bytes=1e9, flops=2e9)},
+                           "fp64", "no-such-workload", copy_gbps=6000.0)
+    assert roof["bound"] == "hbm" and roof["copy_roof_GBps"] == 6000.0
+    assert abs(roof["frac_of_copy_roof"] - 1000.0 / 6000.0) < 1e-4
     # alone, it reports its flop rate against the FP64 vector peak
     dom, roof = b.roofline({"eigensolve": prof["eigensolve"]}, "fp64", "no-such-workload")
     assert dom == "eigensolve" and roof["bound"] == "alu" and roof["traffic"] is None

@@ -14,7 +14,11 @@ def _X(f):
     return (U * s) @ V.T
 
 
-def test_served_results_equal_alone_and_close_to_fp64():
+@pytest.mark.parametrize("graphs", [False, True])
+def test_served_results_equal_alone_and_close_to_fp64(graphs):
+    # the bench serves with captured graphs (relaxed capture from several host
+    # threads over shared streams): both forms must give each request the
+    # bits of its solve alone
     import torch
     from paper_1810_06860_amd import SVT, serving
     desc = synth.serving_trace(num=8, mean_gap_s=0.003, mn_range=(200, 500),
@@ -34,7 +38,7 @@ def test_served_results_equal_alone_and_close_to_fp64():
     reqs = [serving.Request(j, d["t_arrival"], p, prm)
             for j, (d, p, prm) in enumerate(zip(desc, problems, params))]
     served = serving.serve(reqs, budget_bytes=1 << 34, max_active=8, keep_factors=True,
-                           stream_pool=streams)
+                           stream_pool=streams, graphs=graphs)
     torch.cuda.synchronize()
     assert sorted(s.id for s in served) == list(range(len(desc)))
     for s in served:

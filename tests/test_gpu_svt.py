@@ -132,15 +132,15 @@ def test_svt_steps_match_oracle_ratings_scaled(name, steps):
         assert (gi["r"], gi["k"], gi["p"], gi["fresh"], gi["recycled"], gi["rejected"]) == \
             (oi.r, oi.k, oi.p, oi.fresh, oi.recycled, oi.rejected), i
         worst = max(worst, abs(gi["res"] - oi.res) / oi.res)
-        np.testing.assert_allclose(g.sigma(), oi.S, rtol=1e-7)
+        np.testing.assert_allclose(g.sigma(), oi.S, rtol=1e-8)
     U, sig, V = g.factors()
     Xg = (U * sig) @ V.T
     Xo = (orc.U * orc.sig) @ orc.V.T
     rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
     print(f"{name}: {steps} steps, rank {g.result()['rank']}, res {gi['res']:.4f}, "
           f"max res rel diff {worst:.1e}, X rel diff {rel:.1e}")
-    assert worst < 1e-7
-    assert rel < 1e-7
+    assert worst < 1e-8
+    assert rel < 1e-8
 
 
 @pytest.mark.parametrize("recycle,ritz_tol", [(2, 1e-4), (2, 0.0), (1, 0.0)])

@@ -113,3 +113,11 @@ def test_band_schedule_rejects_bad_input(K):
                                  (np.array([1, 3, 1], np.int32), 10, 12)):  # bands % 8
         with pytest.raises(MCError):
             K.band_schedule(ptr, idx, gathered, 64, bands)
+    # a NULL idx with non-empty rows is an error, not a crash
+    import ctypes as C
+    from paper_1810_06860_amd import lib
+    nseg, nfix, nslot = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    st = lib().mc_k_band_schedule(2, ptr.ctypes.data_as(C.POINTER(C.c_int32)), None,
+                                  10, 64, 8, None, C.byref(nseg), None, C.byref(nfix),
+                                  C.byref(nslot))
+    assert st == 1                                  # MC_EINVAL
