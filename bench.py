@@ -9,8 +9,11 @@ A "step" is one iteration of the fast SVT algorithm (Alg. 6): the rank
 search with rSVD-BKI (or a recycled basis), shrinkage, the residual on Phi
 and the update of Y.  The default workload is the largest rating shape
 (140,000 x 27,000, 2.0e7 observed integer ratings, rank cap 100) in FP64.
-The solve starts untimed (problem set-up and W warm-up steps), then K
-consecutive steps are timed with the stream synchronised on both sides.  All
+The solve starts untimed (problem set-up, then its first steps up to the
+middle of the step budget -- `--start-step`, half of i_max by default -- and W
+warm-up steps), then K consecutive steps are timed with the stream
+synchronised on both sides, so the window sees the ranks, block widths and
+recycled calls of the solve's middle rather than its first, rank-1 steps.  All
 inputs and solver state are resident in HBM for the whole timed region.
 Beside that window the line reports the same solve run whole (steps/s from
 the first step to i_max or convergence), the BF16 form against it, per-kernel
@@ -79,6 +82,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--start-step", type=int, default=-1,
+                    help="untimed solve steps run before the warm-up, so that the "
+                         "timed window sits inside the solve (-1: half of i_max; "
+                         "0: the window starts at the solve's first step)")
     ap.add_argument("--workload", default="ratings140k")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=30.0)
@@ -204,16 +211,22 @@ def family_table(prof, total_s, prec="fp64"):
 
 def factored_rel_diff(f1, f2):
     """||U1 S1 V1^T - U2 S2 V2^T||_F / ||U2 S2 V2^T||_F without forming the
-    matrices (they can be 140,000 x 27,000)."""
+    matrices (they can be 140,000 x 27,000).  The difference is A B^T with
+    A = [U1 S1, -U2 S2], B = [V1, V2]; with B = Q R (reduced QR) its norm is
+    ||A R^T||_F, which subtracts the two factorisations entry by entry.  The
+    trace form ||X1||^2 + ||X2||^2 - 2<X1, X2> would cancel in the squares and
+    resolve no relative difference below about 1e-8."""
     import numpy as np
     U1, s1, V1 = f1
     U2, s2, V2 = f2
-    A = np.hstack([U1 * s1, -(U2 * s2)])
-    B = np.hstack([V1, V2])
-    num = np.sum((A.T @ A) * (B.T @ B))
     A2 = U2 * s2
-    den = np.sum((A2.T @ A2) * (V2.T @ V2))
-    return np.sqrt(max(num, 0.0) / den) if den > 0 else 0.0
+    den = np.linalg.norm(A2 @ np.linalg.qr(V2, mode="r").T) if V2.shape[1] else 0.0
+    if V1.shape[1] + V2.shape[1] == 0:
+        return 0.0
+    A = np.hstack([U1 * s1, -A2])
+    R = np.linalg.qr(np.hstack([V1, V2]), mode="r")
+    num = np.linalg.norm(A @ R.T)
+    return num / den if den > 0 else float(num)
 
 
 def cpu_baseline(prob, prm, budget_s, max_steps):
@@ -452,7 +465,8 @@ def main():
         f"nnz {prob.nnz}")
     prm = dict(prm)
     prm["precision"] = a.precision
-    prm["i_max"] = max(prm["i_max"], a.warmup + a.steps)
+    start = prm["i_max"] // 2 if a.start_step < 0 else a.start_step
+    prm["i_max"] = max(prm["i_max"], start + a.warmup + a.steps)
     if a.ritz_tol is not None:
         prm["ritz_tol"] = a.ritz_tol
     if a.eager:
@@ -461,11 +475,12 @@ def main():
     log(f"device copy roof: {copy_gbps:.0f} GB/s")
     solver = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals, prm)
     warm = []
-    for _ in range(a.warmup):
+    for _ in range(start + a.warmup):
         info = solver.step()
         warm.append(info)
         if info["converged"]:
-            raise SystemExit("workload converged during warm-up; lower --warmup")
+            raise SystemExit("workload converged before the timed window; lower "
+                             "--start-step or --warmup")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     infos, step_ms = [], []
@@ -482,7 +497,8 @@ def main():
     dt = t1 - t0
     value = done / dt
     log(f"timed: {done} steps in {dt:.3f} s")
-    window = dict(first_step=a.warmup + 1, last_step=a.warmup + done,
+    window = dict(first_step=start + a.warmup + 1, last_step=start + a.warmup + done,
+                  untimed_before=dict(solve_steps=start, warmup=a.warmup),
                   rank=[min(i["r"] for i in infos), max(i["r"] for i in infos)],
                   k=[min(i["k"] for i in infos), max(i["k"] for i in infos)],
                   p=sorted({i["p"] for i in infos}),
@@ -494,7 +510,7 @@ def main():
     # launches and HIP events around each launch on the solve's stream.
     prof_solver = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals,
                       dict(prm, use_graphs=0))
-    for _ in range(a.warmup):
+    for _ in range(start + a.warmup):
         prof_solver.step()
     prof_solver.profile(True)
     torch.cuda.synchronize()
@@ -516,7 +532,8 @@ def main():
     U, sig, V = solver.factors()
     solver.close()
     acc = dict(res_last=infos[-1]["res"], rank=infos[-1]["r"],
-               steps_total=a.warmup + done, converged=bool(infos[-1]["converged"]))
+               steps_total=start + a.warmup + done,
+               converged=bool(infos[-1]["converged"]))
     # the solve run whole, and its reduced-precision forms against it
     whole, modes, whole_f = None, {}, None
     if a.whole:
@@ -529,7 +546,7 @@ def main():
         # the plain FP64 form on the same GPU, same steps: speed and distance
         ref = SVT(prob.m, prob.n, prob.rows, prob.cols, prob.vals,
                   dict(prm, precision="fp64"))
-        for _ in range(a.warmup):
+        for _ in range(start + a.warmup):
             ref.step()
         torch.cuda.synchronize()
         r0 = time.perf_counter()
@@ -561,7 +578,8 @@ def main():
                                                     np.linalg.norm(t))
     cpu = None
     if not a.no_cpu_baseline:
-        orc, oinfos, cpu = cpu_baseline(prob, prm, a.cpu_seconds, a.warmup + done)
+        orc, oinfos, cpu = cpu_baseline(prob, prm, a.cpu_seconds,
+                                          start + a.warmup + done)
         log(f"cpu baseline: {cpu['value']} steps/s over {len(oinfos)} steps")
         # a fresh GPU solve against the oracle, step by step from step 1
         gpu_hist = warm + infos

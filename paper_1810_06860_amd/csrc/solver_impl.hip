@@ -8,18 +8,23 @@
 //   (Lemmas 2 and 3), so Q = [Q_0 .. Q_p] is already orthonormal;
 //   B^T = Y^T Q; eigSVD(B^T): G = B B^T, eig(G), top k, S = sqrt(lambda),
 //   U = Q W_k, V = B^T W_k S^-1.
+//   Because every Q_j is final once it is formed, the Krylov product
+//   Y^T Q_{j-1} is already block j-1 of B^T: the loop writes it there, and
+//   B^T needs one more product of width b (Y^T Q_p) instead of one of width
+//   (p + 1) b.
 //
 // Precision: P is the type of the dense panels (Omega, H, Q, B^T, U, V), VT
-// the type of the copies of Y read by the Krylov SpMMs of Alg. 5,
-// AT the accumulator of SpMM / Gram / SDDMM dot products.  The Rayleigh-Ritz
-// product B^T = Y^T Q, the Ritz guard and the SDDMM read Y in the panel
+// the type of the copies of Y read by the forward Krylov SpMMs Y X of Alg. 5
+// (and by both products of rSVD-PI), AT the accumulator of SpMM / Gram /
+// SDDMM dot products.  The products Y^T Q_j (blocks of the Rayleigh-Ritz
+// product B^T = Y^T Q), the Ritz guard and the SDDMM read Y in the panel
 // precision P, so the singular values are those of the computed subspace to
 // that precision whatever VT is.  The master copy of Y, M_Phi, every Gram
 // result, the Cholesky factors, the eigensolve and the residual sums are FP64
 // in all modes:
 //   FP64       P = double, VT = double, AT = double
 //   FP32       P = float,  VT = float,  AT = float
-//   BF16       P = float,  VT = bf16,   AT = float   (Krylov values in BF16)
+//   BF16       P = float,  VT = bf16,   AT = float   (forward Krylov values in BF16)
 #include <cmath>
 #include <cstring>
 #include <type_traits>
@@ -104,7 +109,8 @@ class SolverT final : public Solver {
  private:
   using GraphKey = std::array<int64_t, 8>;
   void ensure(int bmax, int Lmax, int kmax);
-  void eig_body(const P* basis, int64_t ldb, int w, int k);
+  // have_bt: B^T = Y^T basis is already in Bt_ (leading dimension w)
+  void eig_body(const P* basis, int64_t ldb, int w, int k, bool have_bt = false);
   void fresh_body(int k, int b, int p_eff, int Lw, bool guarded);
   void ritz_body(int k);
   void read_launch(int k, bool ritz, bool count = false);
@@ -426,8 +432,9 @@ double SolverT<P, VT, AT>::read_finish(int k, bool ritz) {
 // eigSVD of B^T = Y^T basis (Alg. 3 on B^T, the Rayleigh-Ritz end of Alg. 5):
 // kernels only
 template <class P, class VT, class AT>
-void SolverT<P, VT, AT>::eig_body(const P* basis, int64_t ldb, int w, int k) {
-  spmm_yt_rr(basis, ldb, Bt_.p, w, w);                       // B^T = Y^T basis
+void SolverT<P, VT, AT>::eig_body(const P* basis, int64_t ldb, int w, int k,
+                                  bool have_bt) {
+  if (!have_bt) spmm_yt_rr(basis, ldb, Bt_.p, w, w);         // B^T = Y^T basis
   prof.begin(kProfGram, (double)sizeof(P) * n_ * w, 1.0 * n_ * w * (w + 1), ls());
   launch_gram<P, AT>(n_, w, w, Bt_.p, w, Bt_.p, w, G_.p, w, 1, gram_part_.p,
                      gram_cap_, ls());                       // G = B B^T (FP64)
@@ -473,12 +480,16 @@ void SolverT<P, VT, AT>::fresh_body(int k, int b, int p_eff, int Lw, bool guarde
     eig_body(Qw_.p, Lw, Lw, k);
     return;
   }
+  // Y^T Q_{j-1} goes straight into columns [(j-1) b, j b) of B^T; it reads
+  // Y in the Rayleigh-Ritz precision, as B^T does
   for (int j = 1; j <= p_eff; ++j) {
-    spmm_yt(Qw_.p + (int64_t)(j - 1) * b, Lw, Z_.p, b, b);   // Y^T Q_{j-1}
-    spmm_y(Z_.p, b, H1_.p, b, b);                            // H_j
+    P* zj = Bt_.p + (int64_t)(j - 1) * b;
+    spmm_yt_rr(Qw_.p + (int64_t)(j - 1) * b, Lw, zj, Lw, b); // Y^T Q_{j-1}
+    spmm_y(zj, Lw, H1_.p, b, b);                             // H_j
     orth_block(j, b, Lw, guarded);
   }
-  eig_body(Qw_.p, Lw, Lw, k);
+  spmm_yt_rr(Qw_.p + (int64_t)p_eff * b, Lw, Bt_.p + (int64_t)p_eff * b, Lw, b);
+  eig_body(Qw_.p, Lw, Lw, k, true);
 }
 
 template <class P, class VT, class AT>
