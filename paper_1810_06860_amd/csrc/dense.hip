@@ -318,14 +318,15 @@ __global__ __launch_bounds__(GramTailThreads) void gram_kernel(
 // Matrix-core Gram: the same partial products as gram_kernel, computed with
 // the 16x16x4 FP64 / FP32 MFMA instructions.  A workgroup owns a 128 x 128
 // output block and a range of rows, so each row of A and B is read by as few
-// workgroups as possible; each of its four wavefronts owns a 64 x 64 quarter
-// (4 x 4 instruction tiles accumulated in registers).  Instruction tiles that
-// lie wholly outside p x q are skipped.  For a symmetric product only blocks
-// on and above the diagonal run, and on a diagonal block the quarter below
-// the diagonal is skipped: the reduction reads it mirrored (granularity 64).
-// Rows pass through LDS 16 at a time, loaded one stage ahead into registers.
+// workgroups as possible.  The block's 16 x 16 instruction tiles that lie in
+// p x q -- and, on a diagonal block of a symmetric product, on or above the
+// diagonal (the reduction reads the others mirrored, granularity 16) -- are
+// dealt round-robin to the four wavefronts, so no wavefront computes tiles
+// outside the result and the matrix cores of the four SIMDs stay evenly
+// loaded whatever p and q are.  Rows pass through LDS 16 at a time, loaded
+// one stage ahead into registers.
 constexpr int MB = 128;  // output block of gram_mfma_kernel
-constexpr int MQ = 64;   // quarter of a wavefront; mirror granularity
+constexpr int MT = 16;   // instruction tile; mirror granularity
 constexpr int MK = 16;   // rows per LDS stage
 
 template <class T> struct Mfma16;
@@ -345,16 +346,15 @@ template <> struct Mfma16<float> {
   static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane / 16) + v; }
 };
 
-// The row loop of gram_mfma_kernel for one block kind: SAME (diagonal block
-// of a symmetric product: B is A), NI x NJ instruction tiles of the
-// wavefront's quarter (0: loads only).  Everything that varies inside the
-// loop is a template parameter, so the loop body has no branches; only the
-// last, partial stage uses row-guarded loads.
-template <class T, bool SAME, int NI, int NJ>
+// The row loop of gram_mfma_kernel: SAME (diagonal block of a symmetric
+// product: B is A), up to TW instruction tiles per wavefront (tile t of this
+// wavefront is (ti[t], tj[t]) in units of 16 inside the block, nt of them).
+// Only the last, partial stage uses row-guarded loads.
+template <class T, bool SAME, int TW>
 __device__ __forceinline__ void gram_mfma_rows(
     int64_t n0, int64_t n1, int p, int q, const T* __restrict__ A, int64_t lda,
     const T* __restrict__ B, int64_t ldb, T* __restrict__ out, int a0, int b0,
-    int wr, int wc, T (*As)[MB + 1], T (*Bs)[MB + 1]) {
+    const int* ti, const int* tj, int nt, T (*As)[MB + 1], T (*Bs)[MB + 1]) {
   using M = Mfma16<T>;
   using V = typename M::V;
   constexpr int LPT = MK * MB / 256;          // elements per thread and stage
@@ -381,13 +381,12 @@ __device__ __forceinline__ void gram_mfma_rows(
       }
     }
   };
-  V acc[NI > 0 ? NI : 1][NJ > 0 ? NJ : 1];
+  V acc[TW];
 #pragma unroll
-  for (int i = 0; i < (NI > 0 ? NI : 1); ++i)
+  for (int t = 0; t < TW; ++t)
 #pragma unroll
-    for (int j = 0; j < (NJ > 0 ? NJ : 1); ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[i][j][v] = T(0);
+    for (int v = 0; v < 4; ++v) acc[t][v] = T(0);
+  const int cc = lane % 16, kq = lane / 16;
   fetch(n0);
   for (int64_t nb = n0; nb < n1; nb += MK) {
 #pragma unroll
@@ -397,39 +396,34 @@ __device__ __forceinline__ void gram_mfma_rows(
     }
     __syncthreads();
     if (nb + MK < n1) fetch(nb + MK);         // in flight during the products
-    if (NI > 0 && NJ > 0) {
-      T(*Bt)[MB + 1] = SAME ? As : Bs;
+    T(*Bt)[MB + 1] = SAME ? As : Bs;
 #pragma unroll
-      for (int kk = 0; kk < MK; kk += 4) {
-        const int kr = kk + lane / 16, cc = lane % 16;
-        T x[NI > 0 ? NI : 1], y[NJ > 0 ? NJ : 1];
+    for (int kk = 0; kk < MK; kk += 4) {
+      const int kr = kk + kq;
 #pragma unroll
-        for (int i = 0; i < NI; ++i) x[i] = As[kr][wr * MQ + i * 16 + cc];
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) y[j] = Bt[kr][wc * MQ + j * 16 + cc];
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) acc[i][j] = M::op(x[i], y[j], acc[i][j]);
+      for (int t = 0; t < TW; ++t) {
+        if (t < nt) {                          // uniform across the wavefront
+          const T x = As[kr][ti[t] * 16 + cc];
+          const T y = Bt[kr][tj[t] * 16 + cc];
+          acc[t] = M::op(x, y, acc[t]);
+        }
       }
     }
     __syncthreads();
   }
-  if (NI == 0 || NJ == 0) return;
-  const int ra0 = a0 + wr * MQ, cb0 = b0 + wc * MQ;
 #pragma unroll
-  for (int i = 0; i < NI; ++i)
+  for (int t = 0; t < TW; ++t) {
+    if (t >= nt) continue;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = ra0 + i * 16 + M::row(lane, v);
-        const int c = cb0 + j * 16 + lane % 16;
-        if (r < p && c < q) out[(int64_t)r * q + c] = acc[i][j][v];
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int r = a0 + ti[t] * 16 + M::row(lane, v);
+      const int c = b0 + tj[t] * 16 + cc;
+      if (r < p && c < q) out[(int64_t)r * q + c] = acc[t][v];
+    }
+  }
 }
 
-template <class T>
+template <class T, int TW>
 __global__ __launch_bounds__(256) void gram_mfma_kernel(
     int64_t N, int p, int q, const T* __restrict__ A, int64_t lda,
     const T* __restrict__ B, int64_t ldb, T* __restrict__ part,
@@ -440,35 +434,40 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(
   __shared__ T As[MK][MB + 1];
   __shared__ T Bs[MK][MB + 1];
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int wr = w >> 1, wc = w & 1;
   const int a0 = bi * MB, b0 = bj * MB;
   const int64_t n0 = (int64_t)sp * rows_per_split;
   const int64_t n1 = min(N, n0 + rows_per_split);
   if (n0 >= n1) return;
   const bool same = sym && bi == bj;
-  // instruction tiles of this wavefront's quarter that touch p x q, rounded
-  // up to 2 or 4 (0: the quarter is outside, or mirrored)
-  auto tiles = [](int rem) { return rem <= 0 ? 0 : (rem <= 32 ? 2 : 4); };
-  int ni = tiles(p - a0 - wr * MQ), nj = tiles(q - b0 - wc * MQ);
-  if (same && wr > wc) ni = 0;
-  if (ni == 0 || nj == 0) ni = nj = 0;
-  T* out = part + (int64_t)sp * p * q;
-#define MC_GRAM_ROWS(S, I, J)                                                      \
-  gram_mfma_rows<T, S, I, J>(n0, n1, p, q, A, lda, B, ldb, out, a0, b0, wr, wc, As, \
-                             Bs)
-#define MC_GRAM_KIND(S)                            \
-  if (ni == 0) MC_GRAM_ROWS(S, 0, 0);              \
-  else if (ni == 4 && nj == 4) MC_GRAM_ROWS(S, 4, 4); \
-  else if (ni == 4) MC_GRAM_ROWS(S, 4, 2);         \
-  else if (nj == 4) MC_GRAM_ROWS(S, 2, 4);         \
-  else MC_GRAM_ROWS(S, 2, 2);
-  if (same) {
-    MC_GRAM_KIND(true)
-  } else {
-    MC_GRAM_KIND(false)
+  // the block's tiles inside p x q (upper ones on a symmetric diagonal
+  // block) in row-major order; this wavefront takes tiles w, w + 4, ...
+  const int nti = min(MB / 16, (p - a0 + 15) / 16);
+  const int ntj = min(MB / 16, (q - b0 + 15) / 16);
+  const int total = same ? nti * (nti + 1) / 2 : nti * ntj;
+  const int nt = min(TW, (total - w + 3) / 4);
+  int ti[TW], tj[TW];
+#pragma unroll
+  for (int t = 0; t < TW; ++t) {
+    int g = w + 4 * t, i = 0;
+    if (same) {
+      while (i < nti - 1 && g >= ntj - i) {
+        g -= ntj - i;
+        ++i;
+      }
+      ti[t] = i;
+      tj[t] = i + g;
+    } else {
+      ti[t] = g / ntj;
+      tj[t] = g % ntj;
+    }
   }
-#undef MC_GRAM_KIND
-#undef MC_GRAM_ROWS
+  T* out = part + (int64_t)sp * p * q;
+  if (same)
+    gram_mfma_rows<T, true, TW>(n0, n1, p, q, A, lda, B, ldb, out, a0, b0, ti, tj, nt,
+                                As, Bs);
+  else
+    gram_mfma_rows<T, false, TW>(n0, n1, p, q, A, lda, B, ldb, out, a0, b0, ti, tj,
+                                 nt, As, Bs);
 }
 
 // Sum of the split partials.  `lanes` consecutive threads (a power of two
@@ -835,15 +834,33 @@ void launch_gram(int64_t N, int p, int q, const IT* A, int64_t lda, const IT* B,
   splits = std::max<int64_t>(1, ceil_div(std::max<int64_t>(N, 1), rps));
   dim3 grid((unsigned)ceil_div(p, MB), (unsigned)ceil_div(q, MB), (unsigned)splits);
   static_assert(std::is_same<IT, AT>::value, "the matrix-core Gram accumulates in its input type");
-  hipLaunchKernelGGL((gram_mfma_kernel<AT>), grid, dim3(256), 0, st, N, p, q, A,
-                     lda, B, ldb, part, rps, sym, gate);
+  // tiles per wavefront of the fullest block: the first one (a diagonal
+  // block of a symmetric product holds only its upper tiles)
+  const int nti0 = (int)std::min<int64_t>(MB / 16, ceil_div(p, 16));
+  const int ntj0 = (int)std::min<int64_t>(MB / 16, ceil_div(q, 16));
+  const int most = (sym && p <= MB) ? nti0 * (nti0 + 1) / 2 : nti0 * ntj0;
+  const int per_wave = (int)ceil_div(most, 4);
+#define MC_GRAM_MFMA(TW)                                                        \
+  hipLaunchKernelGGL((gram_mfma_kernel<AT, TW>), grid, dim3(256), 0, st, N, p, q, A, \
+                     lda, B, ldb, part, rps, sym, gate)
+  if (per_wave <= 1)
+    MC_GRAM_MFMA(1);
+  else if (per_wave <= 2)
+    MC_GRAM_MFMA(2);
+  else if (per_wave <= 4)
+    MC_GRAM_MFMA(4);
+  else if (per_wave <= 8)
+    MC_GRAM_MFMA(8);
+  else
+    MC_GRAM_MFMA(16);
+#undef MC_GRAM_MFMA
   MC_CHECK_LAUNCH();
   const int64_t tot = (int64_t)p * q;
   int lanes = 1;   // threads per output: about 16 splits each, at most 64
   while (lanes < 64 && lanes * 16 < splits) lanes <<= 1;
   const int64_t per_block = 256 / lanes;
   hipLaunchKernelGGL((gram_reduce_kernel<AT>), dim3((unsigned)ceil_div(tot, per_block)),
-                     dim3(256), 0, st, p, q, (int)splits, lanes, part, C, ldc, sym, MQ,
+                     dim3(256), 0, st, p, q, (int)splits, lanes, part, C, ldc, sym, MT,
                      gate);
   MC_CHECK_LAUNCH();
 }
