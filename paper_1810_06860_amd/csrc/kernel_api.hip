@@ -289,7 +289,7 @@ mc_status mc_k_sddmm(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
       upload(dV, V, n * r, st);
       upload(dsig, sig, r, st);
     }
-    part.reserve(mcsvt::sddmm_partials(nnz), st);
+    part.reserve(mcsvt::sddmm_partials(L), st);
     scal.reserve(1, st);
     dx.reserve(nnz, st);
     if (r > 0) {

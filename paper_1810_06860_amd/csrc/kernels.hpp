@@ -112,7 +112,7 @@ void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
                  const XT* X, int64_t ldx, OT* out, int64_t ldo, int b,
                  AT* part, hipStream_t st);
 
-int64_t sddmm_partials(int64_t nnz);
+int64_t sddmm_partials(const Layout& L);   // residual partial sums of the SDDMM (and of launch_sumsq)
 // FT factor type, AT accumulator, VT / WT types of the operator copies of Y
 // (Krylov / Rayleigh-Ritz products); null copies are skipped
 template <class FT, class AT, class VT, class WT>

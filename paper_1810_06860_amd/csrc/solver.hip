@@ -300,8 +300,10 @@ size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& p
   const int64_t Lb = std::min<int64_t>(L, 1024), kb = std::min<int64_t>(Lb, 140);
   bytes += (size_t)8 * (L * L);
   bytes += (size_t)8 * TriBigWork::doubles((int)Lb, (int)kb);
-  // SpMM partial rows (slots x the widest panel), SDDMM partials, P_Phi(X)
-  bytes += (size_t)8 * (slots * std::max({b, L, k}) + ceil_div(nnz, 256) + nnz);
+  // SpMM partial rows (slots x the widest panel), SDDMM partials (one per
+  // workgroup of row segments, or per 256 entries), P_Phi(X)
+  bytes += (size_t)8 * (slots * std::max({b, L, k}) +
+                        std::max(ceil_div(nnz, 256), ceil_div(m + slots, kSpmmWaves)) + nnz);
   return bytes;
 }
 

@@ -254,7 +254,7 @@ int SolverT<P, VT, AT>::init(const int64_t* rows, const int32_t* cols,
   }
   launch_gather(nnz_, L_.order.p, pv, mvals_.p, st_);
   ensure(1, 1, 1);
-  sdd_part_.reserve(sddmm_partials(nnz_), st_);
+  sdd_part_.reserve(sddmm_partials(L_), st_);
   scal_.reserve(8, st_);
   launch_sumsq(nnz_, mvals_.p, sdd_part_.p, scal_.p, st_);
   MC_HIP(hipMemcpyAsync(hbuf_, scal_.p, sizeof(double), hipMemcpyDeviceToHost, st_));

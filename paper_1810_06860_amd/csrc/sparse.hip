@@ -634,8 +634,6 @@ template void launch_spmm<bf16_t, float, float, float>(
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int kSddmmThreads = 256;
-constexpr int kMaxRankLds = 2048;
 
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -655,40 +653,94 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 // FP64 master Y in double; the operator copies of Y are refreshed from the
 // master: CSR / CSC copies of type VT (Krylov products) and WT (Rayleigh-Ritz
 // products); a null pointer skips a copy (e.g. when the master serves).
-template <class FT, class AT, class VT, class WT>
-__global__ __launch_bounds__(kSddmmThreads) void sddmm_update_kernel(
-    int64_t nnz, const int32_t* __restrict__ row_of,
-    const int32_t* __restrict__ col_idx, const double* __restrict__ mvals,
-    double* __restrict__ y, VT* __restrict__ yv, VT* __restrict__ ycv,
-    WT* __restrict__ yw, WT* __restrict__ ycw,
+//
+// One wavefront per CSR segment (a row, or a piece of a long row).  The
+// row's u_i diag(sig) stays in registers (CPL columns per lane); BW lanes
+// share one nonzero and gather its row of V, a butterfly over those BW lanes
+// completes the dot product, and a shuffle hands the sum to the lane that
+// holds the nonzero's M, Y and index, which forms the residual and the
+// update.  Columns beyond r carry weight zero; ranks above BW * CPL take
+// several passes.  Partial residual sums: one per workgroup, in a fixed
+// order.
+template <class FT, class AT, class VT, class WT, int BW, int CPL>
+__global__ __launch_bounds__(64 * kSpmmWaves) void sddmm_update_kernel(
+    int64_t nseg, const int4* __restrict__ segs, const int32_t* __restrict__ col_idx,
+    const double* __restrict__ mvals, double* __restrict__ y, VT* __restrict__ yv,
+    VT* __restrict__ ycv, WT* __restrict__ yw, WT* __restrict__ ycw,
     const int32_t* __restrict__ invperm, const FT* __restrict__ U, int64_t ldu,
-    const FT* __restrict__ V, int64_t ldv, const double* __restrict__ sig,
-    int r, double delta, int apply, double* __restrict__ partial) {
-  __shared__ AT ssig[kMaxRankLds];
-  __shared__ double sh[kSddmmThreads];
-  for (int t = threadIdx.x; t < r; t += blockDim.x) ssig[t] = (AT)sig[t];
-  __syncthreads();
-  const int64_t e = blockIdx.x * (int64_t)kSddmmThreads + threadIdx.x;
+    const FT* __restrict__ V, int64_t ldv, const double* __restrict__ sig, int r,
+    double delta, int apply, double* __restrict__ partial) {
+  constexpr int G = 64 / BW;       // nonzeros side by side
+  constexpr int CB = BW * CPL;     // columns per pass
+  __shared__ double red[kSpmmWaves];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t wave = (int64_t)blockIdx.x * kSpmmWaves + wv;
   double d2 = 0.0;
-  if (e < nnz) {
-    const FT* u = U + (int64_t)row_of[e] * ldu;
-    const FT* v = V + (int64_t)col_idx[e] * ldv;
-    AT x = 0;
-    for (int t = 0; t < r; ++t) x += ((AT)u[t] * ssig[t]) * (AT)v[t];
-    const double d = mvals[e] - (double)x;
-    d2 = d * d;
-    if (apply) {
-      const double yn = y[e] + delta * d;
-      y[e] = yn;
-      const int32_t ec = invperm[e];
-      if (yv) yv[e] = (VT)yn;
-      if (ycv) ycv[ec] = (VT)yn;
-      if (yw) yw[e] = (WT)yn;
-      if (ycw) ycw[ec] = (WT)yn;
+  const int4 sg = wave < nseg ? segs[wave] : make_int4(-1, 0, 0, -1);
+  if (sg.x >= 0) {
+    const int g = lane / BW, c = lane % BW;
+    const FT* urow = U + (int64_t)sg.x * ldu;
+    for (int base = sg.y; base < sg.z; base += 64) {
+      const int e = base + lane;
+      const bool ok = e < sg.z;
+      const int my_col = ok ? ld_stream(col_idx + e) : 0;
+      const int left = sg.z - base;
+      AT xl = 0;                               // x of nonzero `e` (this lane)
+      for (int c0 = 0; c0 < r; c0 += CB) {
+        AT uu[CPL];
+        int colc[CPL];
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+          const int col = c0 + c + t * BW;
+          colc[t] = col < r ? col : r - 1;
+          uu[t] = col < r ? (AT)urow[col] * (AT)sig[col] : (AT)0;
+        }
+        // two halves of 32 nonzeros: the gathers of a half are independent
+        // and issued back to back; a short tail skips the second half
+#pragma unroll
+        for (int h = 0; h < 64; h += 32) {
+          if (h >= left) break;                // uniform: the wave's segment
+#pragma unroll
+          for (int jj = h; jj < h + 32; jj += G) {
+            const int jc = __shfl(my_col, jj + g);
+            const FT* vr = V + (int64_t)jc * ldv;
+            AT pdot = 0;
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) pdot += uu[t] * (AT)vr[colc[t]];
+#pragma unroll
+            for (int off = 1; off < BW; off <<= 1) pdot += __shfl_xor(pdot, off);
+            // nonzero jj + g's sum sits in every lane of group g; lane
+            // jj + g' takes group g''s
+            const bool mine = lane >= jj && lane < jj + G;
+            const AT got = __shfl(pdot, mine ? (lane - jj) * BW : 0);
+            if (mine) xl += got;
+          }
+        }
+      }
+      if (ok) {
+        const double d = ld_stream(mvals + e) - (double)xl;
+        d2 += d * d;
+        if (apply) {
+          const double yn = y[e] + delta * d;
+          y[e] = yn;
+          const int32_t ec = ld_stream(invperm + e);
+          if (yv) yv[e] = (VT)yn;
+          if (ycv) ycv[ec] = (VT)yn;
+          if (yw) yw[e] = (WT)yn;
+          if (ycw) ycw[ec] = (WT)yn;
+        }
+      }
     }
   }
-  const double s = block_sum<kSddmmThreads>(d2, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) d2 += __shfl_xor(d2, off);
+  if (lane == 0) red[wv] = d2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kSpmmWaves; ++w) s += red[w];
+    partial[blockIdx.x] = s;
+  }
 }
 
 template <class FT>
@@ -737,7 +789,9 @@ __global__ void scale_kernel(int64_t n, const double* __restrict__ a,
 
 }  // namespace
 
-int64_t sddmm_partials(int64_t nnz) { return ceil_div(nnz, kSddmmThreads); }
+int64_t sddmm_partials(const Layout& L) {
+  return std::max<int64_t>(ceil_div(L.nnz, 256), ceil_div(L.sched_csr.nseg, kSpmmWaves));
+}
 
 template <class FT, class AT, class VT, class WT>
 void launch_sddmm_update(const Layout& L, const double* mvals, double* y, VT* yv,
@@ -745,12 +799,40 @@ void launch_sddmm_update(const Layout& L, const double* mvals, double* y, VT* yv
                          const FT* V, int64_t ldv, const double* sig, int r,
                          double delta, int apply, double* partial, double* out_sum,
                          hipStream_t st) {
-  MC_REQUIRE(r <= kMaxRankLds, kEINVAL, "rank exceeds the SDDMM limit");
-  const int64_t nb = sddmm_partials(L.nnz);
-  hipLaunchKernelGGL((sddmm_update_kernel<FT, AT, VT, WT>), dim3((unsigned)nb),
-                     dim3(kSddmmThreads), 0, st, L.nnz, L.row_of.p,
-                     L.col_idx.p, mvals, y, yv, ycv, yw, ycw, L.invperm.p, U, ldu,
-                     V, ldv, sig, r, delta, apply, partial);
+  MC_REQUIRE(r >= 0, kEINVAL, "negative rank");
+  const Schedule& S = L.sched_csr;
+  const int64_t nb = std::max<int64_t>(1, ceil_div(S.nseg, kSpmmWaves));
+#define MC_SDDMM(BW, CPL)                                                           \
+  hipLaunchKernelGGL((sddmm_update_kernel<FT, AT, VT, WT, BW, CPL>), dim3((unsigned)nb), \
+                     dim3(64 * kSpmmWaves), 0, st, S.nseg, S.segs.p, L.col_idx.p, mvals, \
+                     y, yv, ycv, yw, ycw, L.invperm.p, U, ldu, V, ldv, sig, r, delta,  \
+                     apply, partial)
+  // lanes per nonzero and columns per lane as the SpMM's forms
+  if (r <= 8)
+    MC_SDDMM(8, 1);
+  else if (r <= 16)
+    MC_SDDMM(16, 1);
+  else if (r <= 24)
+    MC_SDDMM(8, 3);
+  else if (r <= 32)
+    MC_SDDMM(16, 2);
+  else if (r <= 40)
+    MC_SDDMM(8, 5);
+  else if (r <= 48)
+    MC_SDDMM(16, 3);
+  else if (r <= 56)
+    MC_SDDMM(8, 7);
+  else if (r <= 64)
+    MC_SDDMM(16, 4);
+  else if (r <= 80)
+    MC_SDDMM(16, 5);
+  else if (r <= 96)
+    MC_SDDMM(16, 6);
+  else if (r <= 112)
+    MC_SDDMM(16, 7);
+  else
+    MC_SDDMM(32, 4);                 // passes of 128 columns
+#undef MC_SDDMM
   MC_CHECK_LAUNCH();
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, st, nb, partial,
                      out_sum);

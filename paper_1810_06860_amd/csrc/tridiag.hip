@@ -640,6 +640,30 @@ __global__ __launch_bounds__(256) void big_step_kernel(
   const int o = last ? j : j + 1;             // first row / column this launch touches
   const int npart_stride = (L + kBigRows - 1) / kBigRows;
   const bool upd = j >= 1;
+  // Loads that nothing in this launch writes go out first, so their latency
+  // overlaps the reductions below: this wavefront's trailing row (stored
+  // with the updates up to step j-2) and row j (likewise; step j-1's update
+  // of it is applied on the fly).
+  const int r = blockIdx.x * kBigRows + wave;  // trailing row
+  const int a = o + r;
+  const bool has_row = a < L;
+  double xs[kStepPer];
+  if (has_row) {
+    const double* __restrict__ row = Ag + (int64_t)a * L;
+#pragma unroll
+    for (int u = 0; u < kStepPer; ++u) xs[u] = row[min(o + lane + 64 * u, L - 1)];
+  }
+  constexpr int kRowJ = 1024 / 256;            // row j entries per thread (L <= 1024)
+  double xj[kRowJ];
+  double djj = 0.0;
+  if (!last) {
+#pragma unroll
+    for (int u = 0; u < kRowJ; ++u) {
+      const int c = o + tid + 256 * u;
+      xj[u] = c < L ? Ag[(int64_t)j * L + c] : 0.0;
+    }
+    if (blockIdx.x == 0 && tid == 0) djj = Ag[(int64_t)j * L + j];
+  }
   if (upd) {
     // step j-1: its trailing block starts at j
     const int jp = j - 1;
@@ -666,11 +690,15 @@ __global__ __launch_bounds__(256) void big_step_kernel(
     // row j after step j-1 (columns > j), the reflector of step j from it
     const int n = L - o;
     double sq = 0.0;
-    for (int c = o + tid; c < L; c += 256) {
-      double x = Ag[(int64_t)j * L + c];
-      if (upd) x -= vp[j] * wp[c] + wp[j] * vp[c];
-      vj[c] = x;
-      if (c > o) sq += x * x;
+#pragma unroll
+    for (int u = 0; u < kRowJ; ++u) {
+      const int c = o + tid + 256 * u;
+      if (c < L) {
+        double x = xj[u];
+        if (upd) x -= vp[j] * wp[c] + wp[j] * vp[c];
+        vj[c] = x;
+        if (c > o) sq += x * x;
+      }
     }
     sq = wsum(sq);
     if (lane == 0) red[wave] = sq;
@@ -686,7 +714,6 @@ __global__ __launch_bounds__(256) void big_step_kernel(
     }
     if (blockIdx.x == 0) {
       if (tid == 0) {
-        double djj = Ag[(int64_t)j * L + j];
         if (upd) djj -= vp[j] * wp[j] + wp[j] * vp[j];
         dg[j] = djj;
         eg[j] = mu;
@@ -699,16 +726,9 @@ __global__ __launch_bounds__(256) void big_step_kernel(
     for (int c = o + tid; c < L; c += 256) vj[c] = c == o ? 1.0 : vj[c] * rv;
     __syncthreads();
     // this workgroup's rows: update by step j-1, then p = beta A22 v
-    const int r = blockIdx.x * kBigRows + wave;  // trailing row
     double pr = 0.0;
     if (r < n) {
-      const int a = o + r;
       double* __restrict__ row = Ag + (int64_t)a * L;
-      // the row's entries first (all loads in flight; lanes past the end read
-      // the last entry), then the update and the product
-      double xs[kStepPer];
-#pragma unroll
-      for (int u = 0; u < kStepPer; ++u) xs[u] = row[min(o + lane + 64 * u, L - 1)];
       double acc = 0.0;
 #pragma unroll
       for (int u = 0; u < kStepPer; ++u) {
@@ -732,13 +752,8 @@ __global__ __launch_bounds__(256) void big_step_kernel(
       pbuf[(size_t)(j & 1) * npart_stride + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
   } else if (upd) {
     // the pending update of step j0 - 1 on rows and columns >= j0
-    const int r = blockIdx.x * kBigRows + wave;
-    if (o + r < L) {
-      const int a = o + r;
+    if (has_row) {
       double* __restrict__ row = Ag + (int64_t)a * L;
-      double xs[kStepPer];
-#pragma unroll
-      for (int u = 0; u < kStepPer; ++u) xs[u] = row[min(o + lane + 64 * u, L - 1)];
 #pragma unroll
       for (int u = 0; u < kStepPer; ++u) {
         const int c = o + lane + 64 * u;
