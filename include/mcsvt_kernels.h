@@ -53,6 +53,26 @@ mc_status mc_k_gram(int64_t N, int32_t p, int32_t q, const double* A,
                     const double* B, int32_t sym, int32_t precision,
                     void* stream, double* C);
 
+/* Allocation-free form of mc_k_gram, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc): C (p x q) = A^T B in FP64 with A (N x p, leading
+ * dimension lda), B (N x q, ldb) and C (p x q, ldc) row-major DEVICE arrays
+ * owned by the caller; sym = 1 requires p == q and reads A for B (B may then
+ * be NULL).  Work is enqueued on `stream` (NULL: the default stream) and not
+ * waited for.  The call allocates nothing: the split partial sums live in a
+ * file-scope device array of 2^21 doubles (16 MiB) that each GPU the library
+ * runs on holds until the process ends; its address is looked up once per
+ * device, on the first call with that device current.  Calls on one GPU
+ * share that array, so calls that overlap in time on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.
+ * Errors: MC_EINVAL (sizes < 1, NULL A or C, NULL B without sym, sym with
+ * p != q, a leading dimension below its row width), MC_ERANGE (p * q above
+ * 2^21), MC_EDEVICE (the array's address could not be found, or a launch
+ * failed). */
+mc_status mc_k_gram_noalloc(int64_t N, int32_t p, int32_t q, const double* A,
+                            int64_t lda, const double* B, int64_t ldb,
+                            int32_t sym, void* stream, double* C, int64_t ldc);
+
 /* Panel product C (N x q) = beta C0 + alpha X W diag(colscale) with X (N x p)
  * and W (p x q), all row-major host arrays; colscale (q) and C0 may be NULL
  * (then they are not applied / beta must be 0).  This is the product behind

@@ -131,6 +131,9 @@ _SIGNATURES = {
     "mc_k_gram": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, _P(C.c_double),
                             _P(C.c_double), C.c_int32, C.c_int32, C.c_void_p,
                             _P(C.c_double)]),
+    "mc_k_gram_noalloc": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_void_p,
+                                    C.c_int64, C.c_void_p, C.c_int64, C.c_int32,
+                                    C.c_void_p, C.c_void_p, C.c_int64]),
     "mc_k_panel": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, _P(C.c_double),
                              _P(C.c_double), C.c_double, _P(C.c_double), C.c_double,
                              _P(C.c_double), C.c_int32, C.c_void_p, _P(C.c_double)]),

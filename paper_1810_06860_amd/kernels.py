@@ -94,6 +94,26 @@ def gram(A, B=None, precision="fp64"):
     return out
 
 
+def gram_noalloc(A, B=None, out=None):
+    """C = A^T B on device tensors (FP64, row-major, contiguous rows) through
+    the allocation-free entry point; out (p x q) is a caller-owned device
+    tensor, allocated here when not given.  Enqueued on the current stream."""
+    import torch
+    sym = B is None
+    N, p = A.shape
+    q = p if sym else B.shape[1]
+    if out is None:
+        out = torch.empty((p, q), dtype=torch.float64, device=A.device)
+    for t in (A, out) + (() if sym else (B,)):
+        if t.dtype != torch.float64 or not t.is_cuda or t.stride(1) != 1:
+            raise ValueError("FP64 device tensors with contiguous rows expected")
+    check(lib().mc_k_gram_noalloc(N, p, q, A.data_ptr(),
+                                  A.stride(0), None if sym else B.data_ptr(),
+                                  A.stride(0) if sym else B.stride(0), int(sym),
+                                  current_stream(), out.data_ptr(), out.stride(0)))
+    return out
+
+
 def panel(X, W, alpha=1.0, colscale=None, beta=0.0, C0=None, precision="fp64"):
     X = np.ascontiguousarray(X, dtype=np.float64)
     W = np.ascontiguousarray(W, dtype=np.float64)

@@ -173,3 +173,29 @@ def test_headers_compile_as_c_and_link_against_the_library(tmp_path):
                    check=True, capture_output=True)
     run = subprocess.run([str(exe)], capture_output=True, timeout=60)
     assert run.returncode == 0, run.stderr
+
+
+@pytest.mark.parametrize("case", ["n0", "sym_pq", "ld", "null_b", "oversize"])
+def test_noalloc_gram_validates_before_the_device(lib, case):
+    # every rejection happens before the first device call (the pointers are
+    # placeholders that are never dereferenced)
+    from paper_1810_06860_amd._ffi import MC_EINVAL, MC_ERANGE
+    a = 4096
+    args = dict(N=8, p=4, q=4, A=a, lda=4, B=a, ldb=4, sym=1, C=a, ldc=4)
+    want = MC_EINVAL
+    if case == "n0":
+        args["N"] = 0
+    elif case == "sym_pq":
+        args["q"] = 3
+    elif case == "ld":
+        args["lda"] = 3
+    elif case == "null_b":
+        args.update(sym=0, B=None)
+    else:
+        args.update(p=2048, q=2048, lda=2048, ldb=2048, ldc=2048)
+        want = MC_ERANGE
+    st = lib.mc_k_gram_noalloc(args["N"], args["p"], args["q"], args["A"],
+                               args["lda"], args["B"], args["ldb"], args["sym"],
+                               None, args["C"], args["ldc"])
+    assert st == want
+    assert lib.mc_svt_last_error(None)
