@@ -470,6 +470,88 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(
                                  nt, As, Bs);
 }
 
+// Tall Gram with a single output block (p, q <= 16 NT): every wavefront
+// keeps all the block's 16 x 16 tiles (the upper NT (NT + 1) / 2 of a
+// symmetric product, else NT x NT) and takes its own 4-row steps, loading
+// the MFMA operands straight from memory (a lane reads row 4 s + lane / 16,
+// column 16 i + lane % 16 of tile column i), so the row loop has no LDS
+// traffic and no barriers and keeps many loads in flight.  The four
+// wavefronts' tiles are summed through LDS, one tile at a time, into the
+// workgroup's partial (p x q, lower tiles of a symmetric product left for
+// the reduction to mirror at granularity 16).
+constexpr int kRowsUnroll = 2;      // 4-row steps whose loads are issued together
+
+template <class T, int NT, bool SYM>
+__global__ __launch_bounds__(256) void gram_rows_kernel(
+    int64_t N, int p, int q, const T* __restrict__ A, int64_t lda,
+    const T* __restrict__ B, int64_t ldb, T* __restrict__ part,
+    const int* __restrict__ gate) {
+  using M = Mfma16<T>;
+  using V = typename M::V;
+  constexpr int NTILE = SYM ? NT * (NT + 1) / 2 : NT * NT;
+  if (gate && *gate == 0) return;
+  __shared__ T red[4][256];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int cc = lane % 16, kq = lane / 16;
+  V acc[NTILE];
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[t][v] = T(0);
+  bool acol[NT], bcol[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    acol[i] = i * 16 + cc < p;
+    bcol[i] = i * 16 + cc < q;
+  }
+  const int64_t steps = (N + 3) / 4;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t s0 = (int64_t)blockIdx.x * 4 + w; s0 < steps; s0 += nw * kRowsUnroll) {
+    T a[kRowsUnroll][NT], b[kRowsUnroll][SYM ? 1 : NT];
+#pragma unroll
+    for (int u = 0; u < kRowsUnroll; ++u) {
+      const int64_t row = (s0 + u * nw) * 4 + kq;
+      const bool rin = row < N;
+      const T* ar = A + (rin ? row : 0) * lda;
+      const T* br = B + (rin ? row : 0) * ldb;
+#pragma unroll
+      for (int i = 0; i < NT; ++i) {
+        a[u][i] = (rin && acol[i]) ? ar[i * 16 + cc] : T(0);
+        if (!SYM) b[u][i] = (rin && bcol[i]) ? br[i * 16 + cc] : T(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRowsUnroll; ++u) {
+      int t = 0;
+#pragma unroll
+      for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int j = SYM ? i : 0; j < NT; ++j, ++t)
+          acc[t] = M::op(a[u][i], SYM ? a[u][j] : b[u][j], acc[t]);
+    }
+  }
+  // the four wavefronts' tiles into the workgroup's partial
+  T* out = part + (int64_t)blockIdx.x * p * q;
+  int t = 0;
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = SYM ? i : 0; j < NT; ++j, ++t) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[w][v * 64 + lane] = acc[t][v];
+      __syncthreads();
+      {
+        const int v = threadIdx.x / 64, l = threadIdx.x % 64;
+        const T sum = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                      (red[2][threadIdx.x] + red[3][threadIdx.x]);
+        const int r = i * 16 + M::row(l, v), c = j * 16 + l % 16;
+        if (r < p && c < q) out[(int64_t)r * q + c] = sum;
+      }
+      __syncthreads();
+    }
+}
+
 // Sum of the split partials.  `lanes` consecutive threads (a power of two
 // dividing 64, so they sit in one wavefront) share an output: lane j adds the
 // splits j, j + lanes, ... in order, then the lanes are combined by a fixed
@@ -818,22 +900,87 @@ int64_t gram_mfma_splits(int64_t N, int p, int q, int sym) {
 
 }  // namespace
 
-int64_t gram_splits(int64_t N, int p, int q, int sym) {
-  return std::max(fused_splits(N, p, q, sym), gram_mfma_splits(N, p, q, sym));
+namespace {
+// The row-streaming form takes a single output block whose tiles fit a
+// wavefront's registers: a symmetric product up to 112 wide, a cross product
+// up to 80 x 80; both only for panels tall enough to fill the chip.
+bool rows_form(int64_t N, int p, int q, int sym) {
+  const int nt = (int)ceil_div(std::max(p, q), 16);
+  return N >= 4096 && (sym ? nt <= 7 : nt <= 5);
 }
+
+// workgroups of the row-streaming form: about eight 4-row steps per
+// wavefront, at most 512 workgroups (two per CU)
+int64_t rows_wgs(int64_t N) {
+  return std::max<int64_t>(1, std::min<int64_t>(512, ceil_div(N, 4 * 4 * 8)));
+}
+
+// C (FP64) = the sum of `splits` partials of p x q
+template <class AT>
+void reduce_splits(int p, int q, int64_t splits, const AT* part, double* C, int64_t ldc,
+                   int sym, hipStream_t st, const int* gate) {
+  const int64_t tot = (int64_t)p * q;
+  int lanes = 1;   // threads per output: about 16 splits each, at most 64
+  while (lanes < 64 && lanes * 16 < splits) lanes <<= 1;
+  const int64_t per_block = 256 / lanes;
+  hipLaunchKernelGGL((gram_reduce_kernel<AT>), dim3((unsigned)ceil_div(tot, per_block)),
+                     dim3(256), 0, st, p, q, (int)splits, lanes, part, C, ldc, sym, MT,
+                     gate);
+  MC_CHECK_LAUNCH();
+}
+}  // namespace
+
+int64_t gram_splits(int64_t N, int p, int q, int sym) {
+  return std::max({fused_splits(N, p, q, sym), gram_mfma_splits(N, p, q, sym),
+                   rows_form(N, p, q, sym) ? rows_wgs(N) : int64_t(0)});
+}
+
 
 template <class IT, class AT>
 void launch_gram(int64_t N, int p, int q, const IT* A, int64_t lda, const IT* B,
                  int64_t ldb, double* C, int64_t ldc, int sym, AT* part,
                  int64_t part_cap, hipStream_t st, const int* gate) {
   if (p <= 0 || q <= 0) return;
+  static_assert(std::is_same<IT, AT>::value, "the matrix-core Gram accumulates in its input type");
+  const int nt = (int)ceil_div(std::max(p, q), 16);
+  if (rows_form(N, p, q, sym)) {
+    // one output block: the row-streaming form, one partial per workgroup
+    int64_t nwg = rows_wgs(N);
+    while (nwg > 1 && nwg * p * q > part_cap) --nwg;
+    MC_REQUIRE(nwg * p * q <= part_cap, kEINVAL, "gram partial buffer too small");
+#define MC_GRAM_ROWS(NT, S)                                                          \
+  hipLaunchKernelGGL((gram_rows_kernel<AT, NT, S>), dim3((unsigned)nwg), dim3(256), 0, st, \
+                     N, p, q, A, lda, B, ldb, part, gate)
+    if (sym) {
+      switch (nt) {
+        case 1: MC_GRAM_ROWS(1, true); break;
+        case 2: MC_GRAM_ROWS(2, true); break;
+        case 3: MC_GRAM_ROWS(3, true); break;
+        case 4: MC_GRAM_ROWS(4, true); break;
+        case 5: MC_GRAM_ROWS(5, true); break;
+        case 6: MC_GRAM_ROWS(6, true); break;
+        default: MC_GRAM_ROWS(7, true); break;
+      }
+    } else {
+      switch (nt) {
+        case 1: MC_GRAM_ROWS(1, false); break;
+        case 2: MC_GRAM_ROWS(2, false); break;
+        case 3: MC_GRAM_ROWS(3, false); break;
+        case 4: MC_GRAM_ROWS(4, false); break;
+        default: MC_GRAM_ROWS(5, false); break;
+      }
+    }
+#undef MC_GRAM_ROWS
+    MC_CHECK_LAUNCH();
+    reduce_splits<AT>(p, q, nwg, part, C, ldc, sym, st, gate);
+    return;
+  }
   int64_t splits = gram_mfma_splits(N, p, q, sym);
   while (splits > 1 && splits * p * q > part_cap) --splits;
   MC_REQUIRE(splits * p * q <= part_cap, kEINVAL, "gram partial buffer too small");
   const int64_t rps = round_up(ceil_div(std::max<int64_t>(N, 1), splits), MK);
   splits = std::max<int64_t>(1, ceil_div(std::max<int64_t>(N, 1), rps));
   dim3 grid((unsigned)ceil_div(p, MB), (unsigned)ceil_div(q, MB), (unsigned)splits);
-  static_assert(std::is_same<IT, AT>::value, "the matrix-core Gram accumulates in its input type");
   // tiles per wavefront of the fullest block: the first one (a diagonal
   // block of a symmetric product holds only its upper tiles)
   const int nti0 = (int)std::min<int64_t>(MB / 16, ceil_div(p, 16));
@@ -855,14 +1002,7 @@ void launch_gram(int64_t N, int p, int q, const IT* A, int64_t lda, const IT* B,
     MC_GRAM_MFMA(16);
 #undef MC_GRAM_MFMA
   MC_CHECK_LAUNCH();
-  const int64_t tot = (int64_t)p * q;
-  int lanes = 1;   // threads per output: about 16 splits each, at most 64
-  while (lanes < 64 && lanes * 16 < splits) lanes <<= 1;
-  const int64_t per_block = 256 / lanes;
-  hipLaunchKernelGGL((gram_reduce_kernel<AT>), dim3((unsigned)ceil_div(tot, per_block)),
-                     dim3(256), 0, st, p, q, (int)splits, lanes, part, C, ldc, sym, MT,
-                     gate);
-  MC_CHECK_LAUNCH();
+  reduce_splits<AT>(p, q, splits, part, C, ldc, sym, st, gate);
 }
 template void launch_gram<double, double>(int64_t, int, int, const double*,
                                           int64_t, const double*, int64_t,

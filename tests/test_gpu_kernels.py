@@ -111,7 +111,14 @@ def test_spmm_fp32_error_bound(K):
                                        (777, 63, 21, 0), (33, 5, 7, 0),
                                        (20000, 330, 330, 1), (1, 3, 3, 1),
                                        (16, 64, 64, 1), (4099, 129, 17, 0),
-                                       (70001, 81, 81, 1), (3001, 200, 65, 0)])
+                                       (70001, 81, 81, 1), (3001, 200, 65, 0),
+                                       # the row-streaming form (one output block,
+                                       # N >= 4096): each tile count of both kinds
+                                       (5000, 3, 3, 1), (8192, 17, 17, 1), (4096, 40, 40, 1),
+                                       (6000, 64, 64, 1), (140000, 75, 75, 1),
+                                       (6001, 112, 112, 1), (4096, 16, 16, 0),
+                                       (8192, 33, 17, 0), (9000, 48, 40, 0),
+                                       (12345, 64, 50, 0), (9000, 75, 80, 0)])
 def test_gram_fp64(K, N, p, q, sym):
     rng = np.random.default_rng(N + p)
     A = rng.standard_normal((N, p))
@@ -125,7 +132,8 @@ def test_gram_fp64(K, N, p, q, sym):
 
 
 @pytest.mark.parametrize("N,p,q,sym", [(1000, 21, 21, 1), (4099, 129, 17, 0),
-                                       (70001, 81, 81, 1), (10700, 400, 400, 1)])
+                                       (70001, 81, 81, 1), (10700, 400, 400, 1),
+                                       (9000, 75, 60, 0), (6001, 112, 112, 1)])
 def test_gram_fp32(K, N, p, q, sym):
     # FP32 products accumulated in FP32 within a row split, splits summed in
     # FP64: error within N u32 of sum |a_i||b_j| (a loose form of the
