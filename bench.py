@@ -436,6 +436,11 @@ def run_whole(SVT, prob, prm, log_name):
                s=round(dt, 3), converged=bool(out["converged"]), res_last=out["res"],
                rank=out["rank"], fresh=out["fresh"], recycled=out["recycled"],
                rejected=out["rejected"])
+    if prob.meta.get("value_scale"):
+        # image inpainting: Eq. (10) over every pixel of the stacked channels
+        import synth
+        U, sig, V = f
+        rec["mae_all_pixels"] = round(synth.mae_all_pixels((U * sig) @ V.T, prob), 4)
     log(f"{log_name}: {rec}")
     return rec, f
 
@@ -566,6 +571,8 @@ def main():
         X = (U * sig) @ V.T
         acc["rel_err_vs_truth"] = float(np.linalg.norm(X - truth) /
                                         np.linalg.norm(truth))
+        if prob.meta.get("value_scale"):
+            acc["mae_all_pixels"] = synth.mae_all_pixels(X, prob)
     else:
         # large shapes: on 2^20 cells drawn uniformly (seeded), on and off Phi
         g = np.random.default_rng(7)

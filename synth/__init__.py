@@ -14,11 +14,13 @@ sampling ratios and value ranges.
 from .sampler import splitmix64_output, sample_cells, cells_to_coo
 from .problems import (Problem, planted, image_like, ratings, serving_trace,
                        request_problem, zipf_degrees, sparse_square)
+from .image import landscape_rgb, inpainting, mae_all_pixels
 from .configs import CONFIGS, get_config, make_problem, serving_params
 
 __all__ = [
     "splitmix64_output", "sample_cells", "cells_to_coo",
     "Problem", "planted", "image_like", "ratings", "serving_trace",
     "request_problem", "zipf_degrees", "sparse_square",
+    "landscape_rgb", "inpainting", "mae_all_pixels",
     "CONFIGS", "get_config", "make_problem", "serving_params",
 ]
