@@ -106,6 +106,9 @@ def parse():
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--serve-graphs", type=int, default=1,
                     help="1: served solves replay captured graphs")
+    ap.add_argument("--serve-grouped", type=int, default=1,
+                    help="1: also serve the same requests in batched rounds "
+                         "(mc_svt_step_group, shared sparse-product launches)")
     ap.add_argument("--calls", type=int, default=10,
                     help="sparse45k: timed calls per case")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
@@ -293,6 +296,25 @@ def serving_leg(a):
                                                     f"{s.latency:.2f} s{', ' + s.error if s.error else ''})"))
     torch.cuda.synchronize()
     out = serving.summarize(served)
+    if a.serve_grouped:
+        # the same arrivals served in batched rounds (one driver thread, the
+        # sparse products of each stage launched together for all solves)
+        g0 = time.perf_counter()
+        grouped = serving.serve_grouped(
+            reqs, budget_bytes=int(a.serve_budget_gib * (1 << 30)),
+            max_active=a.serve_slots, stream_pool=streams,
+            on_done=lambda s, n: log(f"serving grouped: {n}/{len(reqs)} done "
+                                     f"(req {s.id}, {s.steps} steps, {s.latency:.2f} s)"))
+        torch.cuda.synchronize()
+        gsum = serving.summarize(grouped)
+        same = {s.id: (s.steps, s.rank, s.res) for s in served}
+        gsum["same_steps_rank_residual_as_streams"] = all(
+            same.get(s.id) == (s.steps, s.rank, s.res) for s in grouped)
+        gsum["wall_s"] = round(time.perf_counter() - g0, 2)
+        for key in ("p50_s", "p99_s", "mean_s", "max_s", "makespan_s", "steps_per_s"):
+            if gsum.get(key) is not None:
+                gsum[key] = round(gsum[key], 4)
+        out["grouped_rounds"] = gsum
     errs = [f"req {s.id}: {s.error}" for s in served if s.error]
     if errs:
         out["errors"] = errs

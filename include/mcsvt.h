@@ -208,6 +208,26 @@ mc_status mc_svt_step(mc_svt_t h, mc_svt_step_info* info);
 mc_status mc_svt_step_many(mc_svt_t* hs, int32_t count,
                            mc_svt_step_info* info, mc_status* status);
 
+/* Advance `count` independent solves by one step each (Alg. 6) with their
+ * sparse products batched: the fresh rSVD-BKI calls (Alg. 5) of all the
+ * handles run in lock-step stages, and the sparse products of one stage --
+ * one per solve -- go out in shared launches (one per lane form and value
+ * type) on a stream of the library's, which waits for each participant's
+ * stage work and is waited for by each participant's stream.  Every other
+ * kernel of a solve stays on its own stream.  The products run the same
+ * per-segment code as a solo launch, so results are bit-identical to
+ * mc_svt_step on each handle alone with graphs off.  FP64 and FP32 handles
+ * are batched (each type with its own kind); BF16 handles, rSVD-PI and
+ * recycled calls launch their products alone.  Captured graphs are not
+ * used for the batched calls.  All handles on the calling thread's device,
+ * distinct; calls of mc_svt_step_group (and mc_svt_step_many on the same
+ * handles) must not overlap.  info[j] / status[j] (may be NULL) as in
+ * mc_svt_step_many; a handle that fails takes no further part in the call
+ * and the others go on.  Returns MC_OK if every handle succeeded or was
+ * already converged, else the first error. */
+mc_status mc_svt_step_group(mc_svt_t* hs, int32_t count,
+                            mc_svt_step_info* info, mc_status* status);
+
 /* Steps until convergence or i_max (Alg. 6 outer loop); MC_ENOTCONV at
  * i_max, with X^{i_max} available as Alg. 2 returns it.  out may be NULL. */
 mc_status mc_svt_solve(mc_svt_t h, mc_svt_result* out);

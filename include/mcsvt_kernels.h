@@ -48,7 +48,11 @@ mc_status mc_k_spmm(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
 
 /* C (p x q) = A^T B for A (N x p), B (N x q), the Gram matrix of eigSVD
  * (Alg. 3) and of the block orthonormalisation (Lemma 2); sym = 1 requires
- * A == B.  Host buffers; FP64 result in every precision. */
+ * A == B.  Host buffers; FP64 result in every precision.  MC_FP32_EIG64
+ * rounds A and B to FP32 and accumulates in FP32; MC_BF16_EIG64 does the same
+ * on the BF16 matrix cores (operands rounded to BF16, FP32 accumulation) for
+ * the one-block shapes of a panel of at least 4096 rows (symmetric up to 112
+ * wide, cross up to 80 x 80), and falls back to FP32 otherwise. */
 mc_status mc_k_gram(int64_t N, int32_t p, int32_t q, const double* A,
                     const double* B, int32_t sym, int32_t precision,
                     void* stream, double* C);

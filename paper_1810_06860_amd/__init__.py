@@ -9,8 +9,9 @@ include/mcsvt.h.
 
 from ._ffi import (LIB_PATH, MC_EDONE, MC_ENOTCONV, MC_OK, MCError, STATUS_NAMES,
                    lib)
-from .svt import RSVD, SVT, default_params, footprint, rsvd_bki, rsvd_pi, step_many
+from .svt import (RSVD, SVT, default_params, footprint, rsvd_bki, rsvd_pi, step_group,
+                  step_many)
 
-__all__ = ["SVT", "RSVD", "rsvd_bki", "rsvd_pi", "step_many", "footprint", "default_params",
+__all__ = ["SVT", "RSVD", "rsvd_bki", "rsvd_pi", "step_many", "step_group", "footprint", "default_params",
            "MCError", "lib", "LIB_PATH", "MC_OK", "MC_EDONE", "MC_ENOTCONV",
            "STATUS_NAMES"]

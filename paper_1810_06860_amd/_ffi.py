@@ -80,6 +80,8 @@ _SIGNATURES = {
     "mc_svt_step": (C.c_int, [C.c_void_p, _P(StepInfo)]),
     "mc_svt_step_many": (C.c_int, [_P(C.c_void_p), C.c_int32, _P(StepInfo),
                                    _P(C.c_int)]),
+    "mc_svt_step_group": (C.c_int, [_P(C.c_void_p), C.c_int32, _P(StepInfo),
+                                    _P(C.c_int)]),
     "mc_svt_solve": (C.c_int, [C.c_void_p, _P(Result)]),
     "mc_svt_get_result": (C.c_int, [C.c_void_p, _P(Result)]),
     "mc_svt_get_factors": (C.c_int, [C.c_void_p, _P(C.c_double), _P(C.c_double),

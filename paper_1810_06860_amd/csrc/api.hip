@@ -424,6 +424,51 @@ mc_status mc_svt_step_many(mc_svt_t* hs, int32_t count, mc_svt_step_info* info,
   return worst;
 }
 
+mc_status mc_svt_step_group(mc_svt_t* hs, int32_t count, mc_svt_step_info* info,
+                            mc_status* status) {
+  if (!hs || count < 0) {
+    mcsvt::t_err = "bad handle array";
+    return MC_EINVAL;
+  }
+  std::vector<mc_status> st(count, MC_OK);
+  std::vector<mcsvt::Solver*> live;
+  std::vector<int32_t> at;
+  for (int32_t j = 0; j < count; ++j) {
+    if (!hs[j] || !hs[j]->solver) {
+      st[j] = MC_EINVAL;
+    } else if (hs[j]->solver->converged()) {
+      st[j] = MC_EDONE;
+    } else if (hs[j]->solver->step_busy()) {
+      st[j] = MC_EINVAL;
+      hs[j]->err = "a step of this solve is in progress";
+    } else {
+      live.push_back(hs[j]->solver.get());
+      at.push_back(j);
+    }
+  }
+  std::vector<int> sst(live.size(), MC_OK);
+  std::vector<std::string> serr(live.size());
+  const mc_status all = guarded(nullptr, [&] { mcsvt::step_group(live, sst, serr); });
+  for (size_t i = 0; i < live.size(); ++i) {
+    const int32_t j = at[i];
+    if (all != MC_OK) {
+      st[j] = all;
+      hs[j]->err = mcsvt::t_err;
+    } else if (sst[i] != MC_OK) {
+      st[j] = (mc_status)sst[i];
+      hs[j]->err = serr[i];
+    } else {
+      fill_info(live[i]->step_result(), info ? &info[j] : nullptr);
+    }
+  }
+  mc_status worst = MC_OK;
+  for (int32_t j = 0; j < count; ++j) {
+    if (status) status[j] = st[j];
+    if (st[j] != MC_OK && st[j] != MC_EDONE && worst == MC_OK) worst = st[j];
+  }
+  return worst;
+}
+
 mc_status mc_svt_solve(mc_svt_t h, mc_svt_result* out) {
   if (!h || !h->solver) {
     mcsvt::t_err = "NULL handle";

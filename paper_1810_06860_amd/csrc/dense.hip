@@ -397,8 +397,7 @@ __device__ __forceinline__ void gram_mfma_rows(
     __syncthreads();
     if (nb + MK < n1) fetch(nb + MK);         // in flight during the products
     T(*Bt)[MB + 1] = SAME ? As : Bs;
-#pragma unroll
-    for (int kk = 0; kk < MK; kk += 4) {
+    auto step4 = [&](int kk) {
       const int kr = kk + kq;
 #pragma unroll
       for (int t = 0; t < TW; ++t) {
@@ -408,6 +407,17 @@ __device__ __forceinline__ void gram_mfma_rows(
           acc[t] = M::op(x, y, acc[t]);
         }
       }
+    };
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+      for (int kk = 0; kk < MK; kk += 4) step4(kk);
+    } else {
+      // FP32: one 4-row step at a time; unrolled across the stage the
+      // compiler hoists every step's LDS operands and runs out of registers
+      // (at eight tiles per wavefront one wavefront per SIMD, five times the
+      // FP64 time); FP64 keeps the unrolled form, which measured faster
+#pragma unroll 1
+      for (int kk = 0; kk < MK; kk += 4) step4(kk);
     }
     __syncthreads();
   }
@@ -546,6 +556,82 @@ __global__ __launch_bounds__(256) void gram_rows_kernel(
         const T sum = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
                       (red[2][threadIdx.x] + red[3][threadIdx.x]);
         const int r = i * 16 + M::row(l, v), c = j * 16 + l % 16;
+        if (r < p && c < q) out[(int64_t)r * q + c] = sum;
+      }
+      __syncthreads();
+    }
+}
+
+// The row-streaming Gram on the BF16 matrix cores (16x16x16 MFMA, FP32
+// accumulation) for FP32 panels: each 16-row step rounds its operands to BF16
+// on load (a lane packs rows 16 s + 4 (lane / 16) + 0..3 of column
+// 16 i + lane % 16), so one instruction covers four times the rows of the
+// FP32 form.  Products of BF16 values are exact in FP32; only the rounding
+// of the operands and the FP32 sums differ from the FP32 Gram.
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float f) {
+  return (short)bf16_t(f).bits;
+}
+
+template <int NT, bool SYM>
+__global__ __launch_bounds__(256) void gram_rows_bf16_kernel(
+    int64_t N, int p, int q, const float* __restrict__ A, int64_t lda,
+    const float* __restrict__ B, int64_t ldb, float* __restrict__ part) {
+  using V = Mfma16<float>::V;
+  constexpr int NTILE = SYM ? NT * (NT + 1) / 2 : NT * NT;
+  __shared__ float red[4][256];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int cc = lane % 16, kq = lane / 16;
+  V acc[NTILE];
+#pragma unroll
+  for (int t = 0; t < NTILE; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[t][v] = 0.0f;
+  bool acol[NT], bcol[NT];
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    acol[i] = i * 16 + cc < p;
+    bcol[i] = i * 16 + cc < q;
+  }
+  const int64_t steps = (N + 15) / 16;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t s = (int64_t)blockIdx.x * 4 + w; s < steps; s += nw) {
+    bf16x4_t a[NT], b[SYM ? 1 : NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t row = s * 16 + kq * 4 + j;
+        const bool rin = row < N;
+        const int64_t rr = rin ? row : 0;
+        a[i][j] = bf16_bits((rin && acol[i]) ? A[rr * lda + i * 16 + cc] : 0.0f);
+        if (!SYM) b[i][j] = bf16_bits((rin && bcol[i]) ? B[rr * ldb + i * 16 + cc] : 0.0f);
+      }
+    }
+    int t = 0;
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+      for (int j = SYM ? i : 0; j < NT; ++j, ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], SYM ? a[j] : b[j],
+                                                            acc[t], 0, 0, 0);
+  }
+  float* out = part + (int64_t)blockIdx.x * p * q;
+  int t = 0;
+#pragma unroll
+  for (int i = 0; i < NT; ++i)
+#pragma unroll
+    for (int j = SYM ? i : 0; j < NT; ++j, ++t) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[w][v * 64 + lane] = acc[t][v];
+      __syncthreads();
+      {
+        const int v = threadIdx.x / 64, l = threadIdx.x % 64;
+        const float sum = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                          (red[2][threadIdx.x] + red[3][threadIdx.x]);
+        const int r = i * 16 + Mfma16<float>::row(l, v), c = j * 16 + l % 16;
         if (r < p && c < q) out[(int64_t)r * q + c] = sum;
       }
       __syncthreads();
@@ -827,6 +913,17 @@ __global__ void copy_gated_kernel(int64_t rows, int cols, const T* __restrict__ 
   dst[i * ldd + j] = src[i * lds_ + j];
 }
 
+// dst (rows x cols, ldd) = src (rows x cols, lds_) converted to D
+template <class S, class D>
+__global__ void cast_panel_kernel(int64_t rows, int cols, const S* __restrict__ src,
+                                  int64_t lds_, D* __restrict__ dst, int64_t ldd) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= rows * cols) return;
+  const int64_t i = t / cols;
+  const int j = (int)(t % cols);
+  dst[i * ldd + j] = (D)src[i * lds_ + j];
+}
+
 __global__ void recip_kernel(int k, const double* __restrict__ S,
                              double* __restrict__ out, const int* __restrict__ count,
                              double* __restrict__ count_out, double* __restrict__ host) {
@@ -1012,6 +1109,44 @@ template void launch_gram<float, float>(int64_t, int, int, const float*,
                                         int64_t, const float*, int64_t, double*,
                                         int64_t, int, float*, int64_t,
                                         hipStream_t, const int*);
+
+bool gram_bf16_fits(int64_t N, int p, int q, int sym) { return rows_form(N, p, q, sym); }
+
+void launch_gram_bf16(int64_t N, int p, int q, const float* A, int64_t lda, const float* B,
+                      int64_t ldb, double* C, int64_t ldc, int sym, float* part,
+                      int64_t part_cap, hipStream_t st) {
+  MC_REQUIRE(p > 0 && q > 0 && rows_form(N, p, q, sym), kEINVAL,
+             "BF16 Gram: shape outside the row-streaming form");
+  const int nt = (int)ceil_div(std::max(p, q), 16);
+  int64_t nwg = rows_wgs(N);
+  while (nwg > 1 && nwg * p * q > part_cap) --nwg;
+  MC_REQUIRE(nwg * p * q <= part_cap, kEINVAL, "gram partial buffer too small");
+#define MC_GRAM_BF(NT, S)                                                             \
+  hipLaunchKernelGGL((gram_rows_bf16_kernel<NT, S>), dim3((unsigned)nwg), dim3(256), 0, st, \
+                     N, p, q, A, lda, B, ldb, part)
+  if (sym) {
+    switch (nt) {
+      case 1: MC_GRAM_BF(1, true); break;
+      case 2: MC_GRAM_BF(2, true); break;
+      case 3: MC_GRAM_BF(3, true); break;
+      case 4: MC_GRAM_BF(4, true); break;
+      case 5: MC_GRAM_BF(5, true); break;
+      case 6: MC_GRAM_BF(6, true); break;
+      default: MC_GRAM_BF(7, true); break;
+    }
+  } else {
+    switch (nt) {
+      case 1: MC_GRAM_BF(1, false); break;
+      case 2: MC_GRAM_BF(2, false); break;
+      case 3: MC_GRAM_BF(3, false); break;
+      case 4: MC_GRAM_BF(4, false); break;
+      default: MC_GRAM_BF(5, false); break;
+    }
+  }
+#undef MC_GRAM_BF
+  MC_CHECK_LAUNCH();
+  reduce_splits<float>(p, q, nwg, part, C, ldc, sym, st, nullptr);
+}
 
 // The one-workgroup form for short blocks with few tiles; false when the
 // shape is outside it (the caller then takes the split form).
@@ -1228,6 +1363,18 @@ template void launch_copy_gated<double>(int64_t, int, const double*, int64_t,
                                         double*, int64_t, const int*, hipStream_t);
 template void launch_copy_gated<float>(int64_t, int, const float*, int64_t, float*,
                                        int64_t, const int*, hipStream_t);
+
+template <class S, class D>
+void launch_cast_panel(int64_t rows, int cols, const S* src, int64_t lds_, D* dst,
+                       int64_t ldd, hipStream_t st) {
+  const int64_t tot = rows * (int64_t)cols;
+  if (tot <= 0) return;
+  hipLaunchKernelGGL((cast_panel_kernel<S, D>), dim3((unsigned)ceil_div(tot, 256)),
+                     dim3(256), 0, st, rows, cols, src, lds_, dst, ldd);
+  MC_CHECK_LAUNCH();
+}
+template void launch_cast_panel<float, bf16_t>(int64_t, int, const float*, int64_t,
+                                               bf16_t*, int64_t, hipStream_t);
 
 void launch_recip(int k, const double* S, double* out, hipStream_t st, const int* count,
                   double* count_out, double* host) {

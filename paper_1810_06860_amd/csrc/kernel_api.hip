@@ -160,8 +160,12 @@ mc_status mc_k_gram(int64_t N, int32_t p, int32_t q, const double* A,
         fpB = fB.p;
       }
       fpart.reserve(cap, st);
-      mcsvt::launch_gram<float, float>(N, p, q, fA.p, p, fpB, sym ? p : q, dC.p, q,
-                                       sym, fpart.p, cap, st);
+      if (precision == MC_BF16_EIG64 && mcsvt::gram_bf16_fits(N, p, q, sym))
+        mcsvt::launch_gram_bf16(N, p, q, fA.p, p, fpB, sym ? p : q, dC.p, q, sym, fpart.p,
+                                cap, st);
+      else
+        mcsvt::launch_gram<float, float>(N, p, q, fA.p, p, fpB, sym ? p : q, dC.p, q,
+                                         sym, fpart.p, cap, st);
       MC_HIP(hipStreamSynchronize(st));
     }
     download(C, dC.p, (int64_t)p * q, st);

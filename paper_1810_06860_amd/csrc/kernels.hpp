@@ -107,6 +107,31 @@ void launch_gaussian_ctr(T* out, int64_t rows, int64_t cols, int64_t ld,
 
 // out (rows x b, ldo) = A X ; A given by schedule + idx + val; part is the
 // partial-row buffer (nslot * b elements).
+// One sparse product of a grouped launch (products of several solves in one
+// kernel): its schedule (the form launch_spmm would take), operands and, set
+// by the launcher, its first workgroup and first fix-up item.
+struct SpmmTask {
+  const int4* segs;
+  int64_t nseg;
+  const int4* fix;
+  int64_t nfix;
+  const int32_t* idx;
+  const void* val;
+  const void* X;
+  int64_t ldx;
+  void* out;
+  int64_t ldo;
+  void* part;
+  int64_t b;
+  int64_t wg0, fx0;
+};
+SpmmTask make_spmm_task(const Schedule& S, const int32_t* idx, const void* val,
+                        const void* X, int64_t ldx, void* out, int64_t ldo, int b,
+                        void* part, size_t x_bytes);
+template <class VT, class XT, class AT, class OT>
+void launch_spmm_group(const std::vector<SpmmTask>& tasks, SpmmTask* staging,
+                       SpmmTask* table, int64_t cap, hipStream_t st);
+
 template <class VT, class XT, class AT, class OT>
 void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
                  const XT* X, int64_t ldx, OT* out, int64_t ldo, int b,
@@ -141,6 +166,15 @@ void launch_gram(int64_t N, int p, int q, const IT* A, int64_t lda, const IT* B,
                  int64_t ldb, double* C, int64_t ldc, int sym, AT* part,
                  int64_t part_cap, hipStream_t st, const int* gate = nullptr);
 
+// C (FP64) = A^T B for FP32 panels on the BF16 matrix cores (operands rounded
+// to BF16, FP32 accumulation), for the shapes gram_bf16_fits accepts (one
+// output block of a panel tall enough to stream); partial buffer as
+// launch_gram's.
+bool gram_bf16_fits(int64_t N, int p, int q, int sym);
+void launch_gram_bf16(int64_t N, int p, int q, const float* A, int64_t lda, const float* B,
+                      int64_t ldb, double* C, int64_t ldc, int sym, float* part,
+                      int64_t part_cap, hipStream_t st);
+
 // The same with the completion in one launch: C (mode "cross", Rinv null), or
 // with A = B also Rinv = R^{-1} for C = R^T R (shifted retry as in
 // launch_chol_inv).  `counter` is a device int that is 0 between launches.
@@ -170,6 +204,10 @@ void launch_chol_inv(int b, const double* G, int64_t ldg, double* Rinv,
                      hipStream_t st, int* flag = nullptr,
                      const int* gate = nullptr);
 void launch_set_int(int* p, int v, hipStream_t st);
+// dst (rows x cols, ldd) = src (rows x cols, lds_) converted to D
+template <class S, class D>
+void launch_cast_panel(int64_t rows, int cols, const S* src, int64_t lds_, D* dst,
+                       int64_t ldd, hipStream_t st);
 template <class T>
 void launch_copy_gated(int64_t rows, int cols, const T* src, int64_t lds_, T* dst,
                        int64_t ldd, const int* gate, hipStream_t st);

@@ -156,14 +156,52 @@ void Solver::launch_svd(bool force_fresh) {
                      suspended;
   if (fresh) {
     last_attempt_ = attempt_++;
-    fresh_launch(k, p_, (uint32_t)i_, last_attempt_, false);
     ++cur_.fresh;
   } else {
-    recycled_launch(k);
     ++q_;
     ++cur_.recycled;
   }
   cur_recycled_ = !fresh;
+  if (defer_) {
+    defer_svd(fresh, k, p_, (uint32_t)i_, last_attempt_, false);
+    return;
+  }
+  if (fresh)
+    fresh_launch(k, p_, (uint32_t)i_, last_attempt_, false);
+  else
+    recycled_launch(k);
+  mark();
+  phase_ = kSvd;
+}
+
+void Solver::defer_svd(bool fresh, int k, int p, uint32_t step, uint32_t attempt,
+                       bool guarded) {
+  pend_.fresh = fresh;
+  pend_.guarded = guarded;
+  pend_.k = k;
+  pend_.p = p;
+  pend_.step = step;
+  pend_.attempt = attempt;
+  phase_ = kSvdPending;
+}
+
+void Solver::launch_pending() {
+  MC_REQUIRE(phase_ == kSvdPending, kEINVAL, "no pending SVD call");
+  if (pend_.fresh)
+    fresh_launch(pend_.k, pend_.p, pend_.step, pend_.attempt, pend_.guarded);
+  else
+    recycled_launch(pend_.k);
+  mark();
+  phase_ = kSvd;
+}
+
+void Solver::fresh_group_begin() {
+  MC_REQUIRE(phase_ == kSvdPending && pend_.fresh, kEINVAL, "no pending fresh call");
+  fresh_begin(pend_.k, pend_.p, pend_.step, pend_.attempt, pend_.guarded);
+}
+
+void Solver::fresh_group_end() {
+  fresh_end();
   mark();
   phase_ = kSvd;
 }
@@ -196,6 +234,7 @@ void Solver::step_begin() {
 
 bool Solver::step_poll(bool block) {
   if (phase_ == kIdle) return true;
+  if (phase_ == kSvdPending) return false;           // waits for its driver
   if (block) {
     wait();
   } else {
@@ -217,6 +256,10 @@ bool Solver::step_poll(bool block) {
         // a shifted Cholesky factorisation in the unguarded call: redo it
         // guarded (same attempt, same test matrix)
         ++redone_total_;
+        if (defer_) {
+          defer_svd(true, k_cur_, p_, (uint32_t)i_, last_attempt_, true);
+          return false;
+        }
         fresh_launch(k_cur_, p_, (uint32_t)i_, last_attempt_, true);
         mark();
         return false;
@@ -301,9 +344,12 @@ size_t footprint_bytes(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& p
   bytes += (size_t)8 * (L * L);
   bytes += (size_t)8 * TriBigWork::doubles((int)Lb, (int)kb);
   // SpMM partial rows (slots x the widest panel), SDDMM partials (one per
-  // workgroup of row segments, or per 256 entries), P_Phi(X)
+  // workgroup of row segments, plain or banded, or per 256 entries), P_Phi(X)
   bytes += (size_t)8 * (slots * std::max({b, L, k}) +
-                        std::max(ceil_div(nnz, 256), ceil_div(m + slots, kSpmmWaves)) + nnz);
+                        std::max(ceil_div(nnz, 256),
+                                 ceil_div((int64_t)kBands * (mx + slots) + mx + slots,
+                                          kSpmmWaves)) +
+                        nnz);
   return bytes;
 }
 

@@ -70,6 +70,23 @@ class Solver {
   void step_begin();
   bool step_poll(bool block);
   bool step_busy() const { return phase_ != kIdle; }
+
+  // Grouped stepping (several solves' sparse products merged into shared
+  // launches): with set_deferred(true) the SVD calls of step_begin() and
+  // step_poll() are not enqueued but left pending for a driver, which
+  // enqueues recycled calls with launch_pending() and runs fresh ones stage
+  // by stage (fresh_group_begin, fresh_group_stage until it returns false,
+  // fresh_group_end), collecting each stage's sparse product in a task list
+  // that it launches for all solves together.  group_kind() says which
+  // solves may share launches (same value types), or -1 for none.
+  void set_deferred(bool on) { defer_ = on; }
+  bool svd_pending() const { return phase_ == kSvdPending; }
+  bool pending_fresh() const { return pend_.fresh; }
+  void launch_pending();
+  virtual int group_kind() const = 0;
+  void fresh_group_begin();
+  virtual bool fresh_group_stage(int t, std::vector<SpmmTask>* sink) = 0;
+  void fresh_group_end();
   const StepInfo& step_result() const { return cur_; }
   // truncated SVD of the current operator: one rSVD-BKI call (Alg. 5)
   void rsvd(int k, int p, uint32_t step_id, uint32_t attempt) {
@@ -145,8 +162,22 @@ class Solver {
   void wait();                  // wait for it
 
   bool power_ = false;          // fresh calls run rSVD-PI instead of rSVD-BKI
-  enum Phase { kIdle, kSvd, kSddmm };
+  enum Phase { kIdle, kSvd, kSddmm, kSvdPending };
   Phase phase_ = kIdle;
+  // a deferred SVD call (grouped stepping)
+  struct Pending {
+    bool fresh = false, guarded = false;
+    int k = 0, p = 0;
+    uint32_t step = 0, attempt = 0;
+  };
+  bool defer_ = false;
+  Pending pend_;
+  void defer_svd(bool fresh, int k, int p, uint32_t step, uint32_t attempt, bool guarded);
+  // the parts of a fresh call around its device body (fresh_launch is
+  // begin, body, end); `grouped` leaves the body to fresh_group_stage
+  virtual void fresh_begin(int k, int p, uint32_t step_id, uint32_t attempt,
+                           bool guarded) = 0;
+  virtual void fresh_end() = 0;
   StepInfo cur_;
   int k_cur_ = 0;
   bool cur_recycled_ = false;
@@ -175,6 +206,11 @@ class Solver {
   int shifts_seen_ = 0;         // shift count read back with the last fresh call
   int redone_total_ = 0;        // fresh calls redone guarded
 };
+
+// One step of each solver with their fresh calls' sparse products launched
+// together (group.hip); per-solver status codes and messages.
+void step_group(const std::vector<Solver*>& ss, std::vector<int>& status,
+                std::vector<std::string>& err);
 
 // FP64, FP32 or BF16-value solver according to prm.precision
 std::unique_ptr<Solver> make_solver(int64_t m, int64_t n, int64_t nnz,

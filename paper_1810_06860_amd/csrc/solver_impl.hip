@@ -24,7 +24,8 @@
 // in all modes:
 //   FP64       P = double, VT = double, AT = double
 //   FP32       P = float,  VT = float,  AT = float
-//   BF16       P = float,  VT = bf16,   AT = float   (forward Krylov values in BF16)
+//   BF16       P = float,  VT = bf16,   AT = float   (forward Krylov products: values
+//                                                   and panel in BF16)
 #include <cmath>
 #include <cstring>
 #include <type_traits>
@@ -63,6 +64,9 @@ class SolverT final : public Solver {
   static constexpr bool kMaster = std::is_same<VT, double>::value;
   // separate Rayleigh-Ritz copies (type P) when the Krylov copies are not P
   static constexpr bool kSplit = !std::is_same<VT, P>::value;
+  // BF16 mode: the forward Krylov products also read their dense panel in
+  // BF16 (a copy made just before the product)
+  static constexpr bool kBfPanel = std::is_same<VT, bf16_t>::value;
 
   SolverT(int64_t m, int64_t n, int64_t nnz, const mc_svt_params& prm,
           hipStream_t st)
@@ -100,6 +104,17 @@ class SolverT final : public Solver {
  protected:
   void fresh_launch(int k, int p, uint32_t step_id, uint32_t attempt,
                     bool guarded) override;
+  void fresh_begin(int k, int p, uint32_t step_id, uint32_t attempt,
+                   bool guarded) override;
+  void fresh_end() override;
+  bool fresh_group_stage(int t, std::vector<SpmmTask>* sink) override;
+  // solves of one kind may share grouped sparse products: FP64 and FP32
+  // (values and panels of one type); BF16 mode mixes types and launches alone
+  int group_kind() const override {
+    if constexpr (std::is_same<VT, double>::value) return 0;
+    if constexpr (std::is_same<VT, float>::value) return 1;
+    return -1;
+  }
   bool fresh_finish(int k) override;
   void recycled_launch(int k) override;
   double recycled_finish(int k) override;
@@ -112,6 +127,16 @@ class SolverT final : public Solver {
   // have_bt: B^T = Y^T basis is already in Bt_ (leading dimension w)
   void eig_body(const P* basis, int64_t ldb, int w, int k, bool have_bt = false);
   void fresh_body(int k, int b, int p_eff, int Lw, bool guarded);
+  // stage t of a fresh rSVD-BKI call (see fresh_stage's definition)
+  bool fresh_stage(int t, int k, int b, int p_eff, int Lw, bool guarded);
+  // the call fresh_begin set up: k, b, p_eff, Lw, guarded
+  struct Call {
+    int k = 0, b = 0, p_eff = 0, Lw = 0;
+    bool guarded = false;
+  } call_;
+  // set while a grouped driver runs the stages: products are collected, not
+  // launched
+  std::vector<SpmmTask>* sink_ = nullptr;
   void ritz_body(int k);
   void read_launch(int k, bool ritz, bool count = false);
   double read_finish(int k, bool ritz);
@@ -127,10 +152,13 @@ class SolverT final : public Solver {
     graphs_.clear();
   }
   void orth_block(int j, int b, int Lw, bool guarded);
+  // low: in BF16 mode the Gram runs on the BF16 matrix cores (the first of
+  // the two orthonormalisation passes; the second, which restores
+  // orthogonality to FP32 accuracy, keeps the FP32 Gram)
   void cholqr_pass(const P* Hin, int64_t ldin, P* out, int64_t ldo, int b,
-                   const int* gate);
+                   const int* gate, bool low = false);
   void project(const P* Hin, int64_t ldin, P* Hout, int jb, int b, int Lw,
-               const int* gate);
+               const int* gate, bool low = false);
   // Krylov products (values of type VT)
   void spmm_y(const P* X, int64_t ldx, P* out, int64_t ldo, int b);
   void spmm_yt(const P* X, int64_t ldx, P* out, int64_t ldo, int b);
@@ -154,6 +182,7 @@ class SolverT final : public Solver {
   DevBuf<P> yw_, ycw_;              // Rayleigh-Ritz copies (when VT != P)
   int cap_b_ = 0, cap_L_ = 0, cap_k_ = 0;
   DevBuf<P> omega_, Qw_, basis_, H1_, H2_, Z_, Bt_, U_, V_;
+  DevBuf<VT> xb_;                 // BF16 copy of a forward product's panel
   DevBuf<AT> gram_part_, spmm_part_;
   DevBuf<double> G_, Cg_, Rinv_, chol_work_, S_, Sinv_, D_, Wk_, sig_, sdd_part_,
       scal_, ritz_part_, ritz_out_, obs_;
@@ -193,6 +222,7 @@ void SolverT<P, VT, AT>::ensure(int bmax, int Lmax, int kmax) {
   H1_.reserve(m_ * std::max(b, k), st_);
   H2_.reserve(m_ * b, st_);
   Z_.reserve(n_ * b, st_);
+  if (kBfPanel) xb_.reserve(n_ * b, st_);
   Bt_.reserve(n_ * Lc, st_);
   G_.reserve(Lc * Lc, st_);
   Cg_.reserve(Lc * b, st_);
@@ -299,10 +329,27 @@ int SolverT<P, VT, AT>::init(const int64_t* rows, const int32_t* cols,
 
 template <class P, class VT, class AT>
 void SolverT<P, VT, AT>::spmm_y(const P* X, int64_t ldx, P* out, int64_t ldo, int b) {
-  prof.begin(kProfSpmmFwd, spmm_bytes(nnz_, m_, n_, b, sizeof(VT), sizeof(P)),
-             2.0 * nnz_ * b, ls());
-  launch_spmm<VT, P, AT, P>(L_.sched_csr, L_.col_idx.p, yv(), X, ldx, out, ldo, b,
-                            spmm_part_.p, ls());
+  if (sink_ && !kBfPanel) {
+    sink_->push_back(make_spmm_task(L_.sched_csr, L_.col_idx.p, yv(), X, ldx, out, ldo, b,
+                                    spmm_part_.p, sizeof(P)));
+    return;
+  }
+  if constexpr (kBfPanel) {
+    // values and panel in BF16, FP32 accumulation; the panel's BF16 copy is
+    // made here (n b elements)
+    const double bytes = (double)nnz_ * (sizeof(VT) + 4) + 4.0 * (m_ + 1) +
+                         (double)n_ * b * sizeof(VT) + (double)m_ * b * sizeof(P) +
+                         (double)n_ * b * (sizeof(P) + sizeof(VT));     // + the copy
+    prof.begin(kProfSpmmFwd, bytes, 2.0 * nnz_ * b, ls());
+    launch_cast_panel<P, VT>(n_, b, X, ldx, xb_.p, b, ls());
+    launch_spmm<VT, VT, AT, P>(L_.sched_csr, L_.col_idx.p, yv(), xb_.p, b, out, ldo, b,
+                               spmm_part_.p, ls());
+  } else {
+    prof.begin(kProfSpmmFwd, spmm_bytes(nnz_, m_, n_, b, sizeof(VT), sizeof(P)),
+               2.0 * nnz_ * b, ls());
+    launch_spmm<VT, P, AT, P>(L_.sched_csr, L_.col_idx.p, yv(), X, ldx, out, ldo, b,
+                              spmm_part_.p, ls());
+  }
   prof.end(ls());
 }
 
@@ -326,6 +373,11 @@ void SolverT<P, VT, AT>::spmm_y_rr(const P* X, int64_t ldx, P* out, int64_t ldo,
 
 template <class P, class VT, class AT>
 void SolverT<P, VT, AT>::spmm_yt_rr(const P* X, int64_t ldx, P* out, int64_t ldo, int b) {
+  if (sink_) {
+    sink_->push_back(make_spmm_task(L_.sched_csc, L_.row_idx.p, ycw(), X, ldx, out, ldo, b,
+                                    spmm_part_.p, sizeof(P)));
+    return;
+  }
   prof.begin(kProfSpmmBwd, spmm_bytes(nnz_, n_, m_, b, sizeof(P), sizeof(P)),
              2.0 * nnz_ * b, ls());
   launch_spmm<P, P, AT, P>(L_.sched_csc, L_.row_idx.p, ycw(), X, ldx, out, ldo, b,
@@ -335,11 +387,23 @@ void SolverT<P, VT, AT>::spmm_yt_rr(const P* X, int64_t ldx, P* out, int64_t ldo
 
 template <class P, class VT, class AT>
 void SolverT<P, VT, AT>::cholqr_pass(const P* Hin, int64_t ldin, P* out, int64_t ldo,
-                                     int b, const int* gate) {
+                                     int b, const int* gate, bool low) {
   // Gram, its completion and the Cholesky inverse in one launch
   prof.begin(kProfGram, (double)sizeof(P) * m_ * b,
              1.0 * m_ * b * (b + 1) + (double)b * b * b, ls());
-  if (b <= kFuseCholMax && m_ <= kFuseRows) {
+  if constexpr (kBfPanel) {
+    low = low && !gate && gram_bf16_fits(m_, b, b, 1);
+  } else {
+    low = false;
+  }
+  if (low) {
+    if constexpr (kBfPanel) {
+      launch_gram_bf16(m_, b, b, Hin, ldin, Hin, ldin, G_.p, b, 1, gram_part_.p,
+                       gram_cap_, ls());
+      launch_chol_inv(b, G_.p, b, Rinv_.p, b, chol_work_.p, m_, shift_count_.p, ls(),
+                      blk_flag_.p, gate);
+    }
+  } else if (b <= kFuseCholMax && m_ <= kFuseRows) {
     launch_gram_fused<P, AT>(m_, b, b, Hin, ldin, Hin, ldin, G_.p, b, 1, gram_part_.p,
                              gram_cap_, fuse_ctr_.p, Rinv_.p, b, m_, shift_count_.p,
                              blk_flag_.p, ls(), gate);
@@ -359,9 +423,18 @@ void SolverT<P, VT, AT>::cholqr_pass(const P* Hin, int64_t ldin, P* out, int64_t
 // Hout = Hin - Qp (Qp^T Hin) with Qp = the first jb columns of Qw_
 template <class P, class VT, class AT>
 void SolverT<P, VT, AT>::project(const P* Hin, int64_t ldin, P* Hout, int jb, int b,
-                                 int Lw, const int* gate) {
+                                 int Lw, const int* gate, bool low) {
   prof.begin(kProfGram, (double)sizeof(P) * m_ * (jb + b), 2.0 * m_ * jb * b, ls());
-  if ((int64_t)jb * b <= 128 * 128 && m_ <= kFuseRows)
+  if constexpr (kBfPanel) {
+    low = low && !gate && gram_bf16_fits(m_, jb, b, 0);
+  } else {
+    low = false;
+  }
+  if (low) {
+    if constexpr (kBfPanel)
+      launch_gram_bf16(m_, jb, b, Qw_.p, Lw, Hin, ldin, Cg_.p, b, 0, gram_part_.p,
+                       gram_cap_, ls());
+  } else if ((int64_t)jb * b <= 128 * 128 && m_ <= kFuseRows)
     launch_gram_fused<P, AT>(m_, jb, b, Qw_.p, Lw, Hin, ldin, Cg_.p, b, 0, gram_part_.p,
                              gram_cap_, fuse_ctr_.p, nullptr, 0, 0, nullptr, nullptr,
                              ls(), gate);
@@ -385,7 +458,7 @@ void SolverT<P, VT, AT>::orth_block(int j, int b, int Lw, bool guarded) {
   const int* gate = blk_flag_.p;
   if (guarded) launch_set_int(blk_flag_.p, 0, ls());
   if (j == 0) {
-    cholqr_pass(H1_.p, b, H2_.p, b, b, nullptr);
+    cholqr_pass(H1_.p, b, H2_.p, b, b, nullptr, true);
     cholqr_pass(H2_.p, b, out, Lw, b, nullptr);
     if (guarded) {
       cholqr_pass(out, Lw, H1_.p, b, b, gate);
@@ -394,8 +467,8 @@ void SolverT<P, VT, AT>::orth_block(int j, int b, int Lw, bool guarded) {
     return;
   }
   const int jb = j * b;
-  project(H1_.p, b, H2_.p, jb, b, Lw, nullptr);
-  cholqr_pass(H2_.p, b, H1_.p, b, b, nullptr);
+  project(H1_.p, b, H2_.p, jb, b, Lw, nullptr, true);
+  cholqr_pass(H2_.p, b, H1_.p, b, b, nullptr, true);
   project(H1_.p, b, H2_.p, jb, b, Lw, nullptr);
   cholqr_pass(H2_.p, b, out, Lw, b, nullptr);
   // the gated pass writes the block directly (it reads H2, not the block)
@@ -464,14 +537,14 @@ void SolverT<P, VT, AT>::ritz_body(int k) {
 
 template <class P, class VT, class AT>
 void SolverT<P, VT, AT>::fresh_body(int k, int b, int p_eff, int Lw, bool guarded) {
-  prof.begin(kProfRng, (double)sizeof(P) * n_ * b, 0.0, ls());
-  launch_gaussian_ctr<P>(omega_.p, n_, b, b, prm_.seed, ctr_.p, ls());
-  prof.end(ls());
-  spmm_y(omega_.p, b, H1_.p, b, b);                          // H_0 = Y Omega
-  orth_block(0, b, Lw, guarded);
   if (power_) {
     // rSVD-PI (Alg. 4): each power iteration replaces the block; the
     // normalisation between iterations only has to keep its range (Lemma 3)
+    prof.begin(kProfRng, (double)sizeof(P) * n_ * b, 0.0, ls());
+    launch_gaussian_ctr<P>(omega_.p, n_, b, b, prm_.seed, ctr_.p, ls());
+    prof.end(ls());
+    spmm_y(omega_.p, b, H1_.p, b, b);                        // H_0 = Y Omega
+    orth_block(0, b, Lw, guarded);
     for (int j = 1; j <= p_eff; ++j) {
       spmm_yt(Qw_.p, Lw, Z_.p, b, b);                        // Y^T Q
       spmm_y(Z_.p, b, H1_.p, b, b);                          // Y Y^T Q
@@ -480,16 +553,41 @@ void SolverT<P, VT, AT>::fresh_body(int k, int b, int p_eff, int Lw, bool guarde
     eig_body(Qw_.p, Lw, Lw, k);
     return;
   }
-  // Y^T Q_{j-1} goes straight into columns [(j-1) b, j b) of B^T; it reads
-  // Y in the Rayleigh-Ritz precision, as B^T does
-  for (int j = 1; j <= p_eff; ++j) {
-    P* zj = Bt_.p + (int64_t)(j - 1) * b;
-    spmm_yt_rr(Qw_.p + (int64_t)(j - 1) * b, Lw, zj, Lw, b); // Y^T Q_{j-1}
-    spmm_y(zj, Lw, H1_.p, b, b);                             // H_j
-    orth_block(j, b, Lw, guarded);
+  for (int t = 0; fresh_stage(t, k, b, p_eff, Lw, guarded); ++t) {
   }
-  spmm_yt_rr(Qw_.p + (int64_t)p_eff * b, Lw, Bt_.p + (int64_t)p_eff * b, Lw, b);
-  eig_body(Qw_.p, Lw, Lw, k, true);
+}
+
+// rSVD-BKI (Alg. 5) in stages that each end with one sparse product, so that
+// a grouped driver can launch the products of several solves together:
+//   t = 0            Omega;                 product H_0 = Y Omega
+//   t = 2j + 1       orthonormalise block j; product Y^T Q_j -> block j of B^T
+//   t = 2j (j >= 1)                          product H_j = Y (block j-1 of B^T)
+//   t = 2 p_eff + 2  eigSVD of B^T (no product); returns false
+// Y^T Q_j is the Krylov product that feeds block j + 1 and, Q_j being final,
+// block j of the Rayleigh-Ritz product B^T = Y^T Q; it reads Y in the
+// Rayleigh-Ritz precision, as B^T does.
+template <class P, class VT, class AT>
+bool SolverT<P, VT, AT>::fresh_stage(int t, int k, int b, int p_eff, int Lw,
+                                     bool guarded) {
+  if (t == 0) {
+    prof.begin(kProfRng, (double)sizeof(P) * n_ * b, 0.0, ls());
+    launch_gaussian_ctr<P>(omega_.p, n_, b, b, prm_.seed, ctr_.p, ls());
+    prof.end(ls());
+    spmm_y(omega_.p, b, H1_.p, b, b);                        // H_0 = Y Omega
+    return true;
+  }
+  if (t == 2 * p_eff + 2) {
+    eig_body(Qw_.p, Lw, Lw, k, true);
+    return false;
+  }
+  const int j = t / 2;
+  if (t % 2 == 1) {
+    orth_block(j, b, Lw, guarded);
+    spmm_yt_rr(Qw_.p + (int64_t)j * b, Lw, Bt_.p + (int64_t)j * b, Lw, b);
+  } else {
+    spmm_y(Bt_.p + (int64_t)(j - 1) * b, Lw, H1_.p, b, b);
+  }
+  return true;
 }
 
 template <class P, class VT, class AT>
@@ -531,8 +629,8 @@ void SolverT<P, VT, AT>::run_graph(const GraphKey& key, F&& body) {
 }
 
 template <class P, class VT, class AT>
-void SolverT<P, VT, AT>::fresh_launch(int k, int p, uint32_t step_id, uint32_t attempt,
-                                      bool guarded) {
+void SolverT<P, VT, AT>::fresh_begin(int k, int p, uint32_t step_id, uint32_t attempt,
+                                     bool guarded) {
   int b, p_eff;
   widths(k, p, b, p_eff);
   const int Lw = power_ ? b : (p_eff + 1) * b;
@@ -541,14 +639,43 @@ void SolverT<P, VT, AT>::fresh_launch(int k, int p, uint32_t step_id, uint32_t a
   hctr_[0] = step_id;
   hctr_[1] = attempt;
   MC_HIP(hipMemcpyAsync(ctr_.p, hctr_, 2 * sizeof(uint32_t), hipMemcpyHostToDevice, st_));
-  if (graphs_ok(Lw, k)) {
-    const GraphKey key{power_ ? 4 : 1, k, b, p_eff, Lw, (int64_t)gen_,
+  call_.k = k;
+  call_.b = b;
+  call_.p_eff = p_eff;
+  call_.Lw = Lw;
+  call_.guarded = guarded;
+}
+
+template <class P, class VT, class AT>
+void SolverT<P, VT, AT>::fresh_launch(int k, int p, uint32_t step_id, uint32_t attempt,
+                                      bool guarded) {
+  fresh_begin(k, p, step_id, attempt, guarded);
+  const Call c = call_;
+  if (graphs_ok(c.Lw, k)) {
+    const GraphKey key{power_ ? 4 : 1, k, c.b, c.p_eff, c.Lw, (int64_t)gen_,
                        (int64_t)(intptr_t)Qw_.p, guarded ? 1 : 0};
-    run_graph(key, [&] { fresh_body(k, b, p_eff, Lw, guarded); });
+    run_graph(key, [&] { fresh_body(k, c.b, c.p_eff, c.Lw, guarded); });
   } else {
-    fresh_body(k, b, p_eff, Lw, guarded);
+    fresh_body(k, c.b, c.p_eff, c.Lw, guarded);
   }
-  last_guarded_ = guarded;
+  fresh_end();
+}
+
+template <class P, class VT, class AT>
+bool SolverT<P, VT, AT>::fresh_group_stage(int t, std::vector<SpmmTask>* sink) {
+  MC_REQUIRE(!power_, kEINVAL, "grouped stepping runs rSVD-BKI only");
+  sink_ = group_kind() >= 0 ? sink : nullptr;   // BF16 mode launches its own
+  struct Reset {
+    std::vector<SpmmTask>*& s;
+    ~Reset() { s = nullptr; }
+  } reset{sink_};
+  return fresh_stage(t, call_.k, call_.b, call_.p_eff, call_.Lw, call_.guarded);
+}
+
+template <class P, class VT, class AT>
+void SolverT<P, VT, AT>::fresh_end() {
+  const int k = call_.k, Lw = call_.Lw;
+  last_guarded_ = call_.guarded;
   k_last_ = k;
   read_launch(k, false, true);
   if (prm_.recycle == 1) {

@@ -464,19 +464,18 @@ __device__ __forceinline__ bf16_t ld_stream<bf16_t>(const bf16_t* p) {
 // columns per load, each lane accumulating CPL columns (c, c + BW, ...), so a
 // nonzero's index and value are broadcast once for up to BW * CPL columns;
 // 64 / BW nonzeros are in flight side by side.  Columns beyond b read an
-// in-bounds address with weight zero.
+// in-bounds address with weight zero.  The same device function serves the
+// single-product kernel and the grouped one (products of several solves in
+// one launch), so a product's arithmetic does not depend on how it was
+// launched.
 template <class VT, class XT, class AT, class OT, int BW, int CPL>
-__global__ __launch_bounds__(256) void spmm_kernel(
-    int64_t nseg, const int4* __restrict__ segs,
-    const int32_t* __restrict__ idx, const VT* __restrict__ val,
+__device__ __forceinline__ void spmm_segment(
+    const int4 sg, const int32_t* __restrict__ idx, const VT* __restrict__ val,
     const XT* __restrict__ X, int64_t ldx, OT* __restrict__ out, int64_t ldo,
     AT* __restrict__ part, int b) {
   constexpr int G = 64 / BW;       // nonzeros processed side by side
   constexpr int CB = BW * CPL;     // columns per pass
   const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (wave >= nseg) return;
-  const int4 sg = segs[wave];
   if (sg.x < 0) return;                        // padding of a banded schedule
   const int g = lane / BW;
   const int c = lane % BW;
@@ -531,21 +530,143 @@ __global__ __launch_bounds__(256) void spmm_kernel(
   }
 }
 
+template <class VT, class XT, class AT, class OT, int BW, int CPL>
+__global__ __launch_bounds__(256) void spmm_kernel(
+    int64_t nseg, const int4* __restrict__ segs,
+    const int32_t* __restrict__ idx, const VT* __restrict__ val,
+    const XT* __restrict__ X, int64_t ldx, OT* __restrict__ out, int64_t ldo,
+    AT* __restrict__ part, int b) {
+  const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (wave >= nseg) return;
+  spmm_segment<VT, XT, AT, OT, BW, CPL>(segs[wave], idx, val, X, ldx, out, ldo, part, b);
+}
+
+// Products of several solves in one launch: task t owns workgroups
+// [wg0_t, wg0_t + ceil(nseg_t / waves)), its first workgroup a multiple of
+// kBands so that a banded schedule keeps its workgroup-to-XCD placement.
+template <class VT, class XT, class AT, class OT, int BW, int CPL>
+__global__ __launch_bounds__(256) void spmm_group_kernel(const SpmmTask* __restrict__ tasks,
+                                                         int ntask) {
+  const int64_t wg = blockIdx.x;
+  int t = 0;
+  while (t + 1 < ntask && tasks[t + 1].wg0 <= wg) ++t;   // few tasks: a scan
+  const SpmmTask& k = tasks[t];
+  const int64_t wave = (wg - k.wg0) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (wave < 0 || wave >= k.nseg) return;
+  spmm_segment<VT, XT, AT, OT, BW, CPL>(k.segs[wave], k.idx, (const VT*)k.val,
+                                        (const XT*)k.X, k.ldx, (OT*)k.out, k.ldo,
+                                        (AT*)k.part, k.b);
+}
+
+template <class AT, class OT>
+__device__ __forceinline__ void spmm_fixup_one(const int4 fx, int col,
+                                               const AT* __restrict__ part,
+                                               OT* __restrict__ out, int64_t ldo, int b) {
+  AT acc = 0;
+  for (int q = 0; q < fx.z; ++q) acc += part[(int64_t)(fx.y + q) * b + col];
+  out[(int64_t)fx.x * ldo + col] = (OT)acc;
+}
+
 template <class AT, class OT>
 __global__ void spmm_fixup_kernel(int64_t nfix, const int4* __restrict__ fix,
                                   const AT* __restrict__ part, OT* __restrict__ out,
                                   int64_t ldo, int b) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= nfix * b) return;
-  const int64_t f = t / b;
-  const int col = (int)(t % b);
-  const int4 fx = fix[f];
-  AT acc = 0;
-  for (int q = 0; q < fx.z; ++q) acc += part[(int64_t)(fx.y + q) * b + col];
-  out[(int64_t)fx.x * ldo + col] = (OT)acc;
+  spmm_fixup_one<AT, OT>(fix[t / b], (int)(t % b), part, out, ldo, b);
+}
+
+// the fix-ups of a grouped launch: task t owns items [fx0_t, fx0_t + nfix_t b)
+template <class AT, class OT>
+__global__ void spmm_group_fixup_kernel(const SpmmTask* __restrict__ tasks, int ntask) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int t = 0;
+  while (t + 1 < ntask && tasks[t + 1].fx0 <= i) ++t;
+  const SpmmTask& k = tasks[t];
+  const int64_t r = i - k.fx0;
+  if (r < 0 || r >= k.nfix * k.b) return;
+  spmm_fixup_one<AT, OT>(k.fix[r / k.b], (int)(r % k.b), (const AT*)k.part, (OT*)k.out,
+                         k.ldo, k.b);
 }
 
 }  // namespace
+
+namespace {
+// The lane split of a product of width b: BW lanes per nonzero, CPL columns
+// per lane (see spmm_segment), as a form number 0..18.
+constexpr int kForms = 19;
+constexpr int kFormBW[kForms] = {8, 16, 8, 16, 8, 16, 8, 16, 8, 16, 16, 16, 32,
+                                 64, 64, 64, 64, 64, 64};
+constexpr int kFormCPL[kForms] = {1, 1, 3, 2, 5, 3, 7, 4, 9, 5, 6, 7, 4,
+                                  3, 4, 5, 6, 7, 8};
+int spmm_form(int b) {
+  if (b <= 8) return 0;
+  if (b <= 16) return 1;
+  if (b <= 24) return 2;
+  if (b <= 32) return 3;
+  if (b <= 40) return 4;
+  if (b <= 48) return 5;
+  if (b <= 56) return 6;
+  if (b <= 64) return 7;
+  if (b <= 72) return 8;
+  if (b <= 80) return 9;
+  if (b <= 96) return 10;
+  if (b <= 112) return 11;
+  if (b <= 128) return 12;
+  // wide panels: 64 lanes per nonzero and the fewest passes of at most 512
+  // columns, each as narrow as covers b
+  const int passes = (int)ceil_div(b, 512);
+  const int cpl = (int)ceil_div(ceil_div(b, passes), 64);   // 3..8
+  return 13 + std::min(std::max(cpl, 3), 8) - 3;
+}
+
+// launch `K<..., BW, CPL>` for form f (a switch over the table above)
+#define MC_FORM_SWITCH(f, LAUNCH) \
+  switch (f) {                    \
+    case 0: LAUNCH(8, 1); break;  \
+    case 1: LAUNCH(16, 1); break; \
+    case 2: LAUNCH(8, 3); break;  \
+    case 3: LAUNCH(16, 2); break; \
+    case 4: LAUNCH(8, 5); break;  \
+    case 5: LAUNCH(16, 3); break; \
+    case 6: LAUNCH(8, 7); break;  \
+    case 7: LAUNCH(16, 4); break; \
+    case 8: LAUNCH(8, 9); break;  \
+    case 9: LAUNCH(16, 5); break; \
+    case 10: LAUNCH(16, 6); break; \
+    case 11: LAUNCH(16, 7); break; \
+    case 12: LAUNCH(32, 4); break; \
+    case 13: LAUNCH(64, 3); break; \
+    case 14: LAUNCH(64, 4); break; \
+    case 15: LAUNCH(64, 5); break; \
+    case 16: LAUNCH(64, 6); break; \
+    case 17: LAUNCH(64, 7); break; \
+    default: LAUNCH(64, 8); break; \
+  }
+}  // namespace
+
+SpmmTask make_spmm_task(const Schedule& S, const int32_t* idx, const void* val,
+                        const void* X, int64_t ldx, void* out, int64_t ldo, int b,
+                        void* part, size_t x_bytes) {
+  SpmmTask t{};
+  // the banded form for large panels (see Schedule)
+  const bool band = S.band_nseg > 0 &&
+                    S.gathered * (int64_t)b * (int64_t)x_bytes >= kBandPanelBytes &&
+                    (b <= kBandWide || S.long_share);
+  t.nseg = band ? S.band_nseg : S.nseg;
+  t.segs = band ? S.band_segs.p : S.segs.p;
+  t.nfix = band ? S.band_nfix : S.nfix;
+  t.fix = band ? S.band_fix.p : S.fix.p;
+  t.idx = idx;
+  t.val = val;
+  t.X = X;
+  t.ldx = ldx;
+  t.out = out;
+  t.ldo = ldo;
+  t.part = part;
+  t.b = b;
+  return t;
+}
 
 template <class VT, class XT, class AT, class OT>
 void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
@@ -553,71 +674,64 @@ void launch_spmm(const Schedule& S, const int32_t* idx, const VT* val,
                  AT* part, hipStream_t st) {
   if (S.nseg == 0 || b <= 0) return;
   const int T = 64 * kSpmmWaves;
-  // the banded form for large panels (see Schedule)
-  const bool band = S.band_nseg > 0 &&
-                    S.gathered * (int64_t)b * (int64_t)sizeof(XT) >= kBandPanelBytes &&
-                    (b <= kBandWide || S.long_share);
-  const int64_t nseg = band ? S.band_nseg : S.nseg;
-  const int4* segs = band ? S.band_segs.p : S.segs.p;
-  const int64_t nfix = band ? S.band_nfix : S.nfix;
-  const int4* fix = band ? S.band_fix.p : S.fix.p;
-  const unsigned grid = (unsigned)ceil_div(nseg, kSpmmWaves);
+  const SpmmTask k = make_spmm_task(S, idx, val, X, ldx, out, ldo, b, part, sizeof(XT));
+  const unsigned grid = (unsigned)ceil_div(k.nseg, kSpmmWaves);
 #define MC_SPMM(BW, CPL)                                                          \
   hipLaunchKernelGGL((spmm_kernel<VT, XT, AT, OT, BW, CPL>), dim3(grid), dim3(T), 0, \
-                     st, nseg, segs, idx, val, X, ldx, out, ldo, part, b)
-  if (b <= 8)
-    MC_SPMM(8, 1);
-  else if (b <= 16)
-    MC_SPMM(16, 1);
-  else if (b <= 24)
-    MC_SPMM(8, 3);
-  else if (b <= 32)
-    MC_SPMM(16, 2);
-  else if (b <= 40)
-    MC_SPMM(8, 5);
-  else if (b <= 48)
-    MC_SPMM(16, 3);
-  else if (b <= 56)
-    MC_SPMM(8, 7);
-  else if (b <= 64)
-    MC_SPMM(16, 4);
-  else if (b <= 72)
-    MC_SPMM(8, 9);
-  else if (b <= 80)
-    MC_SPMM(16, 5);
-  else if (b <= 96)
-    MC_SPMM(16, 6);
-  else if (b <= 112)
-    MC_SPMM(16, 7);
-  else if (b <= 128)
-    MC_SPMM(32, 4);
-  else {
-    // wide panels: 64 lanes per nonzero and the fewest passes of at most
-    // 512 columns, each as narrow as covers b
-    const int passes = (int)ceil_div(b, 512);
-    const int cpl = (int)ceil_div(ceil_div(b, passes), 64);   // 3..8
-    if (cpl <= 3)
-      MC_SPMM(64, 3);
-    else if (cpl == 4)
-      MC_SPMM(64, 4);
-    else if (cpl == 5)
-      MC_SPMM(64, 5);
-    else if (cpl == 6)
-      MC_SPMM(64, 6);
-    else if (cpl == 7)
-      MC_SPMM(64, 7);
-    else
-      MC_SPMM(64, 8);
-  }
+                     st, k.nseg, k.segs, idx, val, X, ldx, out, ldo, part, b)
+  MC_FORM_SWITCH(spmm_form(b), MC_SPMM)
 #undef MC_SPMM
   MC_CHECK_LAUNCH();
-  if (nfix) {
-    const int64_t work = nfix * b;
+  if (k.nfix) {
+    const int64_t work = k.nfix * b;
     hipLaunchKernelGGL((spmm_fixup_kernel<AT, OT>), dim3((unsigned)ceil_div(work, T)),
-                       dim3(T), 0, st, nfix, fix, part, out, ldo, b);
+                       dim3(T), 0, st, k.nfix, k.fix, part, out, ldo, b);
     MC_CHECK_LAUNCH();
   }
 }
+
+// Grouped launches: the tasks are split by lane form; each form's tasks go
+// out in one product launch (and one fix-up launch) whose task table is
+// copied from `staging` (pinned host memory, `cap` entries, left untouched
+// until the stream has passed the copies) to `table` (device).
+template <class VT, class XT, class AT, class OT>
+void launch_spmm_group(const std::vector<SpmmTask>& tasks, SpmmTask* staging,
+                       SpmmTask* table, int64_t cap, hipStream_t st) {
+  const int T = 64 * kSpmmWaves;
+  int64_t used = 0;
+  for (int f = 0; f < kForms; ++f) {
+    int64_t first = used, wg = 0, fx = 0;
+    for (const SpmmTask& k : tasks) {
+      if (k.nseg == 0 || k.b <= 0 || spmm_form((int)k.b) != f) continue;
+      MC_REQUIRE(used < cap, kEINVAL, "grouped SpMM: task table full");
+      SpmmTask e = k;
+      e.wg0 = wg;
+      e.fx0 = fx;
+      wg += round_up(ceil_div(k.nseg, kSpmmWaves), kBands);
+      fx += k.nfix * k.b;
+      staging[used++] = e;
+    }
+    const int n = (int)(used - first);
+    if (n == 0) continue;
+    MC_HIP(hipMemcpyAsync(table + first, staging + first, n * sizeof(SpmmTask),
+                          hipMemcpyHostToDevice, st));
+#define MC_SPMM_G(BW, CPL)                                                           \
+  hipLaunchKernelGGL((spmm_group_kernel<VT, XT, AT, OT, BW, CPL>), dim3((unsigned)wg), \
+                     dim3(T), 0, st, table + first, n)
+    MC_FORM_SWITCH(f, MC_SPMM_G)
+#undef MC_SPMM_G
+    MC_CHECK_LAUNCH();
+    if (fx) {
+      hipLaunchKernelGGL((spmm_group_fixup_kernel<AT, OT>), dim3((unsigned)ceil_div(fx, T)),
+                         dim3(T), 0, st, table + first, n);
+      MC_CHECK_LAUNCH();
+    }
+  }
+}
+template void launch_spmm_group<float, float, float, float>(
+    const std::vector<SpmmTask>&, SpmmTask*, SpmmTask*, int64_t, hipStream_t);
+template void launch_spmm_group<double, double, double, double>(
+    const std::vector<SpmmTask>&, SpmmTask*, SpmmTask*, int64_t, hipStream_t);
 
 template void launch_spmm<double, double, double, double>(
     const Schedule&, const int32_t*, const double*, const double*, int64_t,
@@ -627,6 +741,9 @@ template void launch_spmm<float, float, float, float>(
     float*, int64_t, int, float*, hipStream_t);
 template void launch_spmm<bf16_t, float, float, float>(
     const Schedule&, const int32_t*, const bf16_t*, const float*, int64_t,
+    float*, int64_t, int, float*, hipStream_t);
+template void launch_spmm<bf16_t, bf16_t, float, float>(
+    const Schedule&, const int32_t*, const bf16_t*, const bf16_t*, int64_t,
     float*, int64_t, int, float*, hipStream_t);
 
 // ---------------------------------------------------------------------------
@@ -790,7 +907,8 @@ __global__ void scale_kernel(int64_t n, const double* __restrict__ a,
 }  // namespace
 
 int64_t sddmm_partials(const Layout& L) {
-  return std::max<int64_t>(ceil_div(L.nnz, 256), ceil_div(L.sched_csr.nseg, kSpmmWaves));
+  return std::max({ceil_div(L.nnz, 256), ceil_div(L.sched_csr.nseg, kSpmmWaves),
+                   ceil_div(L.sched_csr.band_nseg, kSpmmWaves)});
 }
 
 template <class FT, class AT, class VT, class WT>
@@ -801,10 +919,18 @@ void launch_sddmm_update(const Layout& L, const double* mvals, double* y, VT* yv
                          hipStream_t st) {
   MC_REQUIRE(r >= 0, kEINVAL, "negative rank");
   const Schedule& S = L.sched_csr;
-  const int64_t nb = std::max<int64_t>(1, ceil_div(S.nseg, kSpmmWaves));
+  // the banded form, as the forward SpMM takes it, once the gathered rows of
+  // V outgrow one XCD's L2: each XCD then gathers from its own column band
+  // (a row cut at the bands needs no partial sums here: every nonzero's dot
+  // product is whole within its piece)
+  const bool band = S.band_nseg > 0 &&
+                    S.gathered * (int64_t)std::max(r, 1) * (int64_t)sizeof(FT) >= kBandPanelBytes;
+  const int64_t nseg = band ? S.band_nseg : S.nseg;
+  const int4* segs = band ? S.band_segs.p : S.segs.p;
+  const int64_t nb = std::max<int64_t>(1, ceil_div(nseg, kSpmmWaves));
 #define MC_SDDMM(BW, CPL)                                                           \
   hipLaunchKernelGGL((sddmm_update_kernel<FT, AT, VT, WT, BW, CPL>), dim3((unsigned)nb), \
-                     dim3(64 * kSpmmWaves), 0, st, S.nseg, S.segs.p, L.col_idx.p, mvals, \
+                     dim3(64 * kSpmmWaves), 0, st, nseg, segs, L.col_idx.p, mvals,      \
                      y, yv, ycv, yw, ycw, L.invperm.p, U, ldu, V, ldv, sig, r, delta,  \
                      apply, partial)
   // lanes per nonzero and columns per lane as the SpMM's forms

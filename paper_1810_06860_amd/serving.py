@@ -17,6 +17,13 @@ finishes.  The loop
 
 Latency is completion time minus arrival time.  The solver factory and the
 footprint are parameters, so the loop can be exercised without a device.
+
+With ``grouped=True`` one driver thread advances all admitted solves
+together, one SVT step each per round (``mc_svt_step_group``): their fresh
+rSVD-BKI calls run in lock-step stages and the sparse products of a stage go
+out in shared launches, so the device sees one launch per stage and lane form
+for the whole batch instead of one per solve.  Admission and retirement
+happen between rounds; results are the same as each request solved alone.
 """
 
 import collections
@@ -172,6 +179,75 @@ def serve(requests, budget_bytes, max_active=16, solver_factory=None,
         th.join()
     if errors:
         raise errors[0]
+    return done
+
+
+def serve_grouped(requests, budget_bytes, max_active=16, solver_factory=None,
+                  footprint_fn=None, clock=time.perf_counter, keep_factors=False,
+                  stream_pool=None, on_done=None, step_group=None):
+    """The request loop with batched rounds: between rounds, arrivals are
+    admitted (arrival order, free slot, footprint within the budget) and
+    finished solves retired; each round advances every admitted solve by one
+    step with `step_group` (``mc_svt_step_group`` by default).  Returns the
+    `Served` records in completion order."""
+    if solver_factory is None:
+        solver_factory = _default_factory(stream_pool, False)
+    if footprint_fn is None:
+        from .svt import footprint
+
+        def footprint_fn(req):
+            p = req.problem
+            return footprint(p.m, p.n, p.rows.size, req.params)
+    if step_group is None:
+        from .svt import step_group
+    pending = collections.deque(sorted(requests, key=lambda r: (r.t_arrival, r.id)))
+    active = []             # [req, solver, footprint, t_admit, steps, last]
+    used = 0
+    done = []
+    t0 = clock()
+
+    def retire(entry, status, err=""):
+        nonlocal used
+        req, solver, fp, t_admit, steps, last = entry
+        facs = solver.factors() if keep_factors and status == MC_OK else None
+        solver.close()
+        rec = Served(id=req.id, t_arrival=req.t_arrival, t_admit=t_admit,
+                     t_done=clock() - t0, steps=steps, status=int(status),
+                     converged=bool(last.get("converged", 0)),
+                     rank=int(last.get("r", 0)),
+                     res=float(last.get("res", float("nan"))), footprint=fp,
+                     factors=facs, error=err)
+        used -= fp
+        done.append(rec)
+        if on_done is not None:
+            on_done(rec, len(done))
+
+    while pending or active:
+        now = clock() - t0
+        while pending and pending[0].t_arrival <= now and len(active) < max_active:
+            req = pending[0]
+            fp = int(footprint_fn(req))
+            if active and used + fp > budget_bytes:
+                break                                      # wait for memory
+            pending.popleft()
+            used += fp
+            active.append([req, solver_factory(req), fp, now, 0, {}])
+        if not active:
+            time.sleep(max(0.0, pending[0].t_arrival - (clock() - t0)))
+            continue
+        infos, status = step_group([e[1] for e in active])
+        still = []
+        for e, info, st in zip(active, infos, status):
+            if st == MC_OK:
+                e[4] += 1
+                e[5] = info
+            i_max = e[0].params.get("i_max", 200)
+            if st != MC_OK or info.get("converged") or e[4] >= i_max:
+                err = "" if st == MC_OK else f"status {st}"
+                retire(e, st, err)
+            else:
+                still.append(e)
+        active = still
     return done
 
 

@@ -190,6 +190,17 @@ def step_many(solves):
     return [infos[j].as_dict() for j in range(n)], list(status)
 
 
+def step_group(solves):
+    """One step of each solve with their sparse products batched into shared
+    launches (mc_svt_step_group); returns (infos, statuses)."""
+    n = len(solves)
+    hs = (C.c_void_p * n)(*[s.handle for s in solves])
+    infos = (StepInfo * n)()
+    status = (C.c_int * n)()
+    lib().mc_svt_step_group(hs, n, infos, status)
+    return [infos[j].as_dict() for j in range(n)], list(status)
+
+
 def footprint(m, n, nnz, params=None):
     p = to_params(params)
     return int(lib().mc_svt_footprint(m, n, nnz, C.byref(p)))

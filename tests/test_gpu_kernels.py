@@ -149,6 +149,34 @@ def test_gram_fp32(K, N, p, q, sym):
         assert np.array_equal(got, got.T)
 
 
+@pytest.mark.parametrize("N,p,q,sym", [(4096, 16, 16, 1), (9001, 75, 75, 1),
+                                       (140000, 48, 48, 1), (6001, 112, 112, 1),
+                                       (8193, 64, 33, 0), (9000, 80, 75, 0)])
+def test_gram_bf16(K, N, p, q, sym):
+    # the BF16 matrix-core Gram: operands rounded to BF16 (exact products in
+    # FP32), FP32 sums within a wavefront's rows, FP64 across workgroups;
+    # against the FP64 product of the BF16-rounded operands
+    rng = np.random.default_rng(N + p + 2)
+    A = rng.standard_normal((N, p))
+    B = None if sym else rng.standard_normal((N, q))
+
+    def bf16(x):
+        u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+        u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+        return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+    got = K.gram(A, B, precision="bf16")
+    Ab = bf16(A)
+    Bb = Ab if sym else bf16(B)
+    want = Ab.T @ Bb
+    scale = np.abs(Ab).T @ np.abs(Bb)
+    assert np.max(np.abs(got - want) / scale) < N * 2.0 ** -24
+    # and it differs from the FP32 Gram by the BF16 rounding of the operands
+    assert np.max(np.abs(got - A.T @ (A if sym else B)) / scale) > 1e-6
+    if sym:
+        assert np.array_equal(got, got.T)
+
+
 @pytest.mark.parametrize("N,p,q", [(1, 1, 1), (63, 5, 7), (1000, 21, 21), (4097, 33, 81),
                                    (70001, 324, 81), (3000, 100, 129), (2000, 81, 300),
                                    (500, 17, 16), (777, 64, 48)])

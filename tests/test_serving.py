@@ -104,3 +104,60 @@ def test_i_max_retires_unconverged_and_idle_wait():
     b = [s for s in out if s.id == 1][0]
     assert a.steps == 7 and not a.converged
     assert b.t_admit >= 0.2 - 1e-9
+
+
+class _Clock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
+class _RoundSolve:
+    """A solve that never converges; closes into a ledger of retirements."""
+
+    def __init__(self, req, closed):
+        self.req, self.i, self.closed = req, 0, closed
+
+    def step(self):
+        self.i += 1
+        return dict(i=self.i, r=1, res=1.0, converged=0)
+
+    def factors(self):
+        return None
+
+    def close(self):
+        self.closed.append(self.req.id)
+
+
+def test_grouped_rounds_admission_and_retirement():
+    # batched rounds: every admitted solve takes one step per round; arrivals
+    # join between rounds while slots and memory allow; a solve retires in
+    # the round it reaches i_max
+    clock = _Clock()
+    rounds, closed = [], []
+
+    def step_group(solves):
+        rounds.append(sorted(s.req.id for s in solves))
+        clock.t += 0.01
+        return [s.step() for s in solves], [0] * len(solves)
+
+    reqs = [serving.Request(0, 0.0, None, dict(i_max=3)),
+            serving.Request(1, 0.0, None, dict(i_max=1)),
+            serving.Request(2, 0.0, None, dict(i_max=2)),
+            serving.Request(3, 0.015, None, dict(i_max=2))]
+    fp = {0: 40, 1: 40, 2: 40, 3: 10}
+    done = serving.serve_grouped(reqs, budget_bytes=100, max_active=4,
+                                 solver_factory=lambda r: _RoundSolve(r, closed),
+                                 footprint_fn=lambda r: fp[r.id], clock=clock,
+                                 step_group=step_group)
+    assert sorted(s.id for s in done) == [0, 1, 2, 3]
+    # request 2 waits for memory until request 1 retires; request 3 arrives
+    # at 15 ms and joins the round after that
+    assert rounds[0] == [0, 1]
+    assert rounds[1] == [0, 2]
+    assert rounds[2] == [0, 2, 3]
+    assert {s.id: s.steps for s in done} == {0: 3, 1: 1, 2: 2, 3: 2}
+    assert closed == [1, 0, 2, 3]
+    assert all(not s.converged for s in done)
