@@ -103,7 +103,8 @@ def parse():
                     help="requests of the serving trace to run (0: skip)")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0)
     ap.add_argument("--serve-slots", type=int, default=16)
-    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-streams", type=int, default=16,
+                    help="streams the served solves are dealt to (one per slot by default)")
     ap.add_argument("--serve-graphs", type=int, default=1,
                     help="1: served solves replay captured graphs")
     ap.add_argument("--serve-grouped", type=int, default=1,
