@@ -17,7 +17,8 @@
 //      their joint invariant subspace.  Rayleigh quotients on T give the
 //      returned eigenvalues.
 //   4. Back-transformation W = H_0 H_1 ... H_{L-3} Z, 16 lanes per vector
-//      with the vector held in registers.
+//      with the vector held in registers; the reflectors are stored as full
+//      rows v_j (zero before j + 1, one at j + 1).
 #include "chol_regs.hpp"
 #include "kernels.hpp"
 
@@ -142,10 +143,11 @@ __device__ TriSmem tri_layout_r(double* sm, int L, size_t region) {
   return s;
 }
 
-// doubles of the matrix region: A (L x L), later Z (L x k), C (k x k) and
-// the U factors of a batch of nb inverse iterations (3 L nb)
+// doubles of the matrix region: A (L x L), later Z (L x k), C (k x k) and,
+// for a batch of nb inverse iterations, the U factors (3 L nb), multipliers
+// (L nb) and row exchanges (L nb ints, in L nb doubles)
 __host__ __device__ inline size_t tri_region(int L, int k, int nb) {
-  const size_t a = (size_t)L * L, b = (size_t)L * k + (size_t)k * k + 3 * (size_t)L * nb;
+  const size_t a = (size_t)L * L, b = (size_t)L * k + (size_t)k * k + 5 * (size_t)L * nb;
   return a > b ? a : b;
 }
 
@@ -259,79 +261,185 @@ __device__ void polar_step_lds(int L, int k, double* __restrict__ Z,
   }
 }
 
+// Inverse iteration for eigenvalue lam on column j of Z (row-major, k
+// columns): solves (T - lam I) x = y for the right-hand side y held in the
+// column, in place.  The pivoted LU of T - lam I is formed on the first solve
+// (FACTOR): row i's U entries go to Uf + i ldu (u0 is replaced by the
+// reciprocal of the clamped pivot once the back substitution has used it),
+// its multiplier to lf[i ldl] and its row exchange to sw[i ldl]; a later
+// solve (!FACTOR) reuses them.  One thread runs it; the operands of kIC
+// consecutive rows are read into registers ahead of each stretch of the
+// recurrences, and the elimination selects instead of branching.  Returns
+// max |x_i| (after any rescaling of the column by 2^-500, which keeps the
+// solution finite).
+constexpr int kIC = 8;
+template <bool FACTOR>
+__device__ __forceinline__ double invit_solve(int L, int k, int j, const double* __restrict__ d,
+                                              const double* __restrict__ e, double lam,
+                                              double ptiny, double* __restrict__ Z,
+                                              double* __restrict__ Uf, int ldu,
+                                              double* __restrict__ lf, int* __restrict__ sw,
+                                              int ldl) {
+  double r0 = d[0] - lam;
+  double r1 = L > 1 ? e[0] : 0.0;
+  double ycur = Z[j];
+  // elimination step i (rows i, i + 1) on the factor and the right-hand side
+  auto elim = [&](int i, double c, double a1, double b1, double ynext, double lv, int sv) {
+    bool swap;
+    double l;
+    if (FACTOR) {
+      // rows i and i + 1 exchange when the subdiagonal entry is larger
+      swap = fabs(r0) < fabs(c);
+      const double num = swap ? r0 : c;
+      const double den = swap ? c : r0;
+      l = den != 0.0 ? num * rcp(den) : 0.0;
+      double* uf = Uf + (size_t)i * ldu;
+      uf[0] = den;
+      uf[1] = swap ? a1 : r1;
+      uf[2] = swap ? b1 : 0.0;
+      lf[(size_t)i * ldl] = l;
+      sw[(size_t)i * ldl] = swap;
+      const double ra = swap ? r1 : a1;
+      const double rb = swap ? a1 : r1;
+      r0 = ra - l * rb;
+      r1 = swap ? -l * b1 : b1;
+    } else {
+      swap = sv != 0;
+      l = lv;
+    }
+    const double zi = swap ? ynext : ycur;
+    const double ya = swap ? ycur : ynext;
+    Z[i * k + j] = zi;
+    ycur = ya - l * zi;
+  };
+  const int nel = L - 1;                       // steps i = 0 .. L - 2
+  int i0 = 0;
+  for (; i0 + kIC <= nel; i0 += kIC) {
+    // row i + 1's operands; Z row i + 1 is read before row i is written
+    double cv[kIC], av[kIC], bv[kIC], yv[kIC], lv[kIC];
+    int sv[kIC];
+#pragma unroll
+    for (int u = 0; u < kIC; ++u) {
+      const int i = i0 + u;
+      yv[u] = Z[(i + 1) * k + j];
+      if (FACTOR) {
+        cv[u] = e[i];
+        av[u] = d[i + 1] - lam;
+        bv[u] = e[i + 1];                      // e[L - 1] = 0
+        lv[u] = 0.0;
+        sv[u] = 0;
+      } else {
+        cv[u] = av[u] = bv[u] = 0.0;
+        lv[u] = lf[(size_t)i * ldl];
+        sv[u] = sw[(size_t)i * ldl];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kIC; ++u) elim(i0 + u, cv[u], av[u], bv[u], yv[u], lv[u], sv[u]);
+  }
+  for (; i0 < nel; ++i0) {
+    const int i = i0;
+    if (FACTOR)
+      elim(i, e[i], d[i + 1] - lam, e[i + 1], Z[(i + 1) * k + j], 0.0, 0);
+    else
+      elim(i, 0.0, 0.0, 0.0, Z[(i + 1) * k + j], lf[(size_t)i * ldl], sw[(size_t)i * ldl]);
+  }
+  if (FACTOR) {
+    double* uf = Uf + (size_t)(L - 1) * ldu;
+    uf[0] = r0; uf[1] = 0.0; uf[2] = 0.0;
+  }
+  Z[(L - 1) * k + j] = ycur;
+  // back substitution, rescaling if the solution grows past 2^500 (after a
+  // rescaling the next stretch starts at the row below, read afresh)
+  double z1 = 0.0, z2 = 0.0, zmax = 0.0;
+  // row i from its U entries and right-hand side; true if it rescaled
+  auto back = [&](int i, double f0, double f1, double f2, double zr) {
+    double ri = f0;
+    if (FACTOR) {
+      const double u0 = fabs(ri) < ptiny ? (ri < 0.0 ? -ptiny : ptiny) : ri;
+      ri = rcp(u0);
+      Uf[(size_t)i * ldu] = ri;
+    }
+    double z = (zr - f1 * z1 - f2 * z2) * ri;
+    const bool big = fabs(z) > 0x1p500;
+    if (big) {
+      const double sc = 0x1p-500;
+      for (int t = 0; t < L; ++t)
+        if (t != i) Z[t * k + j] *= sc;
+      z *= sc; z1 *= sc; z2 *= sc; zmax *= sc;
+    }
+    Z[i * k + j] = z;
+    zmax = fmax(zmax, fabs(z));
+    z2 = z1;
+    z1 = z;
+    return big;
+  };
+  for (int i0 = L - 1; i0 >= 0;) {
+    if (i0 + 1 < kIC) {
+      const double* uf = Uf + (size_t)i0 * ldu;
+      back(i0, uf[0], uf[1], uf[2], Z[i0 * k + j]);
+      --i0;
+      continue;
+    }
+    int next = i0 - kIC;
+    double f0[kIC], f1[kIC], f2[kIC], zv[kIC];
+#pragma unroll
+    for (int u = 0; u < kIC; ++u) {
+      const double* uf = Uf + (size_t)(i0 - u) * ldu;
+      f0[u] = uf[0]; f1[u] = uf[1]; f2[u] = uf[2];
+      zv[u] = Z[(i0 - u) * k + j];
+    }
+#pragma unroll
+    for (int u = 0; u < kIC; ++u) {
+      if (back(i0 - u, f0[u], f1[u], f2[u], zv[u])) {
+        next = i0 - u - 1;
+        break;
+      }
+    }
+    i0 = next;
+  }
+  return zmax;
+}
+
+// column j of Z scaled to unit norm (after a first scaling by 1 / zmax, so
+// the sum of squares cannot overflow); one thread
+__device__ __forceinline__ void invit_normalize(int L, int k, int j, double zmax,
+                                                double* __restrict__ Z) {
+  const double inv = zmax > 0.0 ? rcp(zmax) : 1.0;
+  double ss = 0.0;
+#pragma unroll 8
+  for (int i = 0; i < L; ++i) {
+    const double z = Z[i * k + j] * inv;
+    ss += z * z;
+  }
+  const double sc = inv * rcp(sqrt(ss));
+#pragma unroll 8
+  for (int i = 0; i < L; ++i) Z[i * k + j] *= sc;
+}
+
 // Two steps of inverse iteration for eigenvalue lam on column j of Z (the
-// right-hand side on entry, the normalised solution on exit).  The rows of
-// the U factor of the pivoted LU of T - lam I (3 values per row) go to Uf
-// with stride ldu between rows and unit stride between columns of a batch.
-__device__ void invit_column(int L, int k, int j, const double* d, const double* e,
-                             double lam, double tnorm, double* Z, double* Uf, int ldu) {
+// right-hand side on entry, the normalised solution on exit), in one thread;
+// lf, sw: L entries each (stride ldl) for the multipliers and row exchanges.
+__device__ __forceinline__ void invit_column(int L, int k, int j, const double* __restrict__ d,
+                                             const double* __restrict__ e, double lam,
+                                             double tnorm, double* __restrict__ Z,
+                                             double* __restrict__ Uf, int ldu,
+                                             double* __restrict__ lf, int* __restrict__ sw,
+                                             int ldl) {
   const double ptiny = fmax(kU * tnorm, DBL_MIN / kU);
   for (int pass = 0; pass < 2; ++pass) {
-    double r0 = d[0] - lam;
-    double r1 = L > 1 ? e[0] : 0.0;
-    double ycur = Z[j];
-    for (int i = 0; i + 1 < L; ++i) {
-      const double c = e[i];
-      const double a1 = d[i + 1] - lam;
-      const double b1 = e[i + 1];            // e[L - 1] = 0
-      const double ynext = Z[(i + 1) * k + j];
-      double u0, u1, u2;
-      if (fabs(r0) >= fabs(c)) {
-        const double l = r0 != 0.0 ? c * rcp(r0) : 0.0;
-        u0 = r0; u1 = r1; u2 = 0.0;
-        r0 = a1 - l * r1;
-        r1 = b1;
-        Z[i * k + j] = ycur;
-        ycur = ynext - l * ycur;
-      } else {
-        const double l = r0 * rcp(c);
-        u0 = c; u1 = a1; u2 = b1;
-        r0 = r1 - l * a1;
-        r1 = -l * b1;
-        Z[i * k + j] = ynext;
-        ycur = ycur - l * ynext;
-      }
-      double* u = Uf + (size_t)i * ldu;
-      u[0] = u0; u[1] = u1; u[2] = u2;
-    }
-    {
-      double* u = Uf + (size_t)(L - 1) * ldu;
-      u[0] = r0; u[1] = 0.0; u[2] = 0.0;
-    }
-    Z[(L - 1) * k + j] = ycur;
-    // back substitution, rescaling if the solution grows past 2^500
-    double z1 = 0.0, z2 = 0.0, zmax = 0.0;
-    for (int i = L - 1; i >= 0; --i) {
-      const double* u = Uf + (size_t)i * ldu;
-      double u0 = u[0];
-      if (fabs(u0) < ptiny) u0 = u0 < 0.0 ? -ptiny : ptiny;
-      double z = (Z[i * k + j] - u[1] * z1 - u[2] * z2) * rcp(u0);
-      if (fabs(z) > 0x1p500) {
-        const double sc = 0x1p-500;
-        for (int t = 0; t < L; ++t)
-          if (t != i) Z[t * k + j] *= sc;
-        z *= sc; z1 *= sc; z2 *= sc; zmax *= sc;
-      }
-      Z[i * k + j] = z;
-      zmax = fmax(zmax, fabs(z));
-      z2 = z1;
-      z1 = z;
-    }
-    const double inv = zmax > 0.0 ? rcp(zmax) : 1.0;
-    double ss = 0.0;
-    for (int i = 0; i < L; ++i) {
-      const double z = Z[i * k + j] * inv;
-      ss += z * z;
-    }
-    const double sc = inv * rcp(sqrt(ss));
-    for (int i = 0; i < L; ++i) Z[i * k + j] *= sc;
+    const double zmax =
+        pass == 0 ? invit_solve<true>(L, k, j, d, e, lam, ptiny, Z, Uf, ldu, lf, sw, ldl)
+                  : invit_solve<false>(L, k, j, d, e, lam, ptiny, Z, Uf, ldu, lf, sw, ldl);
+    invit_normalize(L, k, j, zmax, Z);
   }
 }
 
 // Householder steps j = j0 .. L-3 of the reduction to tridiagonal form, on
 // the trailing block held in LDS: element (r, c), r, c >= j0, of the matrix
 // being reduced is Ab[(r - j0) * ldb + (c - j0)].  Writes d, e, hb, hr for
-// j >= j0 and the reflector rows to hh.
+// j >= j0 and, once all steps are done, the reflectors v_j as full rows of hh
+// (no global store inside the step loop, whose barriers would wait for it).
 __device__ void tri_steps(int L, int j0, double* __restrict__ Ab, int ldb,
                           const TriSmem& s, double* __restrict__ hh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -364,7 +472,6 @@ __device__ void tri_steps(int L, int j0, double* __restrict__ Ab, int ldb,
       s.hb[j] = beta;
       s.hr[j] = rv;
     }
-    for (int t = tid; t < n; t += kTT) hh[(int64_t)j * L + o + t] = hrow[t];
     // p = beta A22 v, lanes of a group of S share a row
     int S = 1;
     while (S < 8 && 2 * S * n <= kTT) S <<= 1;
@@ -416,6 +523,15 @@ __device__ void tri_steps(int L, int j0, double* __restrict__ Ab, int ldb,
     sq = wsum(sq);
     if (lane == 0) s.red2[wave] = sq;
     __syncthreads();
+  }
+  // the reflectors, in one pass once all steps are done: row j of hh is v_j
+  // in full (zero before j + 1, one at j + 1), from row j of the block, which
+  // no step after j touches
+  const int nb = L - j0;
+  for (int t = tid; t < nb * L; t += kTT) {
+    const int j = j0 + t / L, c = t % L;
+    if (j + 2 < L)
+      hh[(int64_t)j * L + c] = c == j + 1 ? 1.0 : (c > j + 1 ? el(j, c) * s.hr[j] : 0.0);
   }
   if (tid == 0) {
     if (L >= 2 && L - 2 >= j0) {
@@ -533,6 +649,8 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
   double* Z = A;                       // L x k
   double* C = A + (size_t)L * k;       // k x k
   double* Uf = C + (size_t)k * k;      // 3 x L x nb rows of U for a batch
+  double* lfb = Uf + 3 * (size_t)L * nb;  // L x nb multipliers
+  int* swb = (int*)(lfb + (size_t)L * nb);  // L x nb row exchanges
   for (int t = tid; t < L * k; t += kTT) {
     const int i = t / k, j = t % k;
     const uint64_t h = mix64(((uint64_t)(j + 1) << 32) ^ (uint64_t)i);
@@ -542,7 +660,8 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
   for (int j0 = 0; j0 < k; j0 += nb) {
     const int j = j0 + tid;
     if (tid < nb && j < k)
-      invit_column(L, k, j, s.d, s.e, s.lam[j], tn, Z, Uf + 3 * tid, 3 * nb);
+      invit_column(L, k, j, s.d, s.e, s.lam[j], tn, Z, Uf + 3 * tid, 3 * nb, lfb + tid,
+                   swb + tid, nb);
   }
   __syncthreads();
   cholqr_lds(L, k, Z, C);
@@ -580,14 +699,12 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
     }
     for (int j = L - 3; j >= 0; --j) {
       const double beta = s.hb[j];
-      const double rv = s.hr[j];
       double v[kVecRegs];
       double dot = 0.0;
 #pragma unroll
       for (int q = 0; q < kVecRegs; ++q) {
         const int i = vlane + kVecLanes * q;
-        const double h = A[j * L + min(i, L - 1)];
-        v[q] = i == j + 1 ? 1.0 : (i > j + 1 && i < L ? h * rv : 0.0);
+        v[q] = i < L ? A[j * L + min(i, L - 1)] : 0.0;
         dot += v[q] * z[q];
       }
       dot = group_sum(dot, kVecLanes) * beta;
@@ -607,9 +724,9 @@ __global__ __launch_bounds__(kTT) void tri_topk_kernel(
 // ---- matrices too large for one workgroup's LDS -----------------------------
 // The first j0 = L - Ls Householder steps run on a copy of G in global memory,
 // one launch per step; a one-workgroup kernel then finishes the trailing
-// Ls x Ls block in LDS and finds the eigenvalues.  Eigenvectors: one
-// workgroup per vector for the inverse iteration, Cholesky QR and a
-// Newton-Schulz step with the Gram and panel kernels, and a back-
+// Ls x Ls block in LDS.  Eigenpairs: one workgroup per wanted eigenvalue
+// finds it by multisection and its vector by inverse iteration; Cholesky QR
+// and a Newton-Schulz step with the Gram and panel kernels; a back-
 // transformation kernel with each vector in registers.
 
 constexpr int kBigRows = 4;        // trailing rows per workgroup (one per wavefront)
@@ -626,6 +743,8 @@ static_assert(64 * kStepPer >= 64 * kVecLanes, "big_step_kernel rows must cover 
 // its share of p^T v.  Workgroup 0 records the reflector.  Launch j = j0
 // applies the last pending update to rows and columns >= j0 and stops.
 // p and the p^T v partials alternate between two buffers by step parity.
+// Everything the launch reads from global memory is requested at its start,
+// and it has three barriers.
 __global__ __launch_bounds__(256) void big_step_kernel(
     int L, int j, int j0, double* __restrict__ Ag, double* __restrict__ hh,
     double* __restrict__ dg, double* __restrict__ eg, double* __restrict__ hbg,
@@ -633,18 +752,16 @@ __global__ __launch_bounds__(256) void big_step_kernel(
   extern __shared__ double sv[];
   double* vp = sv;            // v of step j-1 on [j, L)
   double* wp = vp + L;        // w of step j-1 on [j, L)
-  double* vj = wp + L;        // v of step j on [j + 1, L)
-  __shared__ double red[4], redp[4];
+  double* vj = wp + L;        // row j after step j-1, on [j + 1, L) (not scaled)
+  __shared__ double redp[4], red[4], redq[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool last = j == j0;
   const int o = last ? j : j + 1;             // first row / column this launch touches
   const int npart_stride = (L + kBigRows - 1) / kBigRows;
   const bool upd = j >= 1;
-  // Loads that nothing in this launch writes go out first, so their latency
-  // overlaps the reductions below: this wavefront's trailing row (stored
-  // with the updates up to step j-2) and row j (likewise; step j-1's update
-  // of it is applied on the fly).
-  const int r = blockIdx.x * kBigRows + wave;  // trailing row
+  const int jp = j - 1;
+  // this wavefront's trailing row (stored with the updates up to step j-2)
+  const int r = blockIdx.x * kBigRows + wave;
   const int a = o + r;
   const bool has_row = a < L;
   double xs[kStepPer];
@@ -653,56 +770,73 @@ __global__ __launch_bounds__(256) void big_step_kernel(
 #pragma unroll
     for (int u = 0; u < kStepPer; ++u) xs[u] = row[min(o + lane + 64 * u, L - 1)];
   }
-  constexpr int kRowJ = 1024 / 256;            // row j entries per thread (L <= 1024)
-  double xj[kRowJ];
+  // row j (likewise; step j-1's update of it is applied below), and step
+  // j-1's reflector row and p, at columns c = j + tid + 256 u: the thread
+  // that forms vp[c], wp[c] also updates row j at c
+  constexpr int kRowJ = 1024 / 256;            // entries per thread (L <= 1024)
+  double xj[kRowJ], hv[kRowJ], pw[kRowJ];
   double djj = 0.0;
-  if (!last) {
 #pragma unroll
-    for (int u = 0; u < kRowJ; ++u) {
-      const int c = o + tid + 256 * u;
-      xj[u] = c < L ? Ag[(int64_t)j * L + c] : 0.0;
-    }
-    if (blockIdx.x == 0 && tid == 0) djj = Ag[(int64_t)j * L + j];
+  for (int u = 0; u < kRowJ; ++u) {
+    const int c = j + tid + 256 * u;
+    const bool in = c < L;
+    xj[u] = (!last && in) ? Ag[(int64_t)j * L + c] : 0.0;
+    hv[u] = (upd && in) ? hh[(int64_t)jp * L + c] : 0.0;
+    pw[u] = (upd && in) ? Pbuf[(size_t)(jp & 1) * L + (c - j)] : 0.0;
   }
+  if (!last && blockIdx.x == 0 && tid == 0) djj = Ag[(int64_t)j * L + j];
+  // p_j of step j-1 (w_j = p_j - K, since v_j = 1), needed by every thread
+  const double p0 = upd ? Pbuf[(size_t)(jp & 1) * L] : 0.0;
+  double K = 0.0;
   if (upd) {
-    // step j-1: its trailing block starts at j
-    const int jp = j - 1;
-    const double bp = hbg[jp], rvp = hrg[jp];
-    const double* __restrict__ Pp = Pbuf + (size_t)(jp & 1) * L;
+    const double bp = hbg[jp];
     const double* __restrict__ pp = pbuf + (size_t)(jp & 1) * npart_stride;
     const int nparts = (L - j + kBigRows - 1) / kBigRows;
-    // p^T v: the partials summed by the whole workgroup (one load each)
     double pv = 0.0;
     for (int w = tid; w < nparts; w += 256) pv += pp[w];
+    // p^T v: the partials summed by the whole workgroup
     pv = wsum(pv);
     if (lane == 0) redp[wave] = pv;
     __syncthreads();
     const double pvt = (redp[0] + redp[1]) + (redp[2] + redp[3]);
-    const double K = 0.5 * bp * pvt;
-    for (int c = j + tid; c < L; c += 256) {
-      const double v = c == j ? 1.0 : hh[(int64_t)jp * L + c] * rvp;
-      vp[c] = v;
-      wp[c] = Pp[c - j] - K * v;
-    }
-    __syncthreads();
-  }
-  if (!last) {
-    // row j after step j-1 (columns > j), the reflector of step j from it
-    const int n = L - o;
-    double sq = 0.0;
+    K = 0.5 * bp * pvt;
 #pragma unroll
     for (int u = 0; u < kRowJ; ++u) {
-      const int c = o + tid + 256 * u;
+      const int c = j + tid + 256 * u;
       if (c < L) {
+        const double v = hv[u];
+        pw[u] = pw[u] - K * v;
+        vp[c] = v;
+        wp[c] = pw[u];
+      }
+    }
+  }
+  const int n = L - o;
+  double sq = 0.0;
+  if (!last) {
+    // row j after step j-1 needs v_j = 1 and w_j, which every thread forms
+    // itself (the same expressions as vp[j], wp[j]) rather than waiting for LDS
+    const double vjj = 1.0;
+    const double wjj = upd ? p0 - K * vjj : 0.0;
+#pragma unroll
+    for (int u = 0; u < kRowJ; ++u) {
+      const int c = j + tid + 256 * u;
+      if (c >= o && c < L) {
         double x = xj[u];
-        if (upd) x -= vp[j] * wp[c] + wp[j] * vp[c];
+        if (upd) x -= vjj * pw[u] + wjj * hv[u];
         vj[c] = x;
         if (c > o) sq += x * x;
       }
     }
-    sq = wsum(sq);
-    if (lane == 0) red[wave] = sq;
-    __syncthreads();
+    if (blockIdx.x == 0 && tid == 0) {
+      if (upd) djj -= vjj * wjj + wjj * vjj;
+      dg[j] = djj;
+    }
+  }
+  sq = wsum(sq);
+  if (lane == 0) red[wave] = sq;
+  __syncthreads();                            // vj, vp, wp and the sums are complete
+  if (!last) {
     const double sig2 = (red[0] + red[1]) + (red[2] + red[3]);
     const double alpha = vj[o];
     double beta = 0.0, rv = 0.0, mu = alpha;
@@ -714,18 +848,15 @@ __global__ __launch_bounds__(256) void big_step_kernel(
     }
     if (blockIdx.x == 0) {
       if (tid == 0) {
-        if (upd) djj -= vp[j] * wp[j] + wp[j] * vp[j];
-        dg[j] = djj;
         eg[j] = mu;
         hbg[j] = beta;
         hrg[j] = rv;
       }
-      for (int t = tid; t < n; t += 256) hh[(int64_t)j * L + o + t] = vj[o + t];
+      for (int c = tid; c < L; c += 256)
+        hh[(int64_t)j * L + c] = c < o ? 0.0 : (c == o ? 1.0 : vj[c] * rv);
     }
-    __syncthreads();                            // vj[o] read above by every thread
-    for (int c = o + tid; c < L; c += 256) vj[c] = c == o ? 1.0 : vj[c] * rv;
-    __syncthreads();
-    // this workgroup's rows: update by step j-1, then p = beta A22 v
+    // this workgroup's rows: update by step j-1, then p = beta A22 v with
+    // v = (1, vj[o+1..] / v0)
     double pr = 0.0;
     if (r < n) {
       double* __restrict__ row = Ag + (int64_t)a * L;
@@ -739,17 +870,18 @@ __global__ __launch_bounds__(256) void big_step_kernel(
             x -= vp[a] * wp[c] + wp[a] * vp[c];
             row[c] = x;
           }
-          acc += x * vj[c];
+          acc += x * (c == o ? 1.0 : vj[c] * rv);
         }
       }
       acc = wsum(acc);
       pr = beta * acc;
       if (lane == 0) Pbuf[(size_t)(j & 1) * L + r] = pr;
     }
-    if (lane == 0) red[wave] = r < n ? pr * vj[o + r] : 0.0;
+    if (lane == 0) redq[wave] = r < n ? pr * (r == 0 ? 1.0 : vj[o + r] * rv) : 0.0;
     __syncthreads();
     if (tid == 0)
-      pbuf[(size_t)(j & 1) * npart_stride + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+      pbuf[(size_t)(j & 1) * npart_stride + blockIdx.x] =
+          (redq[0] + redq[1]) + (redq[2] + redq[3]);
   } else if (upd) {
     // the pending update of step j0 - 1 on rows and columns >= j0
     if (has_row) {
@@ -773,14 +905,12 @@ __global__ __launch_bounds__(256) void copy_square_kernel(int L, const double* _
   Ag[t] = G[r * ldg + c];
 }
 
-// The trailing block (rows and columns j0 ..) in LDS: the remaining steps and
-// the eigenvalues.  Writes d, e, hb, hr for every step, the k eigenvalues
-// (descending) and ||T||.
+// The trailing block (rows and columns j0 ..) in LDS: the remaining steps.
+// Writes d, e, hb, hr for every step.
 __global__ __launch_bounds__(kTT) void tri_tail_kernel(
     int L, int j0, const double* __restrict__ Ag, double* __restrict__ hh,
     double* __restrict__ dg, double* __restrict__ eg, double* __restrict__ hbg,
-    double* __restrict__ hrg, int k, double* __restrict__ lam,
-    double* __restrict__ tnorm) {
+    double* __restrict__ hrg) {
   extern __shared__ double smem[];
   const int Ls = L - j0;
   const TriSmem s = tri_layout_r(smem, L, (size_t)Ls * Ls);
@@ -789,47 +919,130 @@ __global__ __launch_bounds__(kTT) void tri_tail_kernel(
     const int r = t / Ls, c = t % Ls;
     s.A[t] = Ag[(int64_t)(j0 + r) * L + j0 + c];
   }
-  for (int i = tid; i < j0; i += kTT) {
-    s.d[i] = dg[i];
-    s.e[i] = eg[i];
-    s.hb[i] = hbg[i];
-    s.hr[i] = hrg[i];
-  }
   __syncthreads();
   tri_steps(L, j0, s.A, Ls, s, hh);
-  const double tn = tri_eigvals(L, k, s);
-  for (int i = tid; i < L; i += kTT) {
+  for (int i = j0 + tid; i < L; i += kTT) {
     dg[i] = s.d[i];
     eg[i] = s.e[i];
     hbg[i] = s.hb[i];
     hrg[i] = s.hr[i];
   }
-  for (int i = tid; i < k; i += kTT) lam[i] = s.lam[i];
-  if (tid == 0) tnorm[0] = tn;
 }
 
-// Two inverse-iteration steps for eigenvalue j (one workgroup per vector):
-// the column lands in Zg (L x k, row-major).
-__global__ __launch_bounds__(64) void big_invit_kernel(
+constexpr int kEigT = 256;         // multisection points per round (one per thread)
+
+// Eigenvalue j (the j-th largest) of T = tridiag(e, d, e) by multisection on
+// Sturm counts, kEigT points per round, each round narrowing the bracket by
+// a factor kEigT + 1; then two inverse-iteration steps for its vector, whose
+// column lands in Zg (L x k, row-major): the solves in one thread, the second
+// reusing the first one's factorisation, the normalisations by the whole
+// workgroup.  One workgroup per eigenvalue, so the k searches and solves run
+// side by side on k compute units.
+__global__ __launch_bounds__(kEigT) void big_eigvec_kernel(
     int L, int k, const double* __restrict__ dg, const double* __restrict__ eg,
-    const double* __restrict__ lam, const double* __restrict__ tnorm,
     double* __restrict__ Zg) {
   extern __shared__ double smem[];
   double* d = smem;
   double* e = d + L;
-  double* z = e + L;
-  double* U = z + L;
+  double* e2 = e + L;                         // e^2; the multipliers after the search
+  double* z = e2 + L;
+  double* U = z + L;                          // 3 L
+  int* sw = (int*)(U + 3 * (size_t)L);        // L row exchanges
+  __shared__ double red[4 * (kEigT / 64)];
+  __shared__ int cnt[kEigT / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int kW = kEigT / 64;
   const int j = blockIdx.x;
-  for (int i = threadIdx.x; i < L; i += 64) {
+  for (int i = tid; i < L; i += kEigT) {
     d[i] = dg[i];
     e[i] = eg[i];
     const uint64_t h = mix64(((uint64_t)(j + 1) << 32) ^ (uint64_t)i);
     z[i] = (double)(h >> 11) * 0x1.0p-53 - 0.5;
   }
   __syncthreads();
-  if (threadIdx.x == 0) invit_column(L, 1, 0, d, e, lam[j], tnorm[0], z, U, 3);
+  // Gershgorin interval, ||T||, and the pivot floor
+  double tn = 0.0, glo = INFINITY, ghi = -INFINITY, emax = 0.0;
+  for (int i = tid; i < L; i += kEigT) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < L ? fabs(e[i]) : 0.0);
+    tn = fmax(tn, fabs(d[i]) + r);
+    glo = fmin(glo, d[i] - r);
+    ghi = fmax(ghi, d[i] + r);
+    e2[i] = i + 1 < L ? e[i] * e[i] : 0.0;
+    emax = fmax(emax, e2[i]);
+  }
+  for (int w = 32; w >= 1; w >>= 1) {
+    tn = fmax(tn, __shfl_xor(tn, w, 64));
+    glo = fmin(glo, __shfl_xor(glo, w, 64));
+    ghi = fmax(ghi, __shfl_xor(ghi, w, 64));
+    emax = fmax(emax, __shfl_xor(emax, w, 64));
+  }
+  if (lane == 0) {
+    red[wave] = tn;
+    red[kW + wave] = glo;
+    red[2 * kW + wave] = ghi;
+    red[3 * kW + wave] = emax;
+  }
   __syncthreads();
-  for (int i = threadIdx.x; i < L; i += 64) Zg[(int64_t)i * k + j] = z[i];
+  tn = 0.0; glo = INFINITY; ghi = -INFINITY; emax = 0.0;
+  for (int w = 0; w < kW; ++w) {
+    tn = fmax(tn, red[w]);
+    glo = fmin(glo, red[kW + w]);
+    ghi = fmax(ghi, red[2 * kW + w]);
+    emax = fmax(emax, red[3 * kW + w]);
+  }
+  const double pivmin = DBL_MIN * fmax(1.0, emax);
+  const double widen = 2.0 * L * kU * tn + 2.0 * pivmin;
+  double lo = glo - widen, hi = ghi + widen;
+  const int idx = L - 1 - j;                  // ascending index
+  // every thread holds the same bracket: the count of points at or below idx
+  // is shared, and the new ends are the same expressions as the points
+  for (int round = 0; round < 64; ++round) {
+    const double mid = 0.5 * (lo + hi);
+    if ((hi - lo) <= fmax(4.0 * kU * fmax(fabs(lo), fabs(hi)), 2.0 * kU * tn) || mid <= lo ||
+        mid >= hi)
+      break;
+    const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(kEigT + 1);
+    const int c = sturm(L, d, e2, x, pivmin);
+    const uint64_t m = __ballot(c <= idx);
+    if (lane == 0) cnt[wave] = __popcll(m);
+    __syncthreads();
+    int nle = 0;
+    for (int w = 0; w < kW; ++w) nle += cnt[w];
+    __syncthreads();                          // cnt is rewritten next round
+    const double nlo = nle > 0 ? lo + (hi - lo) * (double)nle / (double)(kEigT + 1) : lo;
+    const double nhi =
+        nle < kEigT ? lo + (hi - lo) * (double)(nle + 1) / (double)(kEigT + 1) : hi;
+    lo = nlo;
+    hi = nhi;
+  }
+  // two inverse-iteration steps: the solves in thread 0 (the second reuses
+  // the factorisation), each followed by a normalisation by all threads
+  const double lam = 0.5 * (lo + hi);
+  const double ptiny = fmax(kU * tn, DBL_MIN / kU);
+  __syncthreads();                            // e2 is the multipliers' array now
+  for (int pass = 0; pass < 2; ++pass) {
+    if (tid == 0)
+      red[0] = pass == 0 ? invit_solve<true>(L, 1, 0, d, e, lam, ptiny, z, U, 3, e2, sw, 1)
+                         : invit_solve<false>(L, 1, 0, d, e, lam, ptiny, z, U, 3, e2, sw, 1);
+    __syncthreads();
+    const double zmax = red[0];
+    const double inv = zmax > 0.0 ? rcp(zmax) : 1.0;
+    double ss = 0.0;
+    for (int i = tid; i < L; i += kEigT) {
+      const double x = z[i] * inv;
+      ss += x * x;
+    }
+    ss = wsum(ss);
+    __syncthreads();                          // red[0] is read by everyone
+    if (lane == 0) red[wave] = ss;
+    __syncthreads();
+    double sst = 0.0;
+    for (int w = 0; w < kW; ++w) sst += red[w];
+    const double sc = inv * rcp(sqrt(sst));
+    for (int i = tid; i < L; i += kEigT) z[i] *= sc;
+    __syncthreads();
+  }
+  for (int i = tid; i < L; i += kEigT) Zg[(int64_t)i * k + j] = z[i];
 }
 
 // C (k x k, symmetric positive definite) -> R^{-1} (upper triangular, with
@@ -914,24 +1127,31 @@ __global__ void ns_matrix_kernel(int k, double* __restrict__ C) {
   C[t] = (a == b ? 1.5 : 0.0) - 0.5 * C[t];
 }
 
+constexpr int kBackT = 256;            // back-transformation: 4 vectors per workgroup
+constexpr int kBackLds = 7680;         // doubles of staged reflector rows (60 KB)
+
 // Rayleigh quotients on T and W = H_0 ... H_{L-3} Z: one wavefront per
-// vector, entries lane + 64 q in registers (q < R)
+// vector, entries lane + 64 q in registers (q < R).  The reflector rows come
+// in chunks of C consecutive rows (one contiguous stretch of hh), staged in
+// LDS by the whole workgroup, so the global-memory latency is paid once per
+// chunk instead of once per reflector.
 template <int R>
-__global__ __launch_bounds__(512) void big_back_kernel(
-    int L, int k, const double* __restrict__ Zg, const double* __restrict__ hh,
-    const double* __restrict__ hbg, const double* __restrict__ hrg,
-    const double* __restrict__ dg, const double* __restrict__ eg,
-    double* __restrict__ S, double* __restrict__ D, double* __restrict__ W,
-    int64_t ldw) {
+__global__ __launch_bounds__(kBackT) void big_back_kernel(
+    int L, int k, int C, const double* __restrict__ Zg, const double* __restrict__ hh,
+    const double* __restrict__ hbg, const double* __restrict__ dg,
+    const double* __restrict__ eg, double* __restrict__ S, double* __restrict__ D,
+    double* __restrict__ W, int64_t ldw) {
+  extern __shared__ double hs[];               // C x L
+  __shared__ double bs[kBackLds / 64];
   const int lane = threadIdx.x & 63;
-  const int col = blockIdx.x * 8 + (threadIdx.x >> 6);
-  if (col >= k) return;                        // whole wavefronts
+  const int col = blockIdx.x * (kBackT / 64) + (threadIdx.x >> 6);
+  const bool act = col < k;                    // whole wavefronts; all of them stage
   double z[R];
   double rq = 0.0;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int i = lane + 64 * q;
-    const bool in = i < L;
+    const bool in = act && i < L;
     const int ic = min(i, L - 1);
     const double zi = in ? Zg[(int64_t)ic * k + col] : 0.0;
     const double zp = (in && i + 1 < L) ? Zg[(int64_t)(ic + 1) * k + col] : 0.0;
@@ -939,35 +1159,44 @@ __global__ __launch_bounds__(512) void big_back_kernel(
     rq += zi * (dg[ic] * zi + 2.0 * eg[ic] * zp);
   }
   rq = wsum(rq);
-  if (lane == 0) {
+  if (act && lane == 0) {
     D[col] = rq;
     S[col] = sqrt(fmax(rq, 0.0));
   }
-  for (int j = L - 3; j >= 0; --j) {
-    const double beta = hbg[j];
-    const double rv = hrg[j];
-    const double* __restrict__ hr = hh + (int64_t)j * L;
-    double dot = 0.0;
+  for (int jh = L - 3; jh >= 0; jh -= C) {
+    const int jl = max(jh - C + 1, 0);
+    const int nr = jh - jl + 1;
+    __syncthreads();                           // the previous chunk is consumed
+    const double* __restrict__ src = hh + (int64_t)jl * L;
+#pragma unroll 8
+    for (int t = threadIdx.x; t < nr * L; t += kBackT) hs[t] = src[t];
+    for (int t = threadIdx.x; t < nr; t += kBackT) bs[t] = hbg[jl + t];
+    __syncthreads();
+    if (act) {
+      for (int j = jh; j >= jl; --j) {
+        // the stored v_j holds its zeros, so no masks; four partial sums
+        // shorten the dependent chain
+        const double* hr = hs + (size_t)(j - jl) * L;
+        double v[R];
+        double dp[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int i = lane + 64 * q;
-      const double h = hr[min(i, L - 1)];
-      const double v = i == j + 1 ? 1.0 : (i > j + 1 && i < L ? h * rv : 0.0);
-      dot += v * z[q];
-    }
-    dot = wsum(dot) * beta;
+        for (int q = 0; q < R; ++q) {
+          const int i = lane + 64 * q;
+          v[q] = i < L ? hr[min(i, L - 1)] : 0.0;
+          dp[q & 3] += v[q] * z[q];
+        }
+        const double dot = wsum((dp[0] + dp[1]) + (dp[2] + dp[3])) * bs[j - jl];
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int i = lane + 64 * q;
-      const double h = hr[min(i, L - 1)];
-      const double v = i == j + 1 ? 1.0 : (i > j + 1 && i < L ? h * rv : 0.0);
-      z[q] -= dot * v;
+        for (int q = 0; q < R; ++q) z[q] -= dot * v[q];
+      }
     }
   }
+  if (act) {
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int i = lane + 64 * q;
-    if (i < L) W[(int64_t)i * ldw + col] = z[q];
+    for (int q = 0; q < R; ++q) {
+      const int i = lane + 64 * q;
+      if (i < L) W[(int64_t)i * ldw + col] = z[q];
+    }
   }
 }
 
@@ -1014,7 +1243,7 @@ static int tail_block(int L, size_t lds_bytes) {
 size_t TriBigWork::doubles(int L, int k) {
   const size_t nparts = (size_t)(L + kBigRows - 1) / kBigRows;
   const size_t splits = (size_t)gram_splits(L, k, k, 1);
-  return 2 * (size_t)L * L + 6 * (size_t)L + 2 * nparts + k + 8 + 2 * (size_t)L * k +
+  return 2 * (size_t)L * L + 6 * (size_t)L + 2 * nparts + 2 * (size_t)L * k +
          3 * (size_t)k * k + splits * k * k;
 }
 
@@ -1033,9 +1262,7 @@ void launch_tri_big(int L, const double* G, int64_t ldg, int k, double* S, doubl
   double* hrg = hbg + L;
   double* Pg = hrg + L;                      // p of two consecutive steps
   double* part = Pg + 2 * (size_t)L;         // their p^T v partials
-  double* lam = part + 2 * (size_t)nparts;
-  double* tn = lam + k;
-  double* Zg = tn + 8;
+  double* Zg = part + 2 * (size_t)nparts;
   double* Z2 = Zg + (size_t)L * k;
   double* C = Z2 + (size_t)L * k;
   double* Ri = C + (size_t)k * k;
@@ -1058,10 +1285,11 @@ void launch_tri_big(int L, const double* G, int64_t ldg, int k, double* S, doubl
   const size_t tail_bytes = sizeof(double) * ((size_t)Ls * Ls + 7 * (size_t)L + 6 * kTWaves) +
                             sizeof(int) * kTT;
   hipLaunchKernelGGL(tri_tail_kernel, dim3(1), dim3(kTT), tail_bytes, st, L, j0, Ag, hh,
-                     dg, eg, hbg, hrg, k, lam, tn);
+                     dg, eg, hbg, hrg);
   MC_CHECK_LAUNCH();
-  hipLaunchKernelGGL(big_invit_kernel, dim3(k), dim3(64), sizeof(double) * 6 * (size_t)L,
-                     st, L, k, dg, eg, lam, tn, Zg);
+  hipLaunchKernelGGL(big_eigvec_kernel, dim3(k), dim3(kEigT),
+                     sizeof(double) * 7 * (size_t)L + sizeof(int) * (size_t)L, st, L, k, dg, eg,
+                     Zg);
   MC_CHECK_LAUNCH();
   // Cholesky QR, then one Newton-Schulz step
   launch_gram<double, double>(L, k, k, Zg, k, Zg, k, C, k, 1, gpart, gcap, st);
@@ -1073,13 +1301,15 @@ void launch_tri_big(int L, const double* G, int64_t ldg, int k, double* S, doubl
   MC_CHECK_LAUNCH();
   launch_panel_gemm<double, double>(L, k, k, Z2, k, C, k, 1.0, nullptr, 0.0, nullptr, 0, Zg,
                                     k, st);
-  const dim3 grid((unsigned)((k + 7) / 8));
+  const dim3 grid((unsigned)((k + kBackT / 64 - 1) / (kBackT / 64)));
+  const int rows = std::max(1, std::min(kBackLds / L, kBackLds / 64));   // per chunk
+  const size_t back_lds = sizeof(double) * (size_t)rows * L;
   if (L <= 512)
-    hipLaunchKernelGGL(big_back_kernel<8>, grid, dim3(512), 0, st, L, k, Zg, hh, hbg, hrg,
-                       dg, eg, S, D, W, ldw);
+    hipLaunchKernelGGL(big_back_kernel<8>, grid, dim3(kBackT), back_lds, st, L, k, rows, Zg,
+                       hh, hbg, dg, eg, S, D, W, ldw);
   else
-    hipLaunchKernelGGL(big_back_kernel<16>, grid, dim3(512), 0, st, L, k, Zg, hh, hbg,
-                       hrg, dg, eg, S, D, W, ldw);
+    hipLaunchKernelGGL(big_back_kernel<16>, grid, dim3(kBackT), back_lds, st, L, k, rows, Zg,
+                       hh, hbg, dg, eg, S, D, W, ldw);
   MC_CHECK_LAUNCH();
 }
 

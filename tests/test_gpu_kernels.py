@@ -279,6 +279,21 @@ def test_syev_tiny_repeated_and_graded(K):
     np.testing.assert_array_equal(np.abs(W2), np.eye(7)[:, [4, 6, 2, 0, 5, 3, 1]])
 
 
+def test_syev_large_diagonal_and_rank_one(K):
+    # the multi-launch path on inputs whose reflectors vanish (a diagonal
+    # matrix) or whose spectrum is one value and a zero cluster (all ones)
+    L = 300
+    G = np.diag(np.arange(L, 0, -1.0))
+    ev, W, _ = K.syev(G, 50)
+    np.testing.assert_allclose(ev, np.arange(L, L - 50, -1.0), rtol=1e-14)
+    np.testing.assert_allclose(np.abs(W), np.eye(L)[:, :50], atol=1e-13)
+    G2 = np.ones((L, L))
+    ev2, W2, _ = K.syev(G2, 4)
+    np.testing.assert_allclose(ev2, [float(L), 0.0, 0.0, 0.0], atol=1e-11)
+    np.testing.assert_allclose(np.abs(W2[:, 0]), np.full(L, L ** -0.5), rtol=1e-12)
+    assert np.linalg.norm(W2.T @ W2 - np.eye(4)) < 2e-14 * L
+
+
 def test_syev_degenerate_and_diagonal(K):
     G = np.diag(np.arange(40, 0, -1.0))
     ev, W, _ = K.syev(G, 10)
