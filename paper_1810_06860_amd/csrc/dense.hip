@@ -638,18 +638,21 @@ __global__ __launch_bounds__(256) void gram_rows_bf16_kernel(
     }
 }
 
-// Sum of the split partials.  `lanes` consecutive threads (a power of two
-// dividing 64, so they sit in one wavefront) share an output: lane j adds the
-// splits j, j + lanes, ... in order, then the lanes are combined by a fixed
-// butterfly, so the result does not depend on scheduling.
+// Sum of the split partials.  A wavefront covers 64 / lanes consecutive
+// outputs with `lanes` threads each (lanes a power of two, at most 16): lane
+// (u, o) -- output o, u = lane / (64 / lanes) -- adds the splits u, u + lanes,
+// ... in order, so that for each split the wavefront reads its outputs'
+// entries side by side; the `lanes` partial sums of an output are then
+// combined by a fixed butterfly, so the result does not depend on scheduling.
 template <class AT>
 __global__ __launch_bounds__(256) void gram_reduce_kernel(
     int p, int q, int nsplit, int lanes, const AT* __restrict__ part,
     double* __restrict__ C, int64_t ldc, int sym, int tile, const int* __restrict__ gate) {
   if (gate && *gate == 0) return;
-  const int per_block = 256 / lanes;
-  const int lane = threadIdx.x % lanes;
-  const int64_t t = blockIdx.x * (int64_t)per_block + threadIdx.x / lanes;
+  const int outs = 64 / lanes;                 // outputs per wavefront
+  const int lane = threadIdx.x & 63;
+  const int o = lane % outs, u = lane / outs;
+  const int64_t t = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * outs + o;
   const int64_t tot = (int64_t)p * q;
   const bool live = t < tot;
   int si = 0, sj = 0, i = 0, j = 0;
@@ -661,11 +664,22 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(
     if (sym && (i / tile) > (j / tile)) { si = j; sj = i; }   // mirrored tile
   }
   double acc = 0.0;
-  if (live)
-    for (int s = lane; s < nsplit; s += lanes)
-      acc += (double)part[(int64_t)s * tot + (int64_t)si * q + sj];
-  for (int w = 1; w < lanes; w <<= 1) acc += __shfl_xor(acc, w, 64);
-  if (live && lane == 0) C[(int64_t)i * ldc + j] = acc;
+  if (live) {
+    // the partials were written by other workgroups (other XCDs): their loads
+    // go out sixteen at a time, and are added in split order
+    const AT* __restrict__ pp = part + (int64_t)si * q + sj;
+    int s = u;
+    for (; s + 15 * lanes < nsplit; s += 16 * lanes) {
+      AT v[16];
+#pragma unroll
+      for (int w = 0; w < 16; ++w) v[w] = pp[(int64_t)(s + w * lanes) * tot];
+#pragma unroll
+      for (int w = 0; w < 16; ++w) acc += (double)v[w];
+    }
+    for (; s < nsplit; s += lanes) acc += (double)pp[(int64_t)s * tot];
+  }
+  for (int w = outs; w < 64; w <<= 1) acc += __shfl_xor(acc, w, 64);
+  if (live && u == 0) C[(int64_t)i * ldc + j] = acc;
 }
 
 // C = beta*C0 + alpha * X W diag(colscale), X tall (N x p), W small (p x q),
@@ -724,6 +738,20 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(
     }
     __syncthreads();
   }
+  // epilogue: the column scales and C0 entries of all of this lane's outputs
+  // are requested together (clamped addresses, uniform conditions), then the
+  // results are formed and stored
+  double cs[NT], cz[NT][4];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = min(c0 + t * 16 + lane % 16, q - 1);
+    cs[t] = colscale ? colscale[col] : 1.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = min<int64_t>(r0 + w * 16 + M::row(lane, v), N - 1);
+      cz[t][v] = beta != 0.0 ? (double)C0[row * ldc0 + col] : 0.0;
+    }
+  }
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -732,8 +760,8 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(
       const int col = c0 + t * 16 + lane % 16;
       if (row < N && col < q) {
         double x = alpha * acc[t][v];
-        if (colscale) x *= colscale[col];
-        if (beta != 0.0) x += beta * (double)C0[row * ldc0 + col];
+        if (colscale) x *= cs[t];
+        if (beta != 0.0) x += beta * cz[t][v];
         C[row * ldc + col] = (OT)x;
       }
     }
@@ -965,7 +993,15 @@ __global__ void ritz_reduce_kernel(int nblk, int k, const double* __restrict__ p
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= k) return;
   double acc = 0.0;
-  for (int b = 0; b < nblk; ++b) acc += partial[(int64_t)b * k + j];
+  int b = 0;
+  for (; b + 8 <= nblk; b += 8) {                // loads eight at a time, added in order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(b + u) * k + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; b < nblk; ++b) acc += partial[(int64_t)b * k + j];
   out[j] = S[j] > 0.0 ? sqrt(acc) / S[j] : INFINITY;
 }
 
@@ -1017,9 +1053,9 @@ template <class AT>
 void reduce_splits(int p, int q, int64_t splits, const AT* part, double* C, int64_t ldc,
                    int sym, hipStream_t st, const int* gate) {
   const int64_t tot = (int64_t)p * q;
-  int lanes = 1;   // threads per output: about 16 splits each, at most 64
-  while (lanes < 64 && lanes * 16 < splits) lanes <<= 1;
-  const int64_t per_block = 256 / lanes;
+  int lanes = 1;   // threads per output: about 32 splits each, at most 16
+  while (lanes < 16 && lanes * 32 < splits) lanes <<= 1;
+  const int64_t per_block = 256 / lanes;       // outputs per workgroup
   hipLaunchKernelGGL((gram_reduce_kernel<AT>), dim3((unsigned)ceil_div(tot, per_block)),
                      dim3(256), 0, st, p, q, (int)splits, lanes, part, C, ldc, sym, MT,
                      gate);

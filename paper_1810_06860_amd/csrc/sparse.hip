@@ -562,8 +562,19 @@ template <class AT, class OT>
 __device__ __forceinline__ void spmm_fixup_one(const int4 fx, int col,
                                                const AT* __restrict__ part,
                                                OT* __restrict__ out, int64_t ldo, int b) {
+  // the partial rows come from other workgroups (other XCDs): their loads go
+  // out eight at a time and are added in slot order
+  const AT* __restrict__ pp = part + (int64_t)fx.y * b + col;
   AT acc = 0;
-  for (int q = 0; q < fx.z; ++q) acc += part[(int64_t)(fx.y + q) * b + col];
+  int q = 0;
+  for (; q + 8 <= fx.z; q += 8) {
+    AT v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = pp[(int64_t)(q + u) * b];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; q < fx.z; ++q) acc += pp[(int64_t)q * b];
   out[(int64_t)fx.x * ldo + col] = (OT)acc;
 }
 
@@ -797,6 +808,24 @@ __global__ __launch_bounds__(64 * kSpmmWaves) void sddmm_update_kernel(
   if (sg.x >= 0) {
     const int g = lane / BW, c = lane % BW;
     const FT* urow = U + (int64_t)sg.x * ldu;
+    // this lane's u_i sig entries of the row for pass c0: loads from clamped
+    // columns (issued together), zeroed past r by a select
+    auto row_weights = [&](int c0, AT* uu, int* colc) {
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) {
+        const int col = c0 + c + t * BW;
+        colc[t] = col < r ? col : r - 1;
+        const AT w = (AT)urow[colc[t]] * (AT)sig[colc[t]];
+        uu[t] = col < r ? w : (AT)0;
+      }
+    };
+    // the first pass's weights serve every 64-entry chunk of the segment when
+    // registers allow (measured: held across the segment they slow the forms
+    // with more than 32 gathers per half-chunk or more than 5 columns per lane)
+    constexpr bool kHold = CPL <= 5 && (32 / G) * CPL <= 32;
+    AT uu0[CPL];
+    int colc0[CPL];
+    if (kHold && r > 0) row_weights(0, uu0, colc0);
     for (int base = sg.y; base < sg.z; base += 64) {
       const int e = base + lane;
       const bool ok = e < sg.z;
@@ -806,11 +835,14 @@ __global__ __launch_bounds__(64 * kSpmmWaves) void sddmm_update_kernel(
       for (int c0 = 0; c0 < r; c0 += CB) {
         AT uu[CPL];
         int colc[CPL];
+        if (kHold && c0 == 0) {
 #pragma unroll
-        for (int t = 0; t < CPL; ++t) {
-          const int col = c0 + c + t * BW;
-          colc[t] = col < r ? col : r - 1;
-          uu[t] = col < r ? (AT)urow[col] * (AT)sig[col] : (AT)0;
+          for (int t = 0; t < CPL; ++t) {
+            uu[t] = uu0[t];
+            colc[t] = colc0[t];
+          }
+        } else {
+          row_weights(c0, uu, colc);
         }
         // two halves of 32 nonzeros: the gathers of a half are independent
         // and issued back to back; a short tail skips the second half
@@ -892,7 +924,15 @@ __global__ void reduce_kernel(int64_t n, const double* __restrict__ partial,
                               double* __restrict__ out) {
   __shared__ double sh[1024];
   double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) acc += partial[i];
+  int64_t i = threadIdx.x;
+  for (; i + 7 * 1024 < n; i += 8 * 1024) {      // loads eight at a time, added in order
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = partial[i + u * 1024];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; i < n; i += 1024) acc += partial[i];
   const double s = block_sum<1024>(acc, sh);
   if (threadIdx.x == 0) out[0] = s;
 }
