@@ -654,20 +654,21 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(
   const int o = lane % outs, u = lane / outs;
   const int64_t t = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * outs + o;
   const int64_t tot = (int64_t)p * q;
-  const bool live = t < tot;
-  int si = 0, sj = 0, i = 0, j = 0;
-  if (live) {
+  int i = 0, j = 0;
+  if (t < tot) {
     i = (int)(t / q);
     j = (int)(t % q);
-    si = i;
-    sj = j;
-    if (sym && (i / tile) > (j / tile)) { si = j; sj = i; }   // mirrored tile
   }
+  // a symmetric product's partials hold the tiles on and above the diagonal:
+  // those entries are read (side by side) and the ones below are written as
+  // their mirror images
+  const bool live = t < tot && !(sym && (i / tile) > (j / tile));
+  const bool mirror = sym && (i / tile) < (j / tile);
   double acc = 0.0;
   if (live) {
     // the partials were written by other workgroups (other XCDs): their loads
     // go out sixteen at a time, and are added in split order
-    const AT* __restrict__ pp = part + (int64_t)si * q + sj;
+    const AT* __restrict__ pp = part + (int64_t)i * q + j;
     int s = u;
     for (; s + 15 * lanes < nsplit; s += 16 * lanes) {
       AT v[16];
@@ -679,7 +680,10 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(
     for (; s < nsplit; s += lanes) acc += (double)pp[(int64_t)s * tot];
   }
   for (int w = outs; w < 64; w <<= 1) acc += __shfl_xor(acc, w, 64);
-  if (live && u == 0) C[(int64_t)i * ldc + j] = acc;
+  if (live && u == 0) {
+    C[(int64_t)i * ldc + j] = acc;
+    if (mirror) C[(int64_t)j * ldc + i] = acc;
+  }
 }
 
 // C = beta*C0 + alpha * X W diag(colscale), X tall (N x p), W small (p x q),
