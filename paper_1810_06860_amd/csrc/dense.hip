@@ -1028,7 +1028,8 @@ int64_t fused_splits(int64_t N, int p, int q, int sym) {
 int64_t gram_mfma_splits(int64_t N, int p, int q, int sym) {
   const int64_t blocks = ceil_div(p, MB) * ceil_div(q, MB);
   const int64_t eff = sym ? (blocks + ceil_div(p, MB)) / 2 : blocks;
-  int64_t splits = std::max<int64_t>(1, 1024 / std::max<int64_t>(eff, 1));
+  // about two workgroups per CU (the occupancy of the wider tilings)
+  int64_t splits = std::max<int64_t>(1, 512 / std::max<int64_t>(eff, 1));
   splits = std::min<int64_t>(splits, std::max<int64_t>(1, ceil_div(N, 4 * MK)));
   splits = std::min<int64_t>(
       splits, std::max<int64_t>(1, N * (int64_t)(p + q) / (2 * (int64_t)p * q)));
