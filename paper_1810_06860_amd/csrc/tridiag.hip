@@ -479,7 +479,7 @@ __device__ void tri_steps(int L, int j0, double* __restrict__ Ab, int ldb,
     double acc = 0.0;
     if (rowi < n) {
       const int i = o + rowi;
-#pragma unroll 4
+#pragma unroll 8
       for (int c = part; c < n; c += S) {
         const double h = hrow[c];
         const double a = el(o + c, i);
@@ -508,17 +508,28 @@ __device__ void tri_steps(int L, int j0, double* __restrict__ Ab, int ldb,
       const double hbv = hrow[b];
       const double vb = b == 0 ? 1.0 : hbv * rv;
       const double wb = s.P[b] - K * vb;
-#pragma unroll 2
-      for (int a = tid / n; a < n; a += step) {
-        const double ha = hrow[a];
-        const double pa = s.P[a];
-        double* x = &el(o + a, o + b);
-        const double old = *x;
+      auto upd = [&](int a, double ha, double pa, double old) {
         const double va = a == 0 ? 1.0 : ha * rv;
         const double nv = old - (va * wb + (pa - K * va) * vb);
-        *x = nv;
+        el(o + a, o + b) = nv;
         if (a == 0 && b >= 2) sq += nv * nv;
+      };
+      int a = tid / n;
+      // eight of this thread's rows at a time: their operands are read before
+      // any of them is written (the rows are distinct, row j is not among them)
+      for (; a + 7 * step < n; a += 8 * step) {
+        double hv[8], pv[8], xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int r = a + u * step;
+          hv[u] = hrow[r];
+          pv[u] = s.P[r];
+          xv[u] = el(o + r, o + b);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) upd(a + u * step, hv[u], pv[u], xv[u]);
       }
+      for (; a < n; a += step) upd(a, hrow[a], s.P[a], el(o + a, o + b));
     }
     sq = wsum(sq);
     if (lane == 0) s.red2[wave] = sq;
