@@ -688,11 +688,12 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(
 
 // C = beta*C0 + alpha * X W diag(colscale), X tall (N x p), W small (p x q),
 // on the FP64 matrix cores.  A workgroup owns 64 rows and up to 128 columns
-// (NT tiles of 16), so X is read once for q <= 128; each wavefront
-// owns 16 rows x NT 16-column instruction tiles.  X (converted to FP64) and
-// W pass through LDS in chunks of 32 along p.
+// (NT tiles of 16), so X is read once for q <= 128; each wavefront owns 16
+// rows x NT 16-column instruction tiles.  W passes through LDS in chunks of
+// 16 along p; each lane reads its A operands (X converted to FP64) straight
+// from memory, the next chunk's while the matrix cores work on this one.
 constexpr int QR = 64;   // rows per workgroup
-constexpr int QK = 32;   // chunk along p
+constexpr int QK = 16;   // chunk along p
 
 template <class XT, class OT, int NT>
 __global__ __launch_bounds__(256) void panel_mfma_kernel(
@@ -704,48 +705,80 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(
   using M = Mfma16<double>;
   using V = M::V;
   constexpr int QC = 16 * NT;
+  constexpr int KS = QK / 4;                   // 4-deep steps per chunk
+  constexpr int WL = QK * QC / 256;            // W entries per thread and chunk
   if (gate && *gate == 0) return;
-  __shared__ double Xs[QR][QK + 1];
   __shared__ double Ws[QK][QC + 1];
   const int64_t r0 = (int64_t)blockIdx.x * QR;
   const int c0 = blockIdx.y * QC;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int g = lane / 16;
+  // this lane's row of X (clamped: rows past N feed outputs that are not
+  // stored), as a 32-bit offset from the workgroup's first row
+  const XT* __restrict__ Xb = X + r0 * ldx;
+  const int64_t xi = r0 + w * 16 + lane % 16;
+  const uint32_t xo = (uint32_t)(((xi < N ? xi : N - 1) - r0) * ldx) + (uint32_t)g;
+  const double* __restrict__ Wc = W + c0;
   V acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[t][v] = 0.0;
-  // loaders: X column xc of rows xr + 8 i; W row wr + 256 / QC * i
-  const int xc = threadIdx.x & (QK - 1), xr = threadIdx.x / QK;
-  for (int k0 = 0; k0 < p; k0 += QK) {
-    const bool kin = k0 + xc < p;
+  // the A operand of step s of a chunk: X[row][k0 + 4 s + g], zero past p
+  double xa[KS], xn[KS];
+  auto fetch = [&](int k0, double* dst) {
+    if (k0 + QK <= p) {                        // whole chunk: immediate offsets
 #pragma unroll
-    for (int i = 0; i < QR / 8; ++i) {
-      const int64_t row = r0 + xr + 8 * i;
-      const bool ok = kin && row < N;
-      const int64_t rc = row < N ? row : N - 1;
-      const double v = (double)X[rc * ldx + (kin ? k0 + xc : 0)];
-      Xs[xr + 8 * i][xc] = ok ? v : 0.0;
+      for (int s = 0; s < KS; ++s) dst[s] = (double)Xb[xo + (uint32_t)(k0 + 4 * s)];
+    } else {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int k = k0 + 4 * s + g;
+        const double v = (double)Xb[xo - (uint32_t)g + (uint32_t)(k < p ? k : p - 1)];
+        dst[s] = k < p ? v : 0.0;
+      }
     }
-    for (int t = threadIdx.x; t < QK * QC; t += 256) {
-      const int r = t / QC, c = t % QC;
-      Ws[r][c] = (k0 + r < p && c0 + c < q) ? W[(int64_t)(k0 + r) * ldw + c0 + c] : 0.0;
+  };
+  if (p > 0) {
+    fetch(0, xa);
+  } else {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) xa[s] = 0.0;
+  }
+  for (int k0 = 0; k0 < p; k0 += QK) {
+    double wv[WL];
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+      const int t = threadIdx.x + 256 * i, r = t / QC, c = t % QC;
+      const bool ok = k0 + r < p && c0 + c < q;
+      const double v = Wc[ok ? (uint32_t)((k0 + r) * ldw + c) : 0u];
+      wv[i] = ok ? v : 0.0;
+    }
+    const bool more = k0 + QK < p;
+    if (more) fetch(k0 + QK, xn);              // the next chunk's X in flight meanwhile
+#pragma unroll
+    for (int i = 0; i < WL; ++i) {
+      const int t = threadIdx.x + 256 * i;
+      Ws[t / QC][t % QC] = wv[i];
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < QK; kk += 4) {
-      const double a = Xs[w * 16 + lane % 16][kk + lane / 16];
+    for (int s = 0; s < KS; ++s)
 #pragma unroll
       for (int t = 0; t < NT; ++t)
-        acc[t] = M::op(a, Ws[kk + lane / 16][t * 16 + lane % 16], acc[t]);
-    }
+        acc[t] = M::op(xa[s], Ws[4 * s + g][t * 16 + lane % 16], acc[t]);
     __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) xa[s] = xn[s];
+    }
   }
   // epilogue: the column scales and C0 entries of all of this lane's outputs
   // are requested together (clamped addresses, uniform conditions), then the
   // results are formed and stored
   double cs[NT], cz[NT][4];
+  const OT* __restrict__ Cb = C0 + r0 * ldc0;
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int col = min(c0 + t * 16 + lane % 16, q - 1);
@@ -753,9 +786,10 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t row = min<int64_t>(r0 + w * 16 + M::row(lane, v), N - 1);
-      cz[t][v] = beta != 0.0 ? (double)C0[row * ldc0 + col] : 0.0;
+      cz[t][v] = beta != 0.0 ? (double)Cb[(uint32_t)((row - r0) * ldc0 + col)] : 0.0;
     }
   }
+  OT* __restrict__ Co = C + r0 * ldc;
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -766,7 +800,7 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(
         double x = alpha * acc[t][v];
         if (colscale) x *= cs[t];
         if (beta != 0.0) x += beta * cz[t][v];
-        C[row * ldc + col] = (OT)x;
+        Co[(uint32_t)((row - r0) * ldc + col)] = (OT)x;
       }
     }
 }

@@ -832,6 +832,24 @@ __global__ __launch_bounds__(64 * kSpmmWaves) void sddmm_update_kernel(
       const int my_col = ok ? ld_stream(col_idx + e) : 0;
       const int left = sg.z - base;
       AT xl = 0;                               // x of nonzero `e` (this lane)
+      // this lane's M, Y and CSC position, requested once the first half's
+      // gathers are out (loads complete in issue order: requested before
+      // them, these streaming loads would hold up the gathers' use).  The
+      // master Y is read and written non-temporally, so that it does not
+      // evict V's rows or the lines the CSC copy is being scattered into.
+      double mv = 0.0, yo = 0.0;
+      int ecp = 0;
+      bool req = false;
+      auto request = [&]() {
+        if (ok) {
+          mv = ld_stream(mvals + e);
+          if (apply) {
+            yo = ld_stream(y + e);
+            ecp = ld_stream(invperm + e);
+          }
+        }
+        req = true;
+      };
       for (int c0 = 0; c0 < r; c0 += CB) {
         AT uu[CPL];
         int colc[CPL];
@@ -844,18 +862,27 @@ __global__ __launch_bounds__(64 * kSpmmWaves) void sddmm_update_kernel(
         } else {
           row_weights(c0, uu, colc);
         }
-        // two halves of 32 nonzeros: the gathers of a half are independent
-        // and issued back to back; a short tail skips the second half
+        // two halves of 32 nonzeros: the gathers of a half are issued back to
+        // back into registers, then their dot products formed; a short tail
+        // skips the second half
 #pragma unroll
         for (int h = 0; h < 64; h += 32) {
           if (h >= left) break;                // uniform: the wave's segment
+          AT gv[32 / G][CPL];
 #pragma unroll
-          for (int jj = h; jj < h + 32; jj += G) {
-            const int jc = __shfl(my_col, jj + g);
+          for (int u = 0; u < 32 / G; ++u) {
+            const int jc = __shfl(my_col, h + u * G + g);
             const FT* vr = V + (int64_t)jc * ldv;
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) gv[u][t] = (AT)vr[colc[t]];
+          }
+          if (!req) request();
+#pragma unroll
+          for (int u = 0; u < 32 / G; ++u) {
+            const int jj = h + u * G;
             AT pdot = 0;
 #pragma unroll
-            for (int t = 0; t < CPL; ++t) pdot += uu[t] * (AT)vr[colc[t]];
+            for (int t = 0; t < CPL; ++t) pdot += uu[t] * gv[u][t];
 #pragma unroll
             for (int off = 1; off < BW; off <<= 1) pdot += __shfl_xor(pdot, off);
             // nonzero jj + g's sum sits in every lane of group g; lane
@@ -866,13 +893,14 @@ __global__ __launch_bounds__(64 * kSpmmWaves) void sddmm_update_kernel(
           }
         }
       }
+      if (!req) request();
       if (ok) {
-        const double d = ld_stream(mvals + e) - (double)xl;
+        const double d = mv - (double)xl;
         d2 += d * d;
         if (apply) {
-          const double yn = y[e] + delta * d;
-          y[e] = yn;
-          const int32_t ec = ld_stream(invperm + e);
+          const double yn = yo + delta * d;
+          __builtin_nontemporal_store(yn, y + e);
+          const int32_t ec = ecp;
           if (yv) yv[e] = (VT)yn;
           if (ycv) ycv[ec] = (VT)yn;
           if (yw) yw[e] = (WT)yn;
