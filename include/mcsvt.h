@@ -68,8 +68,10 @@ typedef struct {
                        (Alg. 2, Alg. 6) */
   double ritz_tol;  /* guarded recycling: a recycled SVD whose Ritz residual
                        max_j ||Y v_j - s_j u_j|| / s_j exceeds this is
-                       discarded and rSVD-BKI runs instead, and the next
-                       q_reuse steps make no recycled call.  0 -> the
+                       discarded and rSVD-BKI runs instead; the rest of that
+                       step and the next q_reuse * 2^(s-1) steps make no
+                       recycled call (s: rejections since the last accepted
+                       recycled SVD, exponent capped at 20).  0 -> the
                        paper's i_reuse / q_reuse gate alone.  Default 1e-4. */
   double c;         /* Y^0 = c delta P_Phi(M); <= 0 -> ceil(tau / (delta
                        ||P_Phi(M)||_2)) (Sec. II.C) */

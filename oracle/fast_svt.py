@@ -22,9 +22,11 @@ Readings of points the paper leaves open:
 * Guarded recycling (ritz_tol > 0) is an addition, not in the paper: a
   recycled result whose Ritz residual max_j ||Y v_j - s_j u_j|| / s_j
   exceeds ritz_tol is discarded and rSVD-BKI runs instead.  A rejection in
-  step i also suspends recycling in steps i+1 .. i+q_reuse (every call of
-  those steps is rSVD-BKI), so an operator whose recycled results keep
-  failing the guard does not pay for a discarded call in every step.  With
+  step i also suspends recycling for the rest of step i and for the next
+  q_reuse * 2^(s - 1) steps, s being the number of rejections since the
+  last accepted recycled result (exponent capped at 20): every call of
+  those steps is rSVD-BKI, so an operator whose recycled results keep
+  failing the guard pays for fewer and fewer discarded calls.  With
   ritz_tol = 0 nothing is rejected and the paper's rule applies unchanged.
 * Block width b = min(k + s, min(m, n)) and the power parameter is clamped so
   that (p + 1) b <= min(m, n) (eigSVD of B^T needs n >= (p + 1) b, Alg. 3).
@@ -99,6 +101,7 @@ class FastSVT:
         self.p = self.prm.p_init
         self.streak = 0
         self.rej_i = 0          # last step with a rejected recycled call
+        self.rej_run = 0        # rejections since the last accepted recycle
         self.err_hist = []
         self.saved = None
         self.kcap = min(self.m, self.n)
@@ -152,7 +155,8 @@ class FastSVT:
         self.p, self.streak = adapt_p(self.p, self.streak, self.err_hist, prm)
         attempt = fresh = recycled = rejected = 0
         while True:
-            suspended = 0 < self.rej_i < self.i <= self.rej_i + prm.q_reuse
+            pause = prm.q_reuse * 2 ** min(self.rej_run - 1, 20) if self.rej_run else 0
+            suspended = 0 < self.rej_i <= self.i <= self.rej_i + pause
             use_fresh = (prm.recycle == 0 or self.i < prm.i_reuse
                          or self.q == prm.q_reuse or self.saved is None
                          or k > self.saved.shape[1] or suspended)
@@ -164,6 +168,9 @@ class FastSVT:
                     use_fresh = True
                     rejected += 1
                     self.rej_i = self.i
+                    self.rej_run += 1
+                else:
+                    self.rej_run = 0
             if use_fresh:
                 U, S, V = self._fresh(Y, k, attempt)
                 attempt += 1

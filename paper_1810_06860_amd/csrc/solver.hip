@@ -6,7 +6,9 @@
 //     fresh rSVD-BKI (Alg. 5) when i < i_reuse, q == q_reuse or there is no
 //     usable basis; otherwise recycle the last call's Q (strategy 1) or U
 //     (strategy 2) (Sec. IV.B), optionally checked by the Ritz residual (a
-//     rejected recycle in step i also makes steps i+1 .. i+q_reuse fresh)
+//     rejected recycle in step i also makes the rest of step i and the next
+//     q_reuse * 2^(s-1) steps fresh, s = rejections since the last accepted
+//     recycle)
 //   until the k-th singular value <= tau (k += l otherwise)
 //   r = #{S_j > tau}; fused SDDMM: residual on Phi and Y += delta P_Phi(M - X)
 // The device work of these calls lives in solver_impl.hip.
@@ -150,7 +152,10 @@ double Solver::sddmm(int r) {
 // Alg. 6 allows it (Sec. IV.B), fresh otherwise.
 void Solver::launch_svd(bool force_fresh) {
   const int k = k_cur_;
-  const bool suspended = rej_i_ > 0 && i_ > rej_i_ && i_ <= rej_i_ + prm_.q_reuse;
+  // after a rejected recycle: the rest of that step and a pause that doubles
+  // with each further rejection before a recycled result is accepted
+  const int64_t pause = rej_run_ > 0 ? (int64_t)prm_.q_reuse << std::min(rej_run_ - 1, 20) : 0;
+  const bool suspended = rej_i_ > 0 && i_ >= rej_i_ && i_ <= rej_i_ + pause;
   const bool fresh = force_fresh || prm_.recycle == 0 || i_ < prm_.i_reuse ||
                      q_ == prm_.q_reuse || basis_cols_ == 0 || k > basis_cols_ ||
                      suspended;
@@ -249,9 +254,11 @@ bool Solver::step_poll(bool block) {
         if (prm_.ritz_tol > 0 && ratio > prm_.ritz_tol) {    // guard: redo fresh
           ++cur_.rejected;
           rej_i_ = i_;
+          ++rej_run_;
           launch_svd(true);
           return false;
         }
+        rej_run_ = 0;
       } else if (!fresh_finish(k_cur_)) {
         // a shifted Cholesky factorisation in the unguarded call: redo it
         // guarded (same attempt, same test matrix)

@@ -194,6 +194,7 @@ class Solver {
   // Alg. 6 state
   int i_ = 0, r_ = 0, q_ = 0, p_ = 3, streak_ = 0;
   int rej_i_ = 0;               // last step whose recycled call was rejected
+  int rej_run_ = 0;             // rejections since the last accepted recycled call
   int basis_cols_ = 0;
   int64_t basis_ld_ = 0;
   int k_last_ = 0;              // columns of U, V, S of the last SVD call

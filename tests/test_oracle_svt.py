@@ -152,9 +152,9 @@ def test_guarded_recycling_matches_plain(strategy):
 def test_rejected_recycles_leave_no_trace(strategy):
     # A guard that rejects every recycled result must reproduce the solve
     # without recycling exactly: a discarded call changes no state, and the
-    # rSVD-BKI calls draw the same test matrices.  After a rejection in step
-    # i, steps i+1 .. i+q_reuse make no recycled call; step i+q_reuse+1 tries
-    # again.
+    # rSVD-BKI calls draw the same test matrices.  The s-th rejection in a
+    # row (step i) suspends recycling for the rest of step i and steps
+    # i+1 .. i+q_reuse*2^(s-1); the step after that tries again.
     p = _small_planted(m=120, n=100, rank=4, ratio=0.35, seed=11)
     base = dict(tau=500.0, delta=1.2 / 0.35, eps=1e-3, i_max=80)
     plain = FastSVT(p.m, p.n, p.rows, p.cols, p.vals, base)
@@ -162,22 +162,58 @@ def test_rejected_recycles_leave_no_trace(strategy):
     rej = FastSVT(p.m, p.n, p.rows, p.cols, p.vals,
                   dict(base, recycle=strategy, i_reuse=20, q_reuse=q_reuse,
                        ritz_tol=1e-300))
-    last_rej = None
+    last_rej, run, tried = None, 0, []
     for _ in range(80):
         a, b = plain.step(), rej.step()
         assert (a.res, a.r, a.k, a.p, a.fresh) == (b.res, b.r, b.k, b.p, b.fresh)
         assert np.array_equal(a.S, b.S)
-        assert b.recycled == b.rejected
-        if last_rej is not None and b.i <= last_rej + q_reuse:
-            assert b.recycled == 0, b.i
-        if last_rej is not None and b.i == last_rej + q_reuse + 1:
-            assert b.recycled > 0, b.i
+        assert b.recycled == b.rejected <= 1
+        if last_rej is not None:
+            pause = q_reuse * 2 ** (run - 1)
+            if b.i <= last_rej + pause:
+                assert b.recycled == 0, b.i
+            if b.i == last_rej + pause + 1:
+                assert b.recycled > 0, b.i
         if b.rejected:
-            last_rej = b.i
+            last_rej, run = b.i, run + 1
+            tried.append(b.i)
         if a.converged:
             break
-    assert rej.rejected_total >= 3
+    # attempts at steps 20, 24, 31, 44 (pauses of 3, 6, 12 steps), ...
+    assert tried[:3] == [20, 24, 31], tried
+    assert rej.rejected_total == len(tried)
     assert np.array_equal(plain.U, rej.U) and np.array_equal(plain.V, rej.V)
+
+
+def test_accepted_recycle_resets_the_pause():
+    # a guard that accepts resets the run of rejections: the pause after the
+    # next rejection is q_reuse again
+    p = _small_planted(m=120, n=100, rank=4, ratio=0.35, seed=11)
+    base = dict(tau=500.0, delta=1.2 / 0.35, eps=1e-12, i_max=60, recycle=1,
+                i_reuse=10, q_reuse=2)
+    f = FastSVT(p.m, p.n, p.rows, p.cols, p.vals, dict(base, ritz_tol=1e-300))
+    while f.rej_run < 2:                 # attempts at steps 10 and 13
+        f.step()
+    assert f.i == 13
+    # from here the guard accepts every recycled result
+    f.prm.ritz_tol = 1e300
+    acc = None
+    for _ in range(30):
+        b = f.step()
+        if b.recycled > b.rejected:
+            acc = b.i
+            break
+    assert acc is not None and f.rej_run == 0
+    f.prm.ritz_tol = 1e-300
+    while True:
+        b = f.step()
+        if b.rejected:
+            break
+    i_rej = b.i
+    assert f.rej_run == 1
+    seen = [f.step() for _ in range(3)]
+    assert [x.recycled for x in seen[:2]] == [0, 0]      # pause of q_reuse = 2
+    assert seen[2].recycled > 0 and seen[2].i == i_rej + 3
 
 
 def test_rank_cap():
