@@ -348,9 +348,11 @@ template <> struct Mfma16<float> {
 
 // The row loop of gram_mfma_kernel: SAME (diagonal block of a symmetric
 // product: B is A), up to TW instruction tiles per wavefront (tile t of this
-// wavefront is (ti[t], tj[t]) in units of 16 inside the block, nt of them).
-// Only the last, partial stage uses row-guarded loads.
-template <class T, bool SAME, int TW>
+// wavefront is (ti[t], tj[t]) in units of 16 inside the block, nt of them;
+// GRID: the tiles form a TW / 4 x 4 grid, tile t at row t / 4 and column
+// t % 4 of it, and nt is the mask of the live ones).  Only the last, partial
+// stage uses row-guarded loads.
+template <class T, bool SAME, int TW, bool GRID>
 __device__ __forceinline__ void gram_mfma_rows(
     int64_t n0, int64_t n1, int p, int q, const T* __restrict__ A, int64_t lda,
     const T* __restrict__ B, int64_t ldb, T* __restrict__ out, int a0, int b0,
@@ -399,12 +401,25 @@ __device__ __forceinline__ void gram_mfma_rows(
     T(*Bt)[MB + 1] = SAME ? As : Bs;
     auto step4 = [&](int kk) {
       const int kr = kk + kq;
+      if constexpr (GRID) {
+        // a TW / 4 x 4 grid of tiles: TW / 4 + 4 operands serve TW
+        // products; nt is the mask of the live tiles
+        T x[TW / 4], y[4];
 #pragma unroll
-      for (int t = 0; t < TW; ++t) {
-        if (t < nt) {                          // uniform across the wavefront
-          const T x = As[kr][ti[t] * 16 + cc];
-          const T y = Bt[kr][tj[t] * 16 + cc];
-          acc[t] = M::op(x, y, acc[t]);
+        for (int i = 0; i < TW / 4; ++i) x[i] = As[kr][ti[4 * i] * 16 + cc];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) y[j] = Bt[kr][tj[j] * 16 + cc];
+#pragma unroll
+        for (int t = 0; t < TW; ++t)
+          if ((nt >> t) & 1) acc[t] = M::op(x[t / 4], y[t % 4], acc[t]);
+      } else {
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+          if (t < nt) {                        // uniform across the wavefront
+            const T x = As[kr][ti[t] * 16 + cc];
+            const T y = Bt[kr][tj[t] * 16 + cc];
+            acc[t] = M::op(x, y, acc[t]);
+          }
         }
       }
     };
@@ -423,7 +438,7 @@ __device__ __forceinline__ void gram_mfma_rows(
   }
 #pragma unroll
   for (int t = 0; t < TW; ++t) {
-    if (t >= nt) continue;
+    if (GRID ? !((nt >> t) & 1) : t >= nt) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = a0 + ti[t] * 16 + M::row(lane, v);
@@ -456,6 +471,29 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(
   const int total = same ? nti * (nti + 1) / 2 : nti * ntj;
   const int nt = min(TW, (total - w + 3) / 4);
   int ti[TW], tj[TW];
+  T* out = part + (int64_t)sp * p * q;
+  if constexpr (TW == 16) {
+    // sixteen tiles per wavefront: wavefront w takes the 4 x 4 tiles at
+    // (4 (w / 2), 4 (w % 2)) of the block's 8 x 8, so that each 4-row step
+    // reads four operands of each side for sixteen products; the tiles
+    // inside p x q (on or above the diagonal of a symmetric diagonal block)
+    // are live.  (Dealt out one by one, every product reads two operands.)
+    const int gi0 = 4 * (w / 2), gj0 = 4 * (w % 2);
+    int live = 0;
+#pragma unroll
+    for (int t = 0; t < TW; ++t) {
+      ti[t] = gi0 + t / 4;
+      tj[t] = gj0 + t % 4;
+      if (ti[t] < nti && tj[t] < ntj && (!same || ti[t] <= tj[t])) live |= 1 << t;
+    }
+    if (same)
+      gram_mfma_rows<T, true, TW, true>(n0, n1, p, q, A, lda, B, ldb, out, a0, b0, ti, tj,
+                                        live, As, Bs);
+    else
+      gram_mfma_rows<T, false, TW, true>(n0, n1, p, q, A, lda, B, ldb, out, a0, b0, ti, tj,
+                                         live, As, Bs);
+    return;
+  }
 #pragma unroll
   for (int t = 0; t < TW; ++t) {
     int g = w + 4 * t, i = 0;
@@ -471,13 +509,12 @@ __global__ __launch_bounds__(256) void gram_mfma_kernel(
       tj[t] = g % ntj;
     }
   }
-  T* out = part + (int64_t)sp * p * q;
   if (same)
-    gram_mfma_rows<T, true, TW>(n0, n1, p, q, A, lda, B, ldb, out, a0, b0, ti, tj, nt,
-                                As, Bs);
+    gram_mfma_rows<T, true, TW, false>(n0, n1, p, q, A, lda, B, ldb, out, a0, b0, ti, tj,
+                                       nt, As, Bs);
   else
-    gram_mfma_rows<T, false, TW>(n0, n1, p, q, A, lda, B, ldb, out, a0, b0, ti, tj,
-                                 nt, As, Bs);
+    gram_mfma_rows<T, false, TW, false>(n0, n1, p, q, A, lda, B, ldb, out, a0, b0, ti, tj,
+                                        nt, As, Bs);
 }
 
 // Tall Gram with a single output block (p, q <= 16 NT): every wavefront
