@@ -472,7 +472,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
-              "by this build (run with --gpus 1)", file=sys.stderr)
+              "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if a.workload == "sparse45k":
         return rsvd_main(a)

@@ -266,7 +266,7 @@ mc_status mc_svt_get_y(mc_svt_t h, double* y);
 mc_status mc_svt_get_sigma(mc_svt_t h, double* S, int32_t k_cap, int32_t* k);
 
 /* Event timing of the solve's kernel families on its own stream (a
- * measurement aid of this build with no counterpart in the paper; adds two
+ * measurement aid of this library with no counterpart in the paper; adds two
  * hipEventRecord calls per timed launch).  Families:
  *   0 SpMM Y X (CSR)       1 SpMM Y^T X (CSC)     2 fused SDDMM/update
  *   3 Gram / cross-Gram    4 panel GEMMs          5 Cholesky + inverse

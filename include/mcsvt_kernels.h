@@ -116,7 +116,7 @@ mc_status mc_k_sddmm(int64_t m, int64_t n, int64_t nnz, const int64_t* rows,
                      void* stream, double* x, double* y_new, double* sumsq);
 
 /* Banded work schedule of the SpMM for a CSR-like structure (host code only:
- * a scheduling aid of this build for the products of Alg. 5, with no
+ * a scheduling aid of this library for the products of Alg. 5, with no
  * counterpart in the paper; no device is touched).  This is the schedule the SpMM uses once the dense
  * panel it gathers from outgrows one XCD's L2: the gathered index range
  * [0, gathered) is cut into `bands` equal ranges (a positive multiple of 8);
